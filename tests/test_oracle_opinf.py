@@ -1,0 +1,185 @@
+"""Pins of the oracle's POD (Sec. 3.1) and OpInf learning (Sec. 3.2, 4.2, Alg. 3)."""
+import numpy as np
+import pytest
+
+from paper_2511_20687_amd.inputs import Bar, gaussian_pulse_u, random_normal, slab_layers
+from oracle.metrics import rel_l2
+from oracle.newmark import FomModel
+from oracle.opinf import (data_matrix, fit, lambda_grid, ridge, rollout_frozen, select_lambda,
+                          trajectory_error)
+from oracle.pod import energy_rank, pod, projection_error
+from oracle.rom import OpInfModel, Operators, kron2, kron2_jacobian
+from oracle.schwarz import Coupled, SchwarzOptions
+
+
+# ---------------------------------------------------------------- POD
+def _orth(seed, n, k):
+    q, _ = np.linalg.qr(random_normal(seed, (n, k)))
+    return q
+
+
+def test_pod_recovers_prescribed_svd_and_eckart_young():
+    N, T = 60, 25
+    L, R = _orth(1, N, T), _orth(2, T, T)
+    sig = 2.0 ** -np.arange(T)
+    U = L @ np.diag(sig) @ R.T
+    for r in (1, 5, 12):
+        Phi, s = pod(U, r=r)
+        assert np.allclose(s, sig, rtol=1e-12, atol=1e-15)
+        assert np.abs(Phi.T @ Phi - np.eye(r)).max() <= 1e-13
+        # same subspace as the prescribed left singular vectors
+        P1, P2 = Phi @ Phi.T, L[:, :r] @ L[:, :r].T
+        assert np.abs(P1 - P2).max() <= 1e-12
+        err = np.linalg.norm(U - Phi @ (Phi.T @ U)) ** 2
+        assert np.isclose(err, np.sum(sig[r:] ** 2), rtol=1e-10)
+        # any other orthonormal r-basis does worse
+        V = _orth(3 + r, N, r)
+        assert np.linalg.norm(U - V @ (V.T @ U)) ** 2 > err
+        assert np.isclose(projection_error(U, Phi), np.sqrt(np.sum(sig[r:] ** 2) / np.sum(sig ** 2)))
+
+
+def test_energy_rank_rule():
+    s = np.sqrt(np.array([50.0, 30.0, 15.0, 4.0, 1.0]))   # energies sum to 100
+    assert energy_rank(s, 0.5) == 1
+    assert energy_rank(s, 0.80) == 2
+    assert energy_rank(s, 0.95) == 3
+    assert energy_rank(s, 0.9500001) == 4
+    assert energy_rank(s, 1.0) == 5
+
+
+def test_pod_sign_convention():
+    U = np.array([[0.0, 0.0], [-3.0, 0.0], [0.0, 2.0]])
+    Phi, _ = pod(U, r=2)
+    assert np.all(Phi[np.argmax(np.abs(Phi), axis=0), [0, 1]] > 0)
+
+
+# ---------------------------------------------------------------- kron2
+def test_kron2_layout_and_jacobian():
+    q = np.array([2.0, 3.0, 5.0])
+    assert np.allclose(kron2(q), [4, 6, 10, 9, 15, 25])
+    J = kron2_jacobian(q)
+    h = 1e-20
+    for k in range(3):
+        e = np.zeros(3, dtype=complex); e[k] = 1j * h
+        assert np.allclose(J[:, k], kron2(q + e).imag / h)
+
+
+# ---------------------------------------------------------------- ridge
+def test_ridge_closed_form_orthonormal_design():
+    D = _orth(7, 40, 6)
+    R = random_normal(8, (40, 3))
+    for lam in (0.0, 1e-3, 0.7):
+        X = ridge(D, R, lam)
+        assert np.allclose(X, D.T @ R / (1.0 + lam), rtol=1e-12, atol=1e-14)
+
+
+def test_ridge_exact_data_and_shrinkage():
+    D = random_normal(9, (50, 8))
+    X0 = random_normal(10, (8, 2))
+    assert np.allclose(ridge(D, D @ X0, 0.0), X0, rtol=1e-11)
+    n1 = np.linalg.norm(ridge(D, D @ X0, 1e-2))
+    n2 = np.linalg.norm(ridge(D, D @ X0, 1e1))
+    assert n2 < n1 < np.linalg.norm(X0) * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------- OpInf on FOM data
+@pytest.fixture(scope="module")
+def training():
+    """FOM-FOM training run on a small bar; snapshots of subdomain 2."""
+    bar = Bar(1, 1, 12, Lx=1.0 / 12, Ly=1.0 / 12, Lz=1.0)
+    dt = bar.explicit_dt()
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.35, 0.08)
+    v0 = np.zeros_like(u0)
+    models = [FomModel(bar, lo, hi, dt) for lo, hi in slab_layers(bar.nz, 2)]
+    cp = Coupled(models)
+    T = 400
+    out = cp.run(u0, v0, T - 1, SchwarzOptions(), record=("u", "v", "a", "s"))
+    return dict(bar=bar, dt=dt, u0=u0, v0=v0, models=models, cp=cp, out=out, T=T)
+
+
+def _reduce(tr, i=1, tol=1e-10):
+    out = tr["out"]
+    U, A, S, V = out["u"][i].T, out["a"][i].T, out["s"][i].T, out["v"][i].T
+    _, sig = pod(U)
+    r = int(np.sum(sig > tol * sig[0]))
+    Phi, _ = pod(U, r=r)
+    _, sS = pod(S)
+    rS = int(np.sum(sS > tol * sS[0]))
+    PhiS, _ = pod(S, r=rS)
+    return U, A, S, V, Phi, PhiS
+
+
+def test_intrusive_operator_recovery(training):
+    """Linear FOM data, full-rank bases, lambda = 0: OpInf returns the projected FE operators
+    A = -Phi^T M^-1 K_ff Phi, B = -Phi^T M^-1 K_fs Phi_S (finite-dt form of the recovery claim
+    in Sec. 3.2)."""
+    m = training["models"][1]
+    U, A, S, V, Phi, PhiS = _reduce(training)
+    ops = fit([Phi.T @ U], [Phi.T @ A], [PhiS.T @ S], 0.0)
+    Minv = 1.0 / m.m_f
+    K_fs = m.K[m.free_dofs][:, m.sch_dofs].toarray()
+    A_int = -Phi.T @ (Minv[:, None] * (m.K_ff @ Phi))
+    B_int = -Phi.T @ (Minv[:, None] * K_fs) @ PhiS
+    assert np.abs(ops.A - A_int).max() <= 1e-8 * np.abs(A_int).max()
+    assert np.abs(ops.B - B_int).max() <= 1e-8 * np.abs(B_int).max()
+
+
+def test_quadratic_fit_of_linear_data_has_no_quadratic_part(training):
+    U, A, S, V, Phi, PhiS = _reduce(training)
+    Phi = Phi[:, :6]                     # keep p = r + r(r+1)/2 + r_S below T
+    Q, Qdd, Sh = Phi.T @ U, Phi.T @ A, PhiS.T @ S
+    # rows of Qdd that the linear model explains exactly: use a synthetic linear target
+    Ax = random_normal(11, (6, 6)); Bx = random_normal(12, (6, Sh.shape[0]))
+    target = Ax @ Q + Bx @ Sh
+    ops = fit([Q], [target], [Sh], 0.0, form="quadratic")
+    assert np.abs(ops.H).max() <= 1e-6 * np.abs(ops.A).max()
+    assert np.allclose(ops.A, Ax, rtol=1e-6, atol=1e-8 * np.abs(Ax).max())
+
+
+def test_full_rank_rom_reproduces_training_trajectory(training):
+    U, A, S, V, Phi, PhiS = _reduce(training)
+    Q, Qdd, Sh = Phi.T @ U, Phi.T @ A, PhiS.T @ S
+    ops = fit([Q], [Qdd], [Sh], 0.0)
+    Qrom = rollout_frozen(ops, Q[:, 0], Phi.T @ V[:, 0], Qdd[:, 0], Sh, Q.shape[1], training["dt"])
+    assert trajectory_error(Qrom, Q) <= 1e-9
+
+
+def test_coupled_fom_opinf_full_rank_reproduces_fom_fom(training):
+    tr = training
+    U, A, S, V, Phi, PhiS = _reduce(tr)
+    ops = fit([Phi.T @ U], [Phi.T @ A], [PhiS.T @ S], 0.0)
+    fom1 = tr["models"][0]
+    rom = OpInfModel(tr["models"][1], Phi, PhiS, ops.A, None, ops.B, None, dt=tr["dt"])
+    hyb = Coupled([fom1, rom]).run(tr["u0"], tr["v0"], tr["T"] - 1, SchwarzOptions())
+    assert rel_l2(hyb["u"][0], tr["out"]["u"][0]) <= 1e-9
+    assert rel_l2(hyb["u"][1], tr["out"]["u"][1]) <= 1e-9
+
+
+def test_lambda_selection_prefers_least_regularisation_on_exact_data(training):
+    U, A, S, V, Phi, PhiS = _reduce(training)
+    Q, Qdd, Sh = Phi.T @ U, Phi.T @ A, PhiS.T @ S
+    traj = dict(Q=Q, Qd0=Phi.T @ V[:, 0], Qdd=Qdd, Shat=Sh)
+    lams = lambda_grid(11)
+    lam, E, ops = select_lambda([traj], lams, dt=training["dt"])
+    assert lam == lams[0]
+    assert E[0] == E.min() and E[-1] > 10 * E[0]
+    # ties resolve to the smallest lambda; non-finite candidates are penalised
+    lam2, E2, _ = select_lambda([traj, traj], lams[:2], dt=training["dt"])
+    assert lam2 == lams[0] or E2[0] <= E2[1]
+    bad = Operators(np.array([[1e8]]))
+    Qb = rollout_frozen(bad, np.ones(1), np.zeros(1), np.zeros(1), None, 4000, 1.0)
+    assert trajectory_error(Qb, np.ones((1, 4000))) == np.inf
+
+
+def test_lambda_grid_matches_paper():
+    g = lambda_grid(11)
+    assert g[0] == 1e-10 and np.isclose(g[-1], 1.0) and np.allclose(np.diff(np.log10(g)), 1.0)
+
+
+def test_data_matrix_columns():
+    Q = np.arange(6.0).reshape(2, 3)
+    Sh = np.ones((1, 3))
+    D = data_matrix(Q, Sh, "quadratic", True)
+    assert D.shape == (3, 2 + 3 + 1 + 1)
+    assert np.allclose(D[:, 2:5], kron2(Q).T)
+    assert np.allclose(D[:, -1], 1.0)
