@@ -1,0 +1,212 @@
+/*
+ * osam.h -- C ABI of libosam: the overlapping Schwarz alternating method (O-SAM)
+ * coupling linear-elastodynamics subdomains that are hex8 finite-element
+ * models (FOM) or Operator-Inference reduced models (OpInf), with OpInf
+ * learning, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Hybrid coupling with operator inference and the overlapping Schwarz
+ * alternating method" (arXiv 2511.20687).  Sec. 2 (FE model, Eq.
+ * matrix_vector_form_with_dbcs), Sec. 3 (POD, OpInf least squares), Sec. 4.1
+ * (multiplicative Schwarz, Alg. 1, Eq. schwarz_discrete, Eq. conv_criterion),
+ * Sec. 4.2 (OpInf-FOM / OpInf-OpInf coupling, Eq. opinf_schwarz_inference,
+ * Alg. 2, Alg. 3).
+ *
+ * Conventions shared by every call
+ *   - Every call returns an osam_status (0 = OK, negative = error) and never
+ *     throws or aborts.  On error, osam_last_error() describes the failure; the
+ *     context is left as it was before the call unless stated otherwise.
+ *   - The context owns every device buffer it allocates and frees them in
+ *     osam_ctx_destroy().  Host pointers passed in are read (or written) only
+ *     during the call.  Device pointers passed in (e.g. torch tensors'
+ *     data_ptr) are borrowed for the call only, except record buffers, which
+ *     are borrowed until replaced or the context is destroyed.
+ *   - A context is not thread-safe.  Separate contexts are independent.
+ *   - Geometry: every subdomain is a set of node layers [z_lo, z_hi] of a
+ *     structured nx x ny x nz hex8 grid of the box [0,Lx]x[0,Ly]x[0,Lz].
+ *     Node (i, j, k) of a subdomain has local id i + (nx+1)(j + (ny+1)(k - z_lo)).
+ *     A z-face at the bar's end (z_lo == 0 or z_hi == nz) is exterior: clamped
+ *     when clamp_ends != 0, traction-free otherwise.  Any other z-face is a
+ *     Schwarz (overlap) boundary whose values come from the neighbouring
+ *     subdomain that contains it.  Lateral faces are traction-free.
+ *   - Vector fields on the host are float64 structure-of-arrays [3][n_nodes].
+ *   - Free-DOF vectors (snapshots, records) use the library layout
+ *     [3][free nodes], free nodes = layers z_lo+1 .. z_hi-1 in node order.
+ *     Schwarz-DOF vectors use [3][schwarz nodes], low face first.
+ *   - "batch" independent instances share all subdomain descriptions; every
+ *     per-instance device array is instance-major.
+ */
+#ifndef OSAM_H
+#define OSAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OSAM_OK = 0,
+  OSAM_E_INVALID = -1,   /* bad argument, size or unsupported option */
+  OSAM_E_OOM = -2,       /* device allocation failed */
+  OSAM_E_HIP = -3,       /* HIP runtime error */
+  OSAM_E_NONFINITE = -4, /* a state or norm became NaN/Inf (run stops) */
+  OSAM_E_SINGULAR = -5,  /* least-squares system not positive definite */
+  OSAM_E_OUTSIDE = -6,   /* a Schwarz node lies in no neighbouring subdomain */
+  OSAM_E_ORDER = -7      /* call-order violation (e.g. run before set_initial) */
+} osam_status;
+
+typedef enum { OSAM_FP64 = 0, OSAM_FP32 = 1 } osam_precision;
+typedef enum { OSAM_GUESS_HOLD = 0, OSAM_GUESS_PREDICTOR = 1 } osam_guess;
+typedef enum { OSAM_LINEAR = 0, OSAM_QUADRATIC = 1 } osam_form;
+
+typedef struct osam_ctx osam_ctx;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t osam_version(void);
+
+/* Create a context on HIP device `device` computing in `precision` with `batch`
+ * independent instances.  `hip_stream` (hipStream_t) is used for all work; NULL
+ * selects the library's own stream.  *out receives the context. */
+int32_t osam_ctx_create(osam_ctx **out, int32_t device, int32_t precision, int32_t batch,
+                        void *hip_stream);
+/* Free every library-owned device buffer and the context itself.  NULL is ignored. */
+void osam_ctx_destroy(osam_ctx *ctx);
+/* Text of the last error on this context ("" if none); valid until the next call. */
+const char *osam_last_error(const osam_ctx *ctx);
+
+/* One subdomain = one mesh + material + BCs + time integrator: the input of
+ * Alg. 1 (overlapping subdomains, each with a mesh, initial condition, time
+ * integrator and uniform time step).  Linear elasticity (App. A.1), 2x2x2-Gauss
+ * hex8 stiffness, row-sum lumped mass, Newmark-beta (Sec. 4.1); beta must be 0
+ * (explicit central difference, gamma = 1/2) in this version. */
+typedef struct {
+  int32_t nx, ny, nz;          /* global grid, elements per axis (>= 1)     */
+  double Lx, Ly, Lz;           /* box size                                  */
+  int32_t z_lo, z_hi;          /* node-layer range, 0 <= z_lo, z_lo+2 <= z_hi <= nz */
+  double E, nu, rho;           /* Young's modulus, Poisson ratio, density   */
+  int32_t clamp_ends;          /* exterior z-faces clamped (chi = 0)        */
+  double dt;                   /* time step = controller step              */
+  double beta, gamma;          /* Newmark parameters: 0, 0.5               */
+} osam_subdomain_desc;
+
+/* Append a FOM subdomain; *sd_id receives its index (0, 1, ...).  The
+ * multiplicative Schwarz order is the index order.  Must precede osam_couple. */
+int32_t create_subdomain(osam_ctx *ctx, const osam_subdomain_desc *desc, int32_t *sd_id);
+
+/* Build the pointwise projections Pi (Sec. 4.1: trilinear interpolation of the
+ * neighbour's FE field at each Schwarz node) for every subdomain.  Called
+ * implicitly by the first call that needs it; OSAM_E_OUTSIDE if a Schwarz node
+ * lies strictly inside no other subdomain. */
+int32_t osam_couple(osam_ctx *ctx);
+
+/* Initial condition of instance `inst` from the global fields u0, v0
+ * (host float64 [3][(nx+1)(ny+1)(nz+1)] of subdomain 0's grid): every subdomain
+ * restricts them, zeroes its clamped DOFs, keeps the IC on its Schwarz DOFs and
+ * forms a0 = M^-1(-K u0) on free DOFs (FOM) or q0 = Phi^T u0, q'0 = Phi^T v0,
+ * q''0 = f(q0, g^0) (OpInf, Sec. 4.2).  Resets the instance's step counter. */
+int32_t osam_set_initial(osam_ctx *ctx, int32_t inst, const double *u0, const double *v0);
+
+/* Current accepted state of subdomain sd, instance inst, as host float64
+ * [3][n_nodes] arrays (any may be NULL).  OpInf subdomains return the lifted
+ * field Phi q on free DOFs, the imposed Schwarz data and zero Dirichlet DOFs. */
+int32_t osam_get_state(osam_ctx *ctx, int32_t sd, int32_t inst, double *u, double *v, double *a);
+/* Reduced state (q, q', q'') of an OpInf subdomain, host float64 [r] each. */
+int32_t osam_get_reduced(osam_ctx *ctx, int32_t sd, int32_t inst, double *q, double *qd,
+                         double *qdd);
+
+/* Sizes of subdomain sd: nodes, free DOFs, Schwarz DOFs, reduced dimension
+ * (0 for a FOM), boundary reduced dimension.  Any pointer may be NULL. */
+int32_t osam_sizes(osam_ctx *ctx, int32_t sd, int64_t *n_nodes, int64_t *n_free, int64_t *n_sch,
+                   int32_t *r, int32_t *r_s);
+
+/* Recording (training snapshots, outputs).  Every `every` accepted steps (and at
+ * step 0, written by osam_set_initial... or the first run step), column
+ * c = step/every of each non-NULL buffer is written; steps beyond n_cols
+ * columns are not recorded.  Device buffers in the context precision,
+ * layout [batch][n_cols][len]: u and a have len = free DOFs (FOM; for OpInf u
+ * holds q, len = r), s has len = Schwarz DOFs.  every = 0 disables. */
+typedef struct {
+  int64_t every, n_cols;
+  void *u, *a, *s;
+} osam_record;
+int32_t osam_set_record(osam_ctx *ctx, int32_t sd, const osam_record *rec);
+
+/* Operator Inference for subdomain sd (Sec. 3, 4.2; Alg. 2 steps 3-4, Alg. 3).
+ * Snapshots of n_traj trajectories, T columns each, device arrays in the
+ * context precision, layout [n_traj][T][len]: U free-DOF displacements, Udd the
+ * FOM's Newmark accelerations at the same times (the D_t^2 data), S Schwarz-DOF
+ * values, V0 [n_traj][n_free] initial velocities (for the Alg. 3 rollout start).
+ * POD bases by the method of snapshots (FP64 Gram, symmetric eigensolver) with
+ * r (or the energy criterion Eq. pod_energy when r <= 0) and r_s (energy_bnd
+ * when r_s <= 0); least squares in FP64 (normal or dual form) for each lambda
+ * in `lambdas`; Alg. 3 picks lambda* (frozen-boundary rollout error, smallest
+ * lambda on ties, non-finite = +inf) and the operators are refit with it.  On
+ * success sd becomes an OpInf subdomain.  Outputs (host, may be NULL): sigma
+ * (singular values of U, min(n_free, n_traj*T) entries), E_lambda [n_lambda],
+ * lambda_star, r_out, rs_out. */
+typedef struct {
+  int32_t form, with_c;
+  int32_t r, r_s;
+  double energy, energy_bnd;
+  int32_t n_lambda;
+  const double *lambdas;
+  int32_t n_traj;
+  int64_t T;
+  const void *U, *Udd, *S, *V0;
+  double *sigma_out, *E_lambda_out, *lambda_star_out;
+  int32_t *r_out, *rs_out;
+} osam_opinf_desc;
+int32_t learn_opinf(osam_ctx *ctx, int32_t sd, const osam_opinf_desc *desc);
+
+/* Install given OpInf data on subdomain sd (host float64, column-major):
+ * Phi [n_free x r], PhiS [n_sch x r_s], A [r x r], H [r x r(r+1)/2] or NULL,
+ * B [r x r_s] or NULL, c [r] or NULL.  Columns of Phi and PhiS should be
+ * orthonormal (the convergence norm is taken in reduced coordinates). */
+int32_t osam_set_opinf(osam_ctx *ctx, int32_t sd, int32_t r, int32_t r_s, const double *Phi,
+                       const double *PhiS, const double *A, const double *H, const double *B,
+                       const double *c);
+/* Read back the OpInf data of subdomain sd into host float64 buffers of the
+ * sizes above (any may be NULL). */
+int32_t osam_get_opinf(osam_ctx *ctx, int32_t sd, double *Phi, double *PhiS, double *A, double *H,
+                       double *B, double *c);
+
+/* Schwarz options (Eq. conv_criterion): converged when n >= min_iter and
+ * sum_i ||du_i + dt_i dv_i||^2 < tol_abs^2 or that sum < tol_rel^2 sum_i
+ * ||u_i + dt_i v_i||^2 (free DOFs; reduced coordinates for OpInf).  At most
+ * max_iter iterations per controller step; reaching the cap is not an error.
+ * guess: initial data of a neighbour not yet advanced in the step. */
+typedef struct {
+  double tol_abs, tol_rel;
+  int32_t min_iter, max_iter;
+  int32_t guess;
+} osam_schwarz_opts;
+
+/* Per-instance progress and statistics. */
+typedef struct {
+  int64_t steps;          /* accepted controller steps since osam_set_initial */
+  int32_t last_iters;     /* Schwarz iterations of the last step              */
+  int32_t last_converged; /* 1 if the last step met the criterion             */
+  double abs2, den2;      /* numerator / denominator of the last test         */
+  int64_t total_iters;    /* sum of iterations over all steps                 */
+  int32_t max_iters;      /* largest iteration count of any step              */
+  int64_t unconverged;    /* steps that hit max_iter                          */
+  int32_t status;         /* OSAM_OK or OSAM_E_NONFINITE                      */
+} osam_instance_info;
+
+/* One controller step of Alg. 1 for every instance (multiplicative sweeps over
+ * the subdomains in index order until Eq. conv_criterion).  info: [batch] or NULL. */
+int32_t schwarz_step(osam_ctx *ctx, const osam_schwarz_opts *opts, osam_instance_info *info);
+
+/* n_steps controller steps for every instance; the host does not wait on
+ * individual steps (each instance iterates at its own pace on the device).
+ * Returns OSAM_E_NONFINITE if any instance went non-finite (that instance stops
+ * at its last finite step; the others complete).  info: [batch] or NULL. */
+int32_t run(osam_ctx *ctx, int64_t n_steps, const osam_schwarz_opts *opts, osam_instance_info *info);
+
+/* Wait for all queued work of the context (host synchronisation). */
+int32_t osam_sync(osam_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OSAM_H */

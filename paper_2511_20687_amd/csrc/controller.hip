@@ -1,0 +1,779 @@
+// Host-side controller of libosam: coupling set-up (pointwise projections,
+// Sec. 4.1), wiring of FOM/OpInf transfers (Sec. 4.2), initial states, and the
+// device-paced Schwarz time loop (Alg. 1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "runtime.hpp"
+
+namespace osam {
+
+template <typename T> hipError_t launch_fe(const FeArgs<T> &, int, int, int, hipStream_t);
+template <typename T> hipError_t launch_rom(const RomArgs<T> &, int, hipStream_t);
+template <typename T>
+hipError_t launch_project(const T *, long long, long long, const T *, long long, long long, double *, int,
+                          int, hipStream_t);
+template <typename T>
+hipError_t launch_lift(const T *, long long, long long, int, const T *, T *, long long, long long, hipStream_t);
+template <typename T>
+hipError_t launch_piphi(const T *, long long, long long, int, const int *, const T *, int, int, int, T *,
+                        hipStream_t);
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(OSAM_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double *Ctx::scratch(size_t n, int32_t *st) {
+  if (n > scratch_n) {
+    dfree(d_scratch);
+    d_scratch = nullptr;
+    void *p = nullptr;
+    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
+      *st = OSAM_E_OOM;
+      scratch_n = 0;
+      return nullptr;
+    }
+    allocs.push_back(p);
+    d_scratch = static_cast<double *>(p);
+    scratch_n = n;
+  }
+  return d_scratch;
+}
+
+// Launch shape of the FE kernel: columns x z-chunks x instances.  block/kc = 0
+// selects the default heuristic (enough workgroups to fill 256 CUs).
+void Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
+  const int nl = s.nzs - 1;
+  int bs = block > 0 ? block : (s.n_int < 2048 ? 64 : 256);
+  auto per_chunk = [&](int b) { return (s.n_int + b - 1) / b + (s.n_bnd + b - 1) / b; };
+  if (kc <= 0) {
+    const int target = 2048;
+    const int pc = per_chunk(bs) * batch;
+    int chunks = std::max(1, std::min(nl, (target + pc - 1) / pc));
+    kc = std::max(std::min(4, nl), (nl + chunks - 1) / chunks);
+  }
+  kc = std::max(1, std::min(kc, nl));
+  s.fe_block = bs;
+  s.fe_kc = kc;
+  s.fe_chunks = (nl + kc - 1) / kc;
+  s.fe_int_blocks = (s.n_int + bs - 1) / bs;
+  s.fe_nblocks = per_chunk(bs) * s.fe_chunks;
+  s.max_nblocks = std::max(s.max_nblocks, per_chunk(64) * nl);
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise projection Pi (Sec. 4.1): trilinear interpolation of the source's
+// FE field at every node of a Schwarz face.  Reference coordinates on a box
+// grid follow from the cell index; values within 1e-9 of a grid line snap to it
+// so that conforming faces become exact injections.
+static void locate(double f, int n, int &i, double &t) {
+  i = (int)std::floor(f);
+  i = std::max(0, std::min(n - 1, i));
+  t = f - i;
+  if (std::fabs(t) < 1e-9) t = 0.0;
+  if (std::fabs(t - 1.0) < 1e-9) t = 1.0;
+}
+
+int32_t Ctx::couple() {
+  if (coupled) return OSAM_OK;
+  const int S = (int)sds.size();
+  for (int i = 0; i < S; ++i) {
+    Subdomain &d = *sds[i];
+    for (int f = 0; f < 2; ++f) {
+      if (d.face_type[f] == kFaceClamped) continue;
+      const int layer = f == 0 ? d.desc.z_lo : d.desc.z_hi;
+      int src = -1;
+      for (int j = 0; j < S && src < 0; ++j)
+        if (j != i && sds[j]->desc.z_lo < layer && layer < sds[j]->desc.z_hi) src = j;
+      if (src < 0) return fail(OSAM_E_OUTSIDE, "Schwarz face of subdomain " + std::to_string(i) +
+                                                   " lies in no other subdomain");
+      const Subdomain &sj = *sds[src];
+      const osam_subdomain_desc &g = sj.desc;
+      const double hx = g.Lx / g.nx, hy = g.Ly / g.ny, hz = g.Lz / g.nz;
+      const double z = layer * (d.desc.Lz / d.desc.nz);
+      FaceProj &P = d.proj[f];
+      P.src = src;
+      std::vector<std::vector<std::pair<int, double>>> rows(d.npl);
+      int width = 1;
+      for (int iy = 0; iy <= d.ny; ++iy)
+        for (int ix = 0; ix <= d.nx; ++ix) {
+          const double x = ix * (d.desc.Lx / d.nx), y = iy * (d.desc.Ly / d.ny);
+          int ci, cj, ck;
+          double tx, ty, tz;
+          locate(x / hx, g.nx, ci, tx);
+          locate(y / hy, g.ny, cj, ty);
+          locate(z / hz - g.z_lo, sj.nzs, ck, tz);
+          auto &row = rows[ix + (d.nx + 1) * iy];
+          for (int c = 0; c < 8; ++c) {
+            const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
+            const double w = (ox ? tx : 1 - tx) * (oy ? ty : 1 - ty) * (oz ? tz : 1 - tz);
+            if (w == 0.0) continue;
+            const int kk = ck + oz;
+            if (kk < 1 || kk > sj.nzs - 1)
+              return fail(OSAM_E_OUTSIDE, "projection touches a constrained node of the source");
+            row.push_back({(ci + ox) + (g.nx + 1) * ((cj + oy) + (g.ny + 1) * kk), w});
+          }
+          width = std::max(width, (int)row.size());
+        }
+      P.width = width;
+      P.idx.assign((size_t)d.npl * width, 0);
+      P.wt.assign((size_t)d.npl * width, 0.0);
+      for (int n = 0; n < d.npl; ++n)
+        for (size_t w = 0; w < rows[n].size(); ++w) {
+          P.idx[(size_t)n * width + w] = rows[n][w].first;
+          P.wt[(size_t)n * width + w] = rows[n][w].second;
+        }
+      // conforming slabs: the projection must be the injection node -> node
+      P.src_layer = layer - g.z_lo;
+      for (int n = 0; n < d.npl; ++n)
+        if (width != 1 || P.wt[n] != 1.0 || P.idx[n] != n + P.src_layer * sj.npl)
+          return fail(OSAM_E_INVALID, "non-conforming Schwarz faces are not supported");
+    }
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  coupled = true;
+  wired = false;
+  return OSAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Wiring: face-value buffers of OpInf subdomains fed by a FOM, Phi_S face
+// blocks and ROM-to-ROM transfer matrices, Pi Phi export rows.
+int32_t Ctx::wire() {
+  if (wired) return OSAM_OK;
+  int32_t st = OSAM_OK;
+  const int S = (int)sds.size();
+  for (int i = 0; i < S; ++i) {
+    Subdomain &d = *sds[i];
+    for (int f = 0; f < 2; ++f) {
+      if (d.face_type[f] == kFaceClamped) continue;
+      const Subdomain &src = *sds[d.proj[f].src];
+      const int n = 3 * d.npl;
+      if (d.rom && !src.rom && !d.sface[f][0]) {
+        for (int k = 0; k < 3; ++k) {
+          d.sface[f][k] = alloc_t((size_t)batch * n, &st);
+          if (st) return fail(st, "oom");
+          HIPCHK(hipMemsetAsync(d.sface[f][k], 0, (size_t)batch * n * esize(), stream));
+        }
+      }
+      if (d.rom) {
+        const long long off = f == 0 ? 0 : d.face_off_hi;
+        const long long ns = 3 * d.nsch_nodes;
+        // Phi_S block of this face: [rs][3 npl]
+        std::vector<double> blk((size_t)d.rs * n);
+        for (int k = 0; k < d.rs; ++k)
+          for (int c = 0; c < 3; ++c)
+            for (int nid = 0; nid < d.npl; ++nid)
+              blk[(size_t)k * n + c * d.npl + nid] = d.oh.PhiS[(size_t)k * ns + c * d.nsch_nodes + off + nid];
+        if (!d.face_phis[f]) {
+          d.face_phis[f] = alloc_t(blk.size(), &st);
+          if (st) return fail(st, "oom");
+        }
+        if ((st = upload(d.face_phis[f], blk.data(), blk.size()))) return st;
+        if (src.rom) {
+          // T = Phi_S,face^T (Pi Phi_src), [rs][r_src] row-major
+          if (src.oh.Phi.empty()) return fail(OSAM_E_INVALID, "source basis not available on host");
+          const FaceProj &P = d.proj[f];
+          const long long nfs = 3 * src.nfree_nodes;
+          std::vector<double> tm((size_t)d.rs * src.r, 0.0);
+          for (int c = 0; c < 3; ++c)
+            for (int nid = 0; nid < d.npl; ++nid)
+              for (int w = 0; w < P.width; ++w) {
+                const double wt = P.wt[(size_t)nid * P.width + w];
+                if (wt == 0.0) continue;
+                const long long fn = P.idx[(size_t)nid * P.width + w] - src.npl;
+                for (int j = 0; j < src.r; ++j) {
+                  const double pv = wt * src.oh.Phi[(size_t)j * nfs + c * src.nfree_nodes + fn];
+                  for (int k = 0; k < d.rs; ++k) tm[(size_t)k * src.r + j] += blk[(size_t)k * n + c * d.npl + nid] * pv;
+                }
+              }
+          if (!d.face_tm[f]) {
+            d.face_tm[f] = alloc_t(tm.size(), &st);
+            if (st) return fail(st, "oom");
+          }
+          if ((st = upload(d.face_tm[f], tm.data(), tm.size()))) return st;
+        }
+      }
+    }
+  }
+  // exports: every FOM face fed by a ROM gets Pi Phi rows, stored at the source
+  for (int j = 0; j < S; ++j) {
+    Subdomain &s = *sds[j];
+    if (!s.rom) continue;
+    s.piphi_h.clear();
+  }
+  for (int i = 0; i < S; ++i) {
+    Subdomain &d = *sds[i];
+    if (d.rom) continue;
+    for (int f = 0; f < 2; ++f) {
+      if (d.face_type[f] == kFaceClamped) continue;
+      Subdomain &src = *sds[d.proj[f].src];
+      if (!src.rom) continue;
+      const FaceProj &P = d.proj[f];
+      const int n = 3 * d.npl;
+      std::vector<double> pp((size_t)src.r * n, 0.0);
+      if (src.oh.Phi.empty()) return fail(OSAM_E_INVALID, "source basis not available on host");
+      const long long nfs = 3 * src.nfree_nodes;
+      for (int c = 0; c < 3; ++c)
+        for (int nid = 0; nid < d.npl; ++nid)
+          for (int w = 0; w < P.width; ++w) {
+            const double wt = P.wt[(size_t)nid * P.width + w];
+            if (wt == 0.0) continue;
+            const long long fn = P.idx[(size_t)nid * P.width + w] - src.npl;
+            for (int k = 0; k < src.r; ++k)
+              pp[(size_t)k * n + c * d.npl + nid] += wt * src.oh.Phi[(size_t)k * nfs + c * src.nfree_nodes + fn];
+          }
+      src.piphi_h.push_back(pp);
+    }
+  }
+  // device copies of the export rows (order: FOM subdomains ascending, low face first)
+  for (int j = 0; j < S; ++j) {
+    Subdomain &s = *sds[j];
+    if (!s.rom) continue;
+    s.piphi_d.clear();
+    for (auto &pp : s.piphi_h) {
+      void *p = alloc_t(pp.size(), &st);
+      if (st) return fail(st, "oom");
+      if ((st = upload(p, pp.data(), pp.size()))) return st;
+      s.piphi_d.push_back(p);
+    }
+  }
+  // FOM state buffers only for FOM subdomains
+  for (int i = 0; i < S; ++i) {
+    Subdomain &d = *sds[i];
+    const size_t nb = (size_t)batch * d.is;
+    if (!d.rom && !d.u[0]) {
+      for (int k = 0; k < 3; ++k) {
+        d.u[k] = alloc_t(nb, &st);
+        if (st) return fail(st, "out of device memory for FOM state");
+        HIPCHK(hipMemsetAsync(d.u[k], 0, nb * esize(), stream));
+      }
+      for (int k = 0; k < 2; ++k) {
+        d.v[k] = alloc_t(nb, &st);
+        d.a[k] = alloc_t(nb, &st);
+        if (st) return fail(st, "out of device memory for FOM state");
+        HIPCHK(hipMemsetAsync(d.v[k], 0, nb * esize(), stream));
+        HIPCHK(hipMemsetAsync(d.a[k], 0, nb * esize(), stream));
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  wired = true;
+  return OSAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+int32_t Ctx::sync_status() {
+  HIPCHK(hipMemcpyAsync(h_status, d_status, sizeof(Status) * batch, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return OSAM_OK;
+}
+
+static void kron2_host(const std::vector<double> &q, std::vector<double> &k) {
+  const int r = (int)q.size();
+  k.clear();
+  for (int i = 0; i < r; ++i)
+    for (int j = i; j < r; ++j) k.push_back(q[i] * q[j]);
+}
+
+int32_t Ctx::set_initial(int inst, const double *u0g, const double *v0g) {
+  int32_t st = wire();
+  if (st) return st;
+  st = sync_status();
+  if (st) return st;
+  const osam_subdomain_desc &g0 = sds[0]->desc;
+  const long long nxp = g0.nx + 1, nyp = g0.ny + 1;
+  const long long ng = nxp * nyp * (g0.nz + 1);
+  for (size_t i = 0; i < sds.size(); ++i) {
+    Subdomain &d = *sds[i];
+    std::vector<double> u((size_t)3 * d.cs, 0.0), v((size_t)3 * d.cs, 0.0);
+    for (int kl = 0; kl <= d.nzs; ++kl) {
+      const bool clamped = (kl == 0 && d.face_type[0] == kFaceClamped) ||
+                           (kl == d.nzs && d.face_type[1] == kFaceClamped);
+      const bool face = kl == 0 || kl == d.nzs;
+      for (int nid = 0; nid < d.npl; ++nid) {
+        const long long gid = nid + nxp * nyp * (kl + d.desc.z_lo);
+        for (int c = 0; c < 3; ++c) {
+          const size_t li = (size_t)c * d.cs + (size_t)kl * d.npl + nid;
+          u[li] = clamped ? 0.0 : u0g[c * ng + gid];
+          v[li] = face ? 0.0 : v0g[c * ng + gid];
+        }
+      }
+    }
+    if (!d.rom) {
+      const size_t off = (size_t)inst * d.is * esize();
+      if ((st = upload((char *)d.u[0] + off, u.data(), u.size()))) return st;
+      if ((st = upload((char *)d.v[0] + off, v.data(), v.size()))) return st;
+    } else {
+      // q0 = Phi^T u0, q'0 = Phi^T v0 on free DOFs (device projection, FP64 sums)
+      const int nchunks = 64;
+      double *part = scratch((size_t)2 * d.r * nchunks + (size_t)3 * d.cs * 2, &st);
+      if (st) return fail(st, "oom");
+      void *fld = (char *)part + sizeof(double) * 2 * d.r * nchunks;
+      std::vector<double> q(d.r), qd(d.r);
+      for (int which = 0; which < 2; ++which) {
+        if ((st = upload(fld, which == 0 ? u.data() : v.data(), u.size()))) return st;
+        hipError_t e;
+        if (prec == OSAM_FP64)
+          e = launch_project<double>((const double *)d.d_Phi, 3 * d.nfree_nodes, d.nfree_nodes,
+                                     (const double *)fld, d.cs, d.npl, part, nchunks, d.r, stream);
+        else
+          e = launch_project<float>((const float *)d.d_Phi, 3 * d.nfree_nodes, d.nfree_nodes,
+                                    (const float *)fld, d.cs, d.npl, part, nchunks, d.r, stream);
+        if (e != hipSuccess) return fail(OSAM_E_HIP, hipGetErrorString(e));
+        std::vector<double> hp((size_t)d.r * nchunks);
+        HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        for (int k = 0; k < d.r; ++k) {
+          double s = 0.0;
+          for (int cch = 0; cch < nchunks; ++cch) s += hp[(size_t)k * nchunks + cch];
+          (which == 0 ? q : qd)[k] = s;
+        }
+      }
+      // g^0 = Phi_S^T s0 with s0 = IC on the Schwarz DOFs; q''0 = f(q0, g^0)
+      const long long ns = 3 * d.nsch_nodes;
+      std::vector<double> s0(ns, 0.0), gh(d.rs, 0.0);
+      for (int c = 0; c < 3; ++c)
+        for (int f = 0; f < 2; ++f) {
+          if (d.face_type[f] == kFaceClamped) continue;
+          const int kl = f == 0 ? 0 : d.nzs;
+          const long long off = f == 0 ? 0 : d.face_off_hi;
+          for (int nid = 0; nid < d.npl; ++nid)
+            s0[c * d.nsch_nodes + off + nid] = u[(size_t)c * d.cs + (size_t)kl * d.npl + nid];
+        }
+      for (int k = 0; k < d.rs; ++k) {
+        double s = 0.0;
+        for (long long m = 0; m < ns; ++m) s += d.oh.PhiS[(size_t)k * ns + m] * s0[m];
+        gh[k] = s;
+      }
+      std::vector<double> qdd(d.r, 0.0), k2;
+      kron2_host(q, k2);
+      const int r2 = d.r * (d.r + 1) / 2;
+      for (int i2 = 0; i2 < d.r; ++i2) {
+        double s = d.oh.c.empty() ? 0.0 : d.oh.c[i2];
+        for (int j = 0; j < d.r; ++j) s += d.oh.A[(size_t)j * d.r + i2] * q[j];
+        if (d.oh.quadratic)
+          for (int m = 0; m < r2; ++m) s += d.oh.H[(size_t)m * d.r + i2] * k2[m];
+        for (int l = 0; l < d.rs; ++l) s += d.oh.B[(size_t)l * d.r + i2] * gh[l];
+        qdd[i2] = s;
+      }
+      const size_t off = (size_t)inst * d.r * esize();
+      if ((st = upload((char *)d.q[0] + off, q.data(), d.r))) return st;
+      if ((st = upload((char *)d.qd[0] + off, qd.data(), d.r))) return st;
+      if ((st = upload((char *)d.qdd[0] + off, qdd.data(), d.r))) return st;
+      if (d.rec.every > 0 && d.rec.u && d.rec.n_cols > 0) {
+        if ((st = upload((char *)d.rec.u + (size_t)inst * d.rec.n_cols * d.r * esize(), q.data(), d.r)))
+          return st;
+      }
+      // the FOM neighbours' faces at t_1: (Pi Phi) of the reduced predictor
+      std::vector<double> q1(d.r);
+      for (int k = 0; k < d.r; ++k)
+        q1[k] = q[k] + d.desc.dt * qd[k] + 0.5 * d.desc.dt * d.desc.dt * qdd[k];
+      int e = 0;
+      for (size_t i2 = 0; i2 < sds.size(); ++i2) {
+        Subdomain &fd = *sds[i2];
+        if (fd.rom) continue;
+        for (int f = 0; f < 2; ++f) {
+          if (fd.face_type[f] == kFaceClamped || fd.proj[f].src != (int)i) continue;
+          const std::vector<double> &pp = d.piphi_h[e++];
+          const int n = 3 * fd.npl;
+          std::vector<double> sv(n, 0.0);
+          for (int k = 0; k < d.r; ++k)
+            for (int m = 0; m < n; ++m) sv[m] += pp[(size_t)k * n + m] * q1[k];
+          const size_t lay = (size_t)(f == 0 ? 0 : fd.nzs) * fd.npl;
+          for (int c = 0; c < 3; ++c) {
+            const size_t off = ((size_t)inst * fd.is + (size_t)c * fd.cs + lay) * esize();
+            if ((st = upload((char *)fd.u[1] + off, sv.data() + (size_t)c * fd.npl, fd.npl))) return st;
+          }
+        }
+      }
+      // own faces fed by a FOM: role U0 (t_0) holds the IC
+      for (int f = 0; f < 2; ++f) {
+        if (!d.sface[f][0]) continue;
+        const int kl = f == 0 ? 0 : d.nzs;
+        std::vector<double> fv((size_t)3 * d.npl);
+        for (int c = 0; c < 3; ++c)
+          for (int nid = 0; nid < d.npl; ++nid)
+            fv[(size_t)c * d.npl + nid] = u[(size_t)c * d.cs + (size_t)kl * d.npl + nid];
+        if ((st = upload((char *)d.sface[f][0] + (size_t)inst * 3 * d.npl * esize(), fv.data(), fv.size())))
+          return st;
+      }
+    }
+  }
+  Status &S = h_status[inst];
+  std::memset(&S, 0, sizeof(Status));
+  S.flags = kNeedInit;
+  HIPCHK(hipMemcpyAsync(d_status + inst, &S, sizeof(Status), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  initialized[inst] = 1;
+  return OSAM_OK;
+}
+
+// a0 = M^-1(-K u0) and the first predictor for instances flagged kNeedInit.
+int32_t Ctx::init_pending() {
+  bool any = false;
+  for (int b = 0; b < batch; ++b) any |= (h_status[b].flags & kNeedInit) != 0;
+  if (!any) return OSAM_OK;
+  Opts o{};
+  o.nsd = (int)sds.size();
+  for (size_t i = 0; i < sds.size(); ++i)
+    if (!sds[i]->rom) {
+      int32_t st = launch_fe_sd((int)i, o, 1);
+      if (st) return st;
+    }
+  int32_t st = sync_status();
+  if (st) return st;
+  for (int b = 0; b < batch; ++b) h_status[b].flags &= ~kNeedInit;
+  HIPCHK(hipMemcpyAsync(d_status, h_status, sizeof(Status) * batch, hipMemcpyHostToDevice, stream));
+  return OSAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T> &A) {
+  std::memset(&A, 0, sizeof(A));
+  A.nx = s.nx;
+  A.ny = s.ny;
+  A.nzs = s.nzs;
+  A.npl = s.npl;
+  A.cs = s.cs;
+  A.is = s.is;
+  for (int k = 0; k < 3; ++k) A.u[k] = (T *)s.u[k];
+  for (int k = 0; k < 2; ++k) {
+    A.v[k] = (T *)s.v[k];
+    A.a[k] = (T *)s.a[k];
+  }
+  A.coef = (const T *)s.coef;
+  A.dt = (T)s.desc.dt;
+  A.half_dt = (T)(0.5 * s.desc.dt);
+  A.half_dt2 = (T)(0.5 * s.desc.dt * s.desc.dt);
+  for (int f = 0; f < 2; ++f) A.face_src[f] = s.face_type[f] == kFaceClamped ? -1 : s.proj[f].src;
+  // pushes: every face of another subdomain whose source is this one
+  A.npush = 0;
+  for (size_t i = 0; i < c.sds.size(); ++i) {
+    Subdomain &d = *c.sds[i];
+    for (int f = 0; f < 2; ++f) {
+      if (d.face_type[f] == kFaceClamped || d.proj[f].src != sdi) continue;
+      PushDev<T> &Pd = A.push[A.npush++];
+      Pd.layer = d.proj[f].src_layer;
+      if (d.rom) {
+        for (int k = 0; k < 3; ++k) Pd.role[k] = (T *)d.sface[f][k];
+        Pd.cs = d.npl;
+        Pd.is = 3LL * d.npl;
+      } else {
+        const long long lay = (long long)(f == 0 ? 0 : d.nzs) * d.npl;
+        for (int k = 0; k < 3; ++k) Pd.role[k] = (T *)d.u[k] + lay;
+        Pd.cs = d.cs;
+        Pd.is = d.is;
+      }
+    }
+  }
+  A.status = c.d_status;
+  A.sd = sdi;
+  A.opts = o;
+  A.partials = s.partials;
+  A.counters = s.counters;
+  A.kc = s.fe_kc;
+  A.n_chunks = s.fe_chunks;
+  A.n_int = s.n_int;
+  A.n_bnd = s.n_bnd;
+  A.int_blocks = s.fe_int_blocks;
+  A.nblocks = s.fe_nblocks;
+  A.bnd_cols = s.bnd_cols;
+  A.rec_u = (T *)s.rec.u;
+  A.rec_a = (T *)s.rec.a;
+  A.rec_s = (T *)s.rec.s;
+  A.rec_every = s.rec.every;
+  A.rec_ncols = s.rec.n_cols;
+  A.nfree_nodes = s.nfree_nodes;
+  A.nsch_nodes = s.nsch_nodes;
+  A.face_off_hi = s.face_off_hi;
+}
+
+int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode) {
+  Subdomain &s = *sds[sdi];
+  hipError_t e;
+  if (prec == OSAM_FP64) {
+    FeArgs<double> A;
+    fill_fe_args<double>(*this, s, sdi, o, A);
+    e = launch_fe<double>(A, batch, s.fe_block, mode, stream);
+  } else {
+    FeArgs<float> A;
+    fill_fe_args<float>(*this, s, sdi, o, A);
+    e = launch_fe<float>(A, batch, s.fe_block, mode, stream);
+  }
+  if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("fe kernel: ") + hipGetErrorString(e));
+  return OSAM_OK;
+}
+
+template <typename T>
+static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<T> &A) {
+  std::memset(&A, 0, sizeof(A));
+  A.r = s.r;
+  A.rs = s.rs;
+  A.r2 = s.oh.quadratic ? s.r * (s.r + 1) / 2 : 0;
+  A.A = (const T *)s.d_A;
+  A.H = (const T *)s.d_H;
+  A.B = s.rs > 0 ? (const T *)s.d_B : nullptr;
+  A.c = (const T *)s.d_c;
+  for (int k = 0; k < 2; ++k) {
+    A.q[k] = (T *)s.q[k];
+    A.qd[k] = (T *)s.qd[k];
+    A.qdd[k] = (T *)s.qdd[k];
+  }
+  A.dt = (T)s.desc.dt;
+  A.half_dt = (T)(0.5 * s.desc.dt);
+  A.half_dt2 = (T)(0.5 * s.desc.dt * s.desc.dt);
+  int nf = 0;
+  for (int f = 0; f < 2; ++f) {
+    if (s.face_type[f] == kFaceClamped || s.rs == 0) continue;
+    const FaceProj &P = s.proj[f];
+    const Subdomain &src = *c.sds[P.src];
+    RomFaceIn<T> &F = A.fin[nf++];
+    F.src_sd = P.src;
+    F.n = 3 * s.npl;
+    F.phis = (const T *)s.face_phis[f];
+    if (src.rom) {
+      F.type = 3;
+      F.src_r = src.r;
+      F.tm = (const T *)s.face_tm[f];
+      F.src_q[0] = (T *)src.q[0];
+      F.src_q[1] = (T *)src.q[1];
+    } else {
+      F.type = kFaceFom;
+      for (int k = 0; k < 3; ++k) F.sface[k] = (const T *)s.sface[f][k];
+    }
+  }
+  A.nfaces = nf;
+  int ne = 0;
+  for (size_t i = 0; i < c.sds.size(); ++i) {
+    Subdomain &fd = *c.sds[i];
+    if (fd.rom) continue;
+    for (int f = 0; f < 2; ++f) {
+      if (fd.face_type[f] == kFaceClamped || fd.proj[f].src != sdi) continue;
+      RomExport<T> &E = A.ex[ne];
+      const long long lay = (long long)(f == 0 ? 0 : fd.nzs) * fd.npl;
+      for (int k = 0; k < 3; ++k) E.role[k] = (T *)fd.u[k] + lay;
+      E.cs = fd.cs;
+      E.is = fd.is;
+      E.npl = fd.npl;
+      E.piphi = (const T *)s.piphi_d[ne];
+      ++ne;
+    }
+  }
+  A.nexp = ne;
+  A.status = c.d_status;
+  A.sd = sdi;
+  A.opts = o;
+  A.rec_q = (T *)s.rec.u;
+  A.rec_every = s.rec.every;
+  A.rec_ncols = s.rec.n_cols;
+}
+
+int32_t Ctx::launch_rom_sd(int sdi, const Opts &o) {
+  Subdomain &s = *sds[sdi];
+  hipError_t e;
+  if (prec == OSAM_FP64) {
+    RomArgs<double> A;
+    fill_rom_args<double>(*this, s, sdi, o, A);
+    e = launch_rom<double>(A, batch, stream);
+  } else {
+    RomArgs<float> A;
+    fill_rom_args<float>(*this, s, sdi, o, A);
+    e = launch_rom<float>(A, batch, stream);
+  }
+  if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("rom kernel: ") + hipGetErrorString(e));
+  return OSAM_OK;
+}
+
+int32_t Ctx::launch_round(const Opts &o) {
+  for (size_t i = 0; i < sds.size(); ++i) {
+    int32_t st = sds[i]->rom ? launch_rom_sd((int)i, o) : launch_fe_sd((int)i, o, 0);
+    if (st) return st;
+  }
+  return OSAM_OK;
+}
+
+int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_info *info) {
+  if (!(op.tol_abs >= 0) || !(op.tol_rel >= 0) || op.min_iter < 1 || op.max_iter < op.min_iter ||
+      op.max_iter > 1000000 || (op.guess != OSAM_GUESS_HOLD && op.guess != OSAM_GUESS_PREDICTOR))
+    return fail(OSAM_E_INVALID, "bad Schwarz options");
+  int32_t st = couple();
+  if (st) return st;
+  if ((st = wire())) return st;
+  for (int b = 0; b < batch; ++b)
+    if (!initialized[b]) return fail(OSAM_E_ORDER, "instance without initial condition");
+  if ((st = sync_status())) return st;
+  if ((st = init_pending())) return st;
+  Opts o{};
+  o.tol_abs2 = op.tol_abs * op.tol_abs;
+  o.tol_rel2 = op.tol_rel * op.tol_rel;
+  o.min_iter = op.min_iter;
+  o.max_iter = op.max_iter;
+  o.guess = op.guess;
+  o.nsd = (int)sds.size();
+  bool any = false;
+  for (int b = 0; b < batch; ++b) {
+    Status &S = h_status[b];
+    if (S.flags & kNonfinite) continue;
+    S.target = S.step + n_steps;
+    S.flags &= ~kFinished;
+    if (n_steps == 0) S.flags |= kFinished;
+    S.iter = 0;
+    any |= n_steps > 0;
+  }
+  HIPCHK(hipMemcpyAsync(d_status, h_status, sizeof(Status) * batch, hipMemcpyHostToDevice, stream));
+  // every step ends within max_iter sweeps: bound the total work the host enqueues
+  const long long round_cap = n_steps * (long long)o.max_iter + 8;
+  long long rounds_done = 0;
+  while (any) {
+    // every step needs at least min_iter sweeps: never enqueue more than the
+    // least any unfinished instance still needs
+    long long rounds = 0;
+    for (int b = 0; b < batch; ++b) {
+      const Status &S = h_status[b];
+      if (S.flags & kFinished) continue;
+      rounds = std::max(rounds, (S.target - S.step) * o.min_iter - S.iter);
+    }
+    rounds = std::max<long long>(1, rounds);
+    if (rounds_done + rounds > round_cap)
+      return fail(OSAM_E_HIP, "controller did not finish within n_steps * max_iter sweeps");
+    for (long long k = 0; k < rounds; ++k)
+      if ((st = launch_round(o))) return st;
+    rounds_done += rounds;
+    if ((st = sync_status())) return st;
+    any = false;
+    for (int b = 0; b < batch; ++b) any |= !(h_status[b].flags & kFinished);
+  }
+  if ((st = sync_status())) return st;
+  bool nonfinite = false;
+  for (int b = 0; b < batch; ++b) {
+    const Status &S = h_status[b];
+    nonfinite |= (S.flags & kNonfinite) != 0;
+    if (info) {
+      osam_instance_info &I = info[b];
+      I.steps = S.step;
+      I.last_iters = S.last_iters;
+      I.last_converged = S.last_conv;
+      I.abs2 = S.abs2;
+      I.den2 = S.den2;
+      I.total_iters = S.total_iters;
+      I.max_iters = S.max_iters;
+      I.unconverged = S.unconverged;
+      I.status = (S.flags & kNonfinite) ? OSAM_E_NONFINITE : OSAM_OK;
+    }
+  }
+  if (nonfinite) return fail(OSAM_E_NONFINITE, "non-finite state or norm");
+  return OSAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+int32_t Ctx::get_state(int sdi, int inst, double *u, double *v, double *a) {
+  int32_t st = sync_status();
+  if (st) return st;
+  Subdomain &d = *sds[sdi];
+  const long long step = h_status[inst].step;
+  std::vector<double> tmp((size_t)3 * d.cs);
+  auto out = [&](double *dst) {
+    for (int c = 0; c < 3; ++c)
+      std::memcpy(dst + (size_t)c * d.nnodes, tmp.data() + (size_t)c * d.cs, sizeof(double) * d.nnodes);
+  };
+  if (!d.rom) {
+    if (!d.u[0]) return fail(OSAM_E_ORDER, "no state");
+    const size_t off = (size_t)inst * d.is * esize();
+    void *bufs[3] = {(char *)d.u[step % 3] + off, (char *)d.v[step % 2] + off, (char *)d.a[step % 2] + off};
+    double *dst[3] = {u, v, a};
+    for (int k = 0; k < 3; ++k) {
+      if (!dst[k]) continue;
+      if ((st = download(tmp.data(), bufs[k], tmp.size()))) return st;
+      out(dst[k]);
+    }
+    return OSAM_OK;
+  }
+  // lifted OpInf field: Phi q on free nodes, zero elsewhere
+  double *scr = scratch((size_t)3 * d.cs + 8, &st);
+  if (st) return fail(st, "oom");
+  void *qs[3] = {d.q[step % 2], d.qd[step % 2], d.qdd[step % 2]};
+  double *dst[3] = {u, v, a};
+  for (int k = 0; k < 3; ++k) {
+    if (!dst[k]) continue;
+    HIPCHK(hipMemsetAsync(scr, 0, (size_t)3 * d.cs * esize(), stream));
+    const size_t qo = (size_t)inst * d.r * esize();
+    hipError_t e;
+    if (prec == OSAM_FP64)
+      e = launch_lift<double>((const double *)d.d_Phi, 3 * d.nfree_nodes, d.nfree_nodes, d.r,
+                              (const double *)((char *)qs[k] + qo), (double *)scr, d.cs, d.npl, stream);
+    else
+      e = launch_lift<float>((const float *)d.d_Phi, 3 * d.nfree_nodes, d.nfree_nodes, d.r,
+                             (const float *)((char *)qs[k] + qo), (float *)scr, d.cs, d.npl, stream);
+    if (e != hipSuccess) return fail(OSAM_E_HIP, hipGetErrorString(e));
+    if ((st = download(tmp.data(), scr, tmp.size()))) return st;
+    out(dst[k]);
+  }
+  return OSAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
+  Subdomain &d = *sds[sdi];
+  int32_t st = OSAM_OK;
+  const int r = oh.r, rs = oh.rs, r2 = r * (r + 1) / 2;
+  const long long nf = 3 * d.nfree_nodes;
+  // free any previous OpInf data and the FOM state buffers
+  void *old[] = {d.d_A, d.d_H, d.d_B, d.d_c, d.d_Phi, d.q[0], d.q[1], d.qd[0], d.qd[1], d.qdd[0], d.qdd[1],
+                 d.u[0], d.u[1], d.u[2], d.v[0], d.v[1], d.a[0], d.a[1], d.face_phis[0], d.face_phis[1],
+                 d.face_tm[0], d.face_tm[1]};
+  HIPCHK(hipStreamSynchronize(stream));
+  for (void *p : old) dfree(p);
+  d.d_A = d.d_H = d.d_B = d.d_c = d.d_Phi = nullptr;
+  for (int k = 0; k < 2; ++k) d.q[k] = d.qd[k] = d.qdd[k] = nullptr;
+  for (int k = 0; k < 3; ++k) d.u[k] = nullptr;
+  for (int k = 0; k < 2; ++k) d.v[k] = d.a[k] = nullptr;
+  for (int k = 0; k < 2; ++k) d.face_phis[k] = d.face_tm[k] = nullptr;
+  // row-major copies for the kernels
+  std::vector<double> Ar((size_t)r * r), Hr, Br;
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) Ar[(size_t)i * r + j] = oh.A[(size_t)j * r + i];
+  if (oh.quadratic) {
+    Hr.resize((size_t)r * r2);
+    for (int i = 0; i < r; ++i)
+      for (int m = 0; m < r2; ++m) Hr[(size_t)i * r2 + m] = oh.H[(size_t)m * r + i];
+  }
+  if (rs > 0) {
+    Br.resize((size_t)r * rs);
+    for (int i = 0; i < r; ++i)
+      for (int l = 0; l < rs; ++l) Br[(size_t)i * rs + l] = oh.B[(size_t)l * r + i];
+  }
+  d.d_A = alloc_t(Ar.size(), &st);
+  if (oh.quadratic) d.d_H = alloc_t(Hr.size(), &st);
+  if (rs > 0) d.d_B = alloc_t(Br.size(), &st);
+  if (!oh.c.empty()) d.d_c = alloc_t(r, &st);
+  d.d_Phi = alloc_t((size_t)nf * r, &st);
+  for (int k = 0; k < 2; ++k) {
+    d.q[k] = alloc_t((size_t)batch * r, &st);
+    d.qd[k] = alloc_t((size_t)batch * r, &st);
+    d.qdd[k] = alloc_t((size_t)batch * r, &st);
+  }
+  if (st) return fail(st, "out of device memory for OpInf data");
+  if ((st = upload(d.d_A, Ar.data(), Ar.size()))) return st;
+  if (oh.quadratic && (st = upload(d.d_H, Hr.data(), Hr.size()))) return st;
+  if (rs > 0 && (st = upload(d.d_B, Br.data(), Br.size()))) return st;
+  if (!oh.c.empty() && (st = upload(d.d_c, oh.c.data(), r))) return st;
+  if (!oh.Phi.empty() && (st = upload(d.d_Phi, oh.Phi.data(), oh.Phi.size()))) return st;
+  d.oh = oh;
+  d.rom = true;
+  d.r = r;
+  d.rs = rs;
+  wired = false;
+  std::fill(initialized.begin(), initialized.end(), 0);
+  HIPCHK(hipStreamSynchronize(stream));
+  return OSAM_OK;
+}
+
+}  // namespace osam

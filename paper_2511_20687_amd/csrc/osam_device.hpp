@@ -1,0 +1,155 @@
+// Device-side data structures shared by the libosam kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace osam {
+
+constexpr int kMaxSd = 8;
+
+// Per-instance controller state, in device memory.  Only the kernels modify it
+// while a run is in flight; the host reads it back between chunks of work.
+struct Status {
+  long long step;          // accepted controller steps
+  long long target;        // the instance stops when step == target
+  int iter;                // Schwarz iterations done in the current step
+  int flags;               // kFinished | kNonfinite
+  int last_iters, last_conv;
+  long long total_iters, unconverged;
+  int max_iters, pad0;
+  double abs2, den2;       // last evaluated criterion
+  double sd_abs2[kMaxSd];  // this iteration's per-subdomain sums
+  double sd_den2[kMaxSd];
+};
+constexpr int kFinished = 1;
+constexpr int kNonfinite = 2;
+constexpr int kNeedInit = 4;
+
+struct Opts {
+  double tol_abs2, tol_rel2;
+  int min_iter, max_iter, guess, nsd;
+};
+
+// Convergence decision of Eq. conv_criterion after the last subdomain of a
+// Schwarz sweep (executed by a single thread).
+__device__ inline void decide(Status &st, int sd, const Opts &o) {
+  if (sd != o.nsd - 1) return;
+  const int n = st.iter + 1;
+  double a = 0.0, d = 0.0;
+  for (int i = 0; i < o.nsd; ++i) {
+    a += st.sd_abs2[i];
+    d += st.sd_den2[i];
+  }
+  const bool tested = n >= o.min_iter;
+  if (!isfinite(d) || (tested && !isfinite(a))) {
+    st.abs2 = a;
+    st.den2 = d;
+    st.flags |= kFinished | kNonfinite;
+    return;
+  }
+  bool conv = false;
+  if (tested) {
+    conv = (a < o.tol_abs2) || (a < o.tol_rel2 * d);
+    st.abs2 = a;
+    st.den2 = d;
+  }
+  if (conv || n >= o.max_iter) {
+    st.step += 1;
+    st.last_iters = n;
+    st.last_conv = conv ? 1 : 0;
+    st.total_iters += n;
+    if (n > st.max_iters) st.max_iters = n;
+    if (!conv) st.unconverged += 1;
+    st.iter = 0;
+    if (st.step >= st.target) st.flags |= kFinished;
+  } else {
+    st.iter = n;
+  }
+}
+
+// Faces and pushes.  All subdomains share one global grid, so a Schwarz face of
+// subdomain i coincides with a node layer of its source j (the pointwise
+// projection is an injection).  Every source writes the displacement it will
+// have at the next controller step (its Newmark predictor) straight into the
+// face values of its destinations, into the buffer role of the next step;
+// buffer roles rotate with the instance's step count (U0 = role s%3, P =
+// (s+1)%3, P2 = (s+2)%3).  A destination then finds on its face:
+//   role U0 : the source at t_{k-1}  (HOLD guess, Sec. 4.1)
+//   role P  : the source at t_k      (newest iterate; equal across iterations
+//                                     for the explicit scheme)
+enum FaceType : int { kFaceClamped = 0, kFaceFom = 1, kFaceStage = 2 };
+
+template <typename T>
+struct PushDev {
+  int layer;               // source-local node layer that feeds the face
+  int pad;
+  T *role[3];              // destination face-value buffers by role, at the face start
+  long long cs, is;        // destination component / instance strides
+};
+
+// Arguments of the FE explicit-step kernel (one subdomain, all instances).
+template <typename T>
+struct FeArgs {
+  int nx, ny, nzs, npl;
+  long long cs, is;        // component stride, instance stride (elements)
+  T *u[3];                 // rotating displacement buffers (U0, P, P2 by step parity)
+  T *v[2];
+  T *a[2];
+  const T *coef;           // [9 cases][26 offsets][3][3]: -K_d / m
+  T dt, half_dt, half_dt2;
+  int face_src[2];         // source subdomain of the low / high face, -1 if clamped
+  int npush;
+  PushDev<T> push[2];
+  Status *status;
+  int sd;
+  Opts opts;
+  double *partials;        // [batch][nblocks][2]
+  unsigned *counters;      // [batch]
+  int kc, n_chunks, n_int, n_bnd, int_blocks, nblocks;
+  const int *bnd_cols;     // boundary columns (ids in the layer)
+  // records: [batch][ncols][len]
+  T *rec_u, *rec_a, *rec_s;
+  long long rec_every, rec_ncols;
+  long long nfree_nodes, nsch_nodes, face_off_hi;  // Schwarz nodes of low face come first
+};
+
+template <typename T>
+struct RomFaceIn {
+  int type;                // kFaceFom: pushed values in sface; 3: ROM source (tm q_src)
+  int src_sd;
+  int n;                   // Schwarz DOFs of this face (3*npl)
+  int src_r;
+  const T *sface[3];       // [batch][n] face values by role (kFaceFom)
+  const T *phis;           // [rs][n] column-major block of Phi_S for this face
+  const T *tm;             // [rs][src_r] row-major: Phi_S,face^T Pi Phi_src (ROM source)
+  T *src_q[2];             // source reduced displacement buffers [batch][src_r]
+};
+
+template <typename T>
+struct RomExport {
+  T *role[3];              // destination face values by role, at the face start
+  long long cs, is;        // destination component / instance strides
+  int npl;
+  const T *piphi;          // [r][3 npl] column-major rows of Pi Phi for the face
+};
+
+template <typename T>
+struct RomArgs {
+  int r, rs, r2;           // r2 = r(r+1)/2 when quadratic else 0
+  const T *A;              // [r][r] row-major
+  const T *H;              // [r][r2] row-major or null
+  const T *B;              // [r][rs] row-major or null
+  const T *c;              // [r] or null
+  T *q[2], *qd[2], *qdd[2];  // [batch][r] by step parity
+  T dt, half_dt, half_dt2;
+  int nfaces, nexp;
+  RomFaceIn<T> fin[2];
+  RomExport<T> ex[2];
+  Status *status;
+  int sd;
+  Opts opts;
+  T *rec_q;
+  long long rec_every, rec_ncols;
+};
+
+}  // namespace osam

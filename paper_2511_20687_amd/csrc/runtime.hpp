@@ -1,0 +1,103 @@
+// Host-side objects of libosam (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/osam.h"
+#include "osam_device.hpp"
+
+namespace osam {
+
+// OpInf data in float64 on the host (column-major as installed), kept for
+// read-back, initial states and re-wiring.
+struct OpinfHost {
+  int r = 0, rs = 0;
+  bool quadratic = false;
+  std::vector<double> Phi, PhiS, A, H, B, c;   // Phi [nfree x r], PhiS [nsch x rs], A [r x r], ...
+};
+
+// Pointwise projection of one z-face: ELL rows over the face's npl nodes.
+struct FaceProj {
+  int src = -1;          // source subdomain
+  int width = 0;
+  std::vector<int> idx;  // [npl][width] source node ids
+  std::vector<double> wt;
+  int src_layer = 0;     // source-local node layer that coincides with the face
+};
+
+struct Subdomain {
+  osam_subdomain_desc desc{};
+  int nx = 0, ny = 0, nzs = 0, npl = 0;
+  long long nnodes = 0, cs = 0, is = 0, nfree_nodes = 0, nsch_nodes = 0, face_off_hi = 0;
+  int face_type[2] = {0, 0};    // geometry: clamped or Schwarz
+  FaceProj proj[2];
+  // FOM buffers
+  void *u[3] = {}, *v[2] = {}, *a[2] = {};
+  void *coef = nullptr;
+  int *bnd_cols = nullptr;
+  int n_int = 0, n_bnd = 0;
+  unsigned *counters = nullptr;
+  double *partials = nullptr;
+  int fe_block = 256, fe_kc = 8, fe_chunks = 1, fe_int_blocks = 0, fe_nblocks = 0, max_nblocks = 0;
+  // OpInf
+  bool rom = false;
+  int r = 0, rs = 0;
+  OpinfHost oh;
+  void *d_A = nullptr, *d_H = nullptr, *d_B = nullptr, *d_c = nullptr;   // row-major
+  void *d_Phi = nullptr;           // [r][nfree] column-major
+  void *q[2] = {}, *qd[2] = {}, *qdd[2] = {};
+  void *face_phis[2] = {};         // [rs][3 npl] Phi_S block per Schwarz face
+  void *face_tm[2] = {};           // [rs][r_src] for ROM sources
+  void *sface[2][3] = {};          // OpInf: pushed face values by role, [batch][3 npl] (FOM source)
+  std::vector<std::vector<double>> piphi_h;  // host copy per export
+  std::vector<void *> piphi_d;               // device copy per export
+  // records
+  osam_record rec{};
+};
+
+struct Ctx {
+  int device = 0;
+  int prec = OSAM_FP64;
+  int batch = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<std::unique_ptr<Subdomain>> sds;
+  Status *d_status = nullptr;
+  Status *h_status = nullptr;   // pinned mirror
+  std::vector<void *> allocs;
+  std::vector<char> initialized;
+  bool coupled = false;
+  bool wired = false;
+  std::string err;
+  double avg_iters = 3.0;
+  // scratch
+  double *d_scratch = nullptr;
+  size_t scratch_n = 0;
+
+  int32_t fail(int32_t code, const std::string &msg);
+  void dfree(void *p);
+  size_t esize() const;
+  void *alloc_t(size_t n, int32_t *st);
+  int32_t upload(void *dst, const double *src, size_t n);
+  int32_t download(double *dst, const void *src, size_t n);
+  double *scratch(size_t n, int32_t *st);
+
+  void choose_fe_launch(Subdomain &s, int block, int kc);
+  int32_t couple();
+  int32_t wire();
+  int32_t set_initial(int inst, const double *u0, const double *v0);
+  int32_t init_pending();
+  int32_t get_state(int sd, int inst, double *u, double *v, double *a);
+  int32_t install_opinf(int sd, const OpinfHost &oh);
+  int32_t sync_status();
+  int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info);
+  int32_t launch_round(const Opts &o);
+  int32_t launch_fe_sd(int sdi, const Opts &o, int mode);
+  int32_t launch_rom_sd(int sdi, const Opts &o);
+  int32_t learn(int sd, const osam_opinf_desc &d);
+};
+
+}  // namespace osam

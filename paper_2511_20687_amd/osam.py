@@ -1,0 +1,317 @@
+"""ctypes binding of libosam (include/osam.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+libosam.so.  Host arrays are numpy float64; device buffers (records,
+snapshots) are torch CUDA tensors passed by data pointer.  The library must
+have been built (``python -m paper_2511_20687_amd.build``); importing this
+module on a machine without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libosam.so")
+
+OSAM_OK, OSAM_E_INVALID, OSAM_E_OOM, OSAM_E_HIP = 0, -1, -2, -3
+OSAM_E_NONFINITE, OSAM_E_SINGULAR, OSAM_E_OUTSIDE, OSAM_E_ORDER = -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -4: "NONFINITE", -5: "SINGULAR",
+                -6: "OUTSIDE", -7: "ORDER"}
+EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_error",
+            "create_subdomain", "osam_couple", "osam_set_initial", "osam_get_state",
+            "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
+            "osam_get_opinf", "schwarz_step", "run", "osam_sync"]
+
+
+class OsamError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"osam error {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SubdomainDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("Lx", C.c_double), ("Ly", C.c_double), ("Lz", C.c_double),
+                ("z_lo", C.c_int32), ("z_hi", C.c_int32),
+                ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
+                ("clamp_ends", C.c_int32), ("dt", C.c_double), ("beta", C.c_double),
+                ("gamma", C.c_double)]
+
+
+class Record(C.Structure):
+    _fields_ = [("every", C.c_int64), ("n_cols", C.c_int64), ("u", C.c_void_p), ("a", C.c_void_p),
+                ("s", C.c_void_p)]
+
+
+class OpinfDesc(C.Structure):
+    _fields_ = [("form", C.c_int32), ("with_c", C.c_int32), ("r", C.c_int32), ("r_s", C.c_int32),
+                ("energy", C.c_double), ("energy_bnd", C.c_double), ("n_lambda", C.c_int32),
+                ("lambdas", C.POINTER(C.c_double)), ("n_traj", C.c_int32), ("T", C.c_int64),
+                ("U", C.c_void_p), ("Udd", C.c_void_p), ("S", C.c_void_p), ("V0", C.c_void_p),
+                ("sigma_out", C.POINTER(C.c_double)), ("E_lambda_out", C.POINTER(C.c_double)),
+                ("lambda_star_out", C.POINTER(C.c_double)), ("r_out", C.POINTER(C.c_int32)),
+                ("rs_out", C.POINTER(C.c_int32))]
+
+
+class SchwarzOpts(C.Structure):
+    _fields_ = [("tol_abs", C.c_double), ("tol_rel", C.c_double), ("min_iter", C.c_int32),
+                ("max_iter", C.c_int32), ("guess", C.c_int32)]
+
+
+class InstanceInfo(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("last_iters", C.c_int32), ("last_converged", C.c_int32),
+                ("abs2", C.c_double), ("den2", C.c_double), ("total_iters", C.c_int64),
+                ("max_iters", C.c_int32), ("unconverged", C.c_int64), ("status", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libosam.so (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2511_20687_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.osam_version.restype = i32
+    lib.osam_ctx_create.argtypes = [C.POINTER(vp), i32, i32, i32, vp]
+    lib.osam_ctx_create.restype = i32
+    lib.osam_ctx_destroy.argtypes = [vp]
+    lib.osam_ctx_destroy.restype = None
+    lib.osam_last_error.argtypes = [vp]
+    lib.osam_last_error.restype = C.c_char_p
+    lib.create_subdomain.argtypes = [vp, C.POINTER(SubdomainDesc), C.POINTER(i32)]
+    lib.create_subdomain.restype = i32
+    lib.osam_couple.argtypes = [vp]
+    lib.osam_couple.restype = i32
+    lib.osam_set_initial.argtypes = [vp, i32, dp, dp]
+    lib.osam_set_initial.restype = i32
+    lib.osam_get_state.argtypes = [vp, i32, i32, dp, dp, dp]
+    lib.osam_get_state.restype = i32
+    lib.osam_get_reduced.argtypes = [vp, i32, i32, dp, dp, dp]
+    lib.osam_get_reduced.restype = i32
+    lib.osam_sizes.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                               C.POINTER(i32), C.POINTER(i32)]
+    lib.osam_sizes.restype = i32
+    lib.osam_set_record.argtypes = [vp, i32, C.POINTER(Record)]
+    lib.osam_set_record.restype = i32
+    if hasattr(lib, "learn_opinf"):
+        lib.learn_opinf.argtypes = [vp, i32, C.POINTER(OpinfDesc)]
+        lib.learn_opinf.restype = i32
+    lib.osam_set_opinf.argtypes = [vp, i32, i32, i32, dp, dp, dp, dp, dp, dp]
+    lib.osam_set_opinf.restype = i32
+    lib.osam_get_opinf.argtypes = [vp, i32, dp, dp, dp, dp, dp, dp]
+    lib.osam_get_opinf.restype = i32
+    lib.schwarz_step.argtypes = [vp, C.POINTER(SchwarzOpts), C.POINTER(InstanceInfo)]
+    lib.schwarz_step.restype = i32
+    lib.run.argtypes = [vp, i64, C.POINTER(SchwarzOpts), C.POINTER(InstanceInfo)]
+    lib.run.restype = i32
+    lib.osam_sync.argtypes = [vp]
+    lib.osam_sync.restype = i32
+    _lib = lib
+    return lib
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _devptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+@dataclass
+class Options:
+    tol_abs: float = 1.0e-8
+    tol_rel: float = 1.0e-12
+    min_iter: int = 2
+    max_iter: int = 32
+    guess: int = 0          # 0 HOLD, 1 PREDICTOR
+
+    def c(self) -> SchwarzOpts:
+        return SchwarzOpts(self.tol_abs, self.tol_rel, self.min_iter, self.max_iter, self.guess)
+
+
+class Context:
+    """One libosam context: a batch of coupled-subdomain instances on one GPU."""
+
+    def __init__(self, device: int = 0, precision: str = "f64", batch: int = 1, stream=None):
+        self.lib = load_library()
+        self.precision = precision
+        self.batch = batch
+        h = C.c_void_p()
+        prec = {"f64": 0, "f32": 1}[precision]
+        st = self.lib.osam_ctx_create(C.byref(h), device, prec, batch,
+                                      None if stream is None else C.c_void_p(stream))
+        if st != OSAM_OK:
+            raise OsamError(st, "osam_ctx_create failed")
+        self.h = h
+        self.n_sd = 0
+
+    # -- helpers -----------------------------------------------------------
+    def _check(self, st: int):
+        if st != OSAM_OK:
+            raise OsamError(st, self.lib.osam_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.osam_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- set-up ------------------------------------------------------------
+    def create_subdomain(self, nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, dt,
+                         clamp_ends=True, beta=0.0, gamma=0.5) -> int:
+        d = SubdomainDesc(nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, int(clamp_ends), dt, beta,
+                          gamma)
+        sid = C.c_int32()
+        self._check(self.lib.create_subdomain(self.h, C.byref(d), C.byref(sid)))
+        self.n_sd += 1
+        return sid.value
+
+    def couple(self):
+        self._check(self.lib.osam_couple(self.h))
+
+    def sizes(self, sd: int) -> dict:
+        nn, nf, ns = C.c_int64(), C.c_int64(), C.c_int64()
+        r, rs = C.c_int32(), C.c_int32()
+        self._check(self.lib.osam_sizes(self.h, sd, C.byref(nn), C.byref(nf), C.byref(ns),
+                                        C.byref(r), C.byref(rs)))
+        return dict(n_nodes=nn.value, n_free=nf.value, n_sch=ns.value, r=r.value, r_s=rs.value)
+
+    def set_initial(self, inst: int, u0: np.ndarray, v0: np.ndarray):
+        u0, v0 = _f64(u0), _f64(v0)
+        self._check(self.lib.osam_set_initial(self.h, inst, _dptr(u0), _dptr(v0)))
+
+    def get_state(self, sd: int, inst: int = 0):
+        n = self.sizes(sd)["n_nodes"]
+        u, v, a = (np.zeros((3, n)) for _ in range(3))
+        self._check(self.lib.osam_get_state(self.h, sd, inst, _dptr(u), _dptr(v), _dptr(a)))
+        return u, v, a
+
+    def get_reduced(self, sd: int, inst: int = 0):
+        r = self.sizes(sd)["r"]
+        q, qd, qdd = (np.zeros(r) for _ in range(3))
+        self._check(self.lib.osam_get_reduced(self.h, sd, inst, _dptr(q), _dptr(qd), _dptr(qdd)))
+        return q, qd, qdd
+
+    def set_record(self, sd: int, every: int, n_cols: int, u=None, a=None, s=None):
+        """u, a, s: torch device tensors [batch][n_cols][len] in the context precision."""
+        self._keep = getattr(self, "_keep", {})
+        self._keep[sd] = (u, a, s)
+        rec = Record(every, n_cols, _devptr(u), _devptr(a), _devptr(s))
+        self._check(self.lib.osam_set_record(self.h, sd, C.byref(rec)))
+
+    def set_opinf(self, sd: int, Phi, PhiS, A, H=None, B=None, c=None):
+        Phi = np.asfortranarray(np.asarray(Phi, dtype=np.float64))
+        r = Phi.shape[1]
+        rs = 0 if PhiS is None else np.asarray(PhiS).shape[1]
+        PhiS_f = None if PhiS is None else np.asfortranarray(np.asarray(PhiS, dtype=np.float64))
+        A_f = np.asfortranarray(np.asarray(A, dtype=np.float64))
+        H_f = None if H is None else np.asfortranarray(np.asarray(H, dtype=np.float64))
+        B_f = None if B is None else np.asfortranarray(np.asarray(B, dtype=np.float64))
+        c_f = None if c is None else _f64(c)
+        p = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self.lib.osam_set_opinf(self.h, sd, r, rs, p(Phi), p(PhiS_f), p(A_f), p(H_f),
+                                            p(B_f), p(c_f)))
+
+    def get_opinf(self, sd: int, quadratic: bool = False, with_c: bool = False):
+        z = self.sizes(sd)
+        r, rs, nf, ns = z["r"], z["r_s"], z["n_free"], z["n_sch"]
+        Phi = np.zeros((nf, r), order="F")
+        PhiS = np.zeros((ns, rs), order="F")
+        A = np.zeros((r, r), order="F")
+        H = np.zeros((r, r * (r + 1) // 2), order="F") if quadratic else None
+        B = np.zeros((r, rs), order="F")
+        c = np.zeros(r) if with_c else None
+        p = lambda a: None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self.lib.osam_get_opinf(self.h, sd, p(Phi), p(PhiS), p(A), p(H), p(B), p(c)))
+        return dict(Phi=Phi, PhiS=PhiS, A=A, H=H, B=B, c=c)
+
+    def learn_opinf(self, sd: int, U, Udd, S, V0, n_traj: int, T: int, form: str = "linear",
+                    r: int = 0, r_s: int = 0, energy: float = 1 - 1e-6, energy_bnd: float = 1 - 1e-6,
+                    lambdas: Sequence[float] = (1e-10,), with_c: bool = False):
+        lam = _f64(list(lambdas))
+        z = self.sizes(sd)
+        nsig = min(z["n_free"], n_traj * T)
+        sig = np.zeros(nsig)
+        E = np.zeros(len(lam))
+        ls = C.c_double()
+        ro, rso = C.c_int32(), C.c_int32()
+        d = OpinfDesc(1 if form == "quadratic" else 0, int(with_c), r, r_s, energy, energy_bnd, len(lam),
+                      _dptr(lam), n_traj, T, _devptr(U), _devptr(Udd), _devptr(S), _devptr(V0),
+                      _dptr(sig), _dptr(E), C.pointer(ls), C.pointer(ro), C.pointer(rso))
+        self._check(self.lib.learn_opinf(self.h, sd, C.byref(d)))
+        return dict(sigma=sig, E_lambda=E, lambda_star=ls.value, r=ro.value, r_s=rso.value)
+
+    # -- time loop ---------------------------------------------------------
+    def _infos(self):
+        return (InstanceInfo * self.batch)()
+
+    @staticmethod
+    def _info_list(arr) -> List[dict]:
+        return [dict(steps=i.steps, last_iters=i.last_iters, last_converged=i.last_converged,
+                     abs2=i.abs2, den2=i.den2, total_iters=i.total_iters, max_iters=i.max_iters,
+                     unconverged=i.unconverged, status=i.status) for i in arr]
+
+    def schwarz_step(self, opts: Options = Options()) -> List[dict]:
+        info = self._infos()
+        o = opts.c()
+        self._check(self.lib.schwarz_step(self.h, C.byref(o), info))
+        return self._info_list(info)
+
+    def run(self, n_steps: int, opts: Options = Options(), check: bool = True) -> List[dict]:
+        info = self._infos()
+        o = opts.c()
+        st = self.lib.run(self.h, n_steps, C.byref(o), info)
+        if check:
+            self._check(st)
+        return self._info_list(info)
+
+    def sync(self):
+        self._check(self.lib.osam_sync(self.h))
+
+
+def free_dof_map(nx: int, ny: int, nzs: int) -> np.ndarray:
+    """Library free-DOF index [3][free nodes] of every (node, comp) free DOF in node-major
+    order (node ids i + (nx+1)(j + (ny+1) k), layers 1..nzs-1)."""
+    npl = (nx + 1) * (ny + 1)
+    nfn = npl * (nzs - 1)
+    nodes = np.arange(npl, npl * nzs)
+    out = np.empty((nodes.size, 3), dtype=np.int64)
+    for c in range(3):
+        out[:, c] = c * nfn + (nodes - npl)
+    return out.ravel()
+
+
+def add_bar_subdomains(ctx: Context, bar, layers, dt: float) -> List[int]:
+    """Create one FOM subdomain per node-layer range of a bar (inputs.Bar)."""
+    return [ctx.create_subdomain(bar.nx, bar.ny, bar.nz, bar.Lx, bar.Ly, bar.Lz, lo, hi, bar.E, bar.nu,
+                                 bar.rho, dt) for lo, hi in layers]

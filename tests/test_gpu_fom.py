@@ -1,0 +1,147 @@
+"""GPU parity of the FOM-FOM Schwarz path (libosam via the C ABI) against the FP64 oracle.
+
+Tolerances (relative space-time L2 of the displacement, Eq. mse): 1e-10 in FP64,
+1e-4 in FP32.
+"""
+import numpy as np
+import pytest
+
+from paper_2511_20687_amd.inputs import CFG1, Bar, Pulse, gaussian_pulse_u, slab_layers
+from oracle.schwarz import SchwarzOptions
+from tests._gpu import lib_free_index, lib_sch_index, oracle_fom_coupled, rel_err, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s=False):
+    import torch
+    from paper_2511_20687_amd import osam
+    ctx = osam.Context(0, precision, batch)
+    sds = osam.add_bar_subdomains(ctx, bar, layers, dt)
+    dev = torch.device("cuda:0")
+    recs = []
+    for sd in sds:
+        z = ctx.sizes(sd)
+        ru = torch.zeros((batch, n + 1, z["n_free"]), dtype=torch_dtype(precision), device=dev)
+        rs = torch.zeros((batch, n + 1, z["n_sch"]), dtype=torch_dtype(precision), device=dev) \
+            if record_s else None
+        ctx.set_record(sd, 1, n + 1, u=ru, s=rs)
+        recs.append((ru, rs))
+    for b in range(batch):
+        ctx.set_initial(b, u0[b] if isinstance(u0, list) else u0, v0[b] if isinstance(v0, list) else v0)
+    info = ctx.run(n, opts or osam.Options())
+    torch.cuda.synchronize()
+    return ctx, [(ru.cpu().numpy(), None if rs is None else rs.cpu().numpy()) for ru, rs in recs], info
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_cfg1_fom_fom_matches_oracle(precision, tol):
+    """Bar 4x4x40, two slabs with 20% overlap, 1000 explicit steps."""
+    w = CFG1
+    bar, dt, layers = w.bar, w.dt, w.layers
+    u0 = Pulse().u0(bar)
+    v0 = np.zeros_like(u0)
+    n = w.steps
+    print(f"[cfg1 {precision}] oracle", flush=True)
+    models, ref = oracle_fom_coupled(bar, layers, dt, u0, v0, n)
+    print(f"[cfg1 {precision}] gpu", flush=True)
+    ctx, recs, info = _lib_run(bar, layers, dt, u0, v0, n, precision)
+    for i, (lo, hi) in enumerate(layers):
+        got = recs[i][0][0][:, lib_free_index(bar, lo, hi)]
+        err = rel_err(got, ref["u"][i])
+        print(f"subdomain {i}: rel err {err:.3e}")
+        assert err <= tol
+    assert info[0]["steps"] == n
+    # iteration counts: FP64 reproduces the oracle's decisions exactly
+    if precision == "f64":
+        assert info[0]["total_iters"] == int(ref["iters"].sum())
+        assert info[0]["max_iters"] == int(ref["iters"].max())
+
+
+def test_three_slabs_and_schwarz_records_f64():
+    """Three subdomains (middle one with two Schwarz faces); records of the Schwarz data."""
+    bar = Bar(3, 2, 36)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 3)
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.4, 0.06)
+    v0 = np.zeros_like(u0)
+    v0[2] = 3.0 * np.exp(-((bar.node_z() - 0.7) ** 2) / (2 * 0.05 ** 2))
+    n = 200
+    models, ref = oracle_fom_coupled(bar, layers, dt, u0, v0, n, record=("u", "s"))
+    ctx, recs, info = _lib_run(bar, layers, dt, u0, v0, n, "f64", record_s=True)
+    for i, (lo, hi) in enumerate(layers):
+        assert rel_err(recs[i][0][0][:, lib_free_index(bar, lo, hi)], ref["u"][i]) <= 1e-10
+        assert rel_err(recs[i][1][0][:, lib_sch_index(bar, lo, hi)], ref["s"][i]) <= 1e-10
+    assert info[0]["total_iters"] == int(ref["iters"].sum())
+
+
+def test_predictor_guess_and_iteration_cap_f64():
+    from paper_2511_20687_amd import osam
+    bar = Bar(2, 2, 30)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.5, 0.05)
+    v0 = np.zeros_like(u0)
+    n = 60
+    _, ref = oracle_fom_coupled(bar, layers, dt, u0, v0, n, SchwarzOptions(guess="predictor"))
+    ctx, recs, info = _lib_run(bar, layers, dt, u0, v0, n, "f64", osam.Options(guess=1))
+    assert info[0]["total_iters"] == 2 * n
+    for i, (lo, hi) in enumerate(layers):
+        assert rel_err(recs[i][0][0][:, lib_free_index(bar, lo, hi)], ref["u"][i]) <= 1e-10
+    # unreachable tolerance: every step runs to the cap and is reported unconverged
+    ctx2, _, info2 = _lib_run(bar, layers, dt, u0, v0, 5, "f64",
+                              osam.Options(tol_abs=0.0, tol_rel=0.0, max_iter=4))
+    assert info2[0]["total_iters"] == 20 and info2[0]["unconverged"] == 5
+
+
+def test_batched_instances_match_unbatched_f32():
+    """Independent instances in one launch give bitwise the single-instance results."""
+    bar = Bar(6, 5, 48)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    pulses = [Pulse(1e-3, 0.3, 0.05), Pulse(2e-3, 0.2, 0.04), Pulse(0.7e-3, 0.35, 0.06)]
+    u0 = [p.u0(bar) for p in pulses]
+    v0 = [np.zeros_like(x) for x in u0]
+    n = 120
+    _, recs, info = _lib_run(bar, layers, dt, u0, v0, n, "f32", batch=3)
+    for b in range(3):
+        _, r1, _ = _lib_run(bar, layers, dt, u0[b], v0[b], n, "f32")
+        for i in range(2):
+            assert np.array_equal(recs[i][0][b], r1[i][0][0])
+
+
+def test_repeat_runs_are_bitwise_identical_f32():
+    bar = Bar(8, 8, 80)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    u0 = Pulse().u0(bar)
+    v0 = np.zeros_like(u0)
+    _, r1, _ = _lib_run(bar, layers, dt, u0, v0, 50, "f32")
+    _, r2, _ = _lib_run(bar, layers, dt, u0, v0, 50, "f32")
+    for i in range(2):
+        assert np.array_equal(r1[i][0], r2[i][0])
+
+
+def test_state_readback_and_nonfinite_detection_f64():
+    from paper_2511_20687_amd import osam
+    bar = Bar(2, 2, 20)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.5, 0.05)
+    v0 = np.zeros_like(u0)
+    models, ref = oracle_fom_coupled(bar, layers, dt, u0, v0, 10, record=("u",))
+    ctx, _, info = _lib_run(bar, layers, dt, u0, v0, 10, "f64")
+    st = ref["states"]
+    for i, m in enumerate(models):
+        u, v, a = ctx.get_state(i, 0)
+        assert rel_err(u.T.ravel(), st[i].u) <= 1e-12
+        assert rel_err(v.T.ravel()[m.free_dofs], st[i].v[m.free_dofs]) <= 1e-12
+        assert rel_err(a.T.ravel()[m.free_dofs], st[i].a[m.free_dofs]) <= 1e-12
+    # a NaN in the initial field is reported as OSAM_E_NONFINITE
+    bad = u0.copy()
+    bad[2, bad.shape[1] // 3] = np.nan
+    ctx2 = osam.Context(0, "f64", 1)
+    osam.add_bar_subdomains(ctx2, bar, layers, dt)
+    ctx2.set_initial(0, bad, v0)
+    info2 = ctx2.run(5, osam.Options(), check=False)
+    assert info2[0]["status"] == osam.OSAM_E_NONFINITE
