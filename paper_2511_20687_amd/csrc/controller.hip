@@ -177,22 +177,15 @@ int32_t Ctx::wire() {
         }
         if ((st = upload(d.face_phis[f], blk.data(), blk.size()))) return st;
         if (src.rom) {
-          // T = Phi_S,face^T (Pi Phi_src), [rs][r_src] row-major
-          if (src.oh.Phi.empty()) return fail(OSAM_E_INVALID, "source basis not available on host");
-          const FaceProj &P = d.proj[f];
-          const long long nfs = 3 * src.nfree_nodes;
+          // T = Phi_S,face^T (Pi Phi_src), [rs][r_src] row-major; Pi is the injection
+          std::vector<double> rows;
+          if ((st = phi_layer_rows(const_cast<Subdomain &>(src), d.proj[f].src_layer, rows))) return st;
           std::vector<double> tm((size_t)d.rs * src.r, 0.0);
-          for (int c = 0; c < 3; ++c)
-            for (int nid = 0; nid < d.npl; ++nid)
-              for (int w = 0; w < P.width; ++w) {
-                const double wt = P.wt[(size_t)nid * P.width + w];
-                if (wt == 0.0) continue;
-                const long long fn = P.idx[(size_t)nid * P.width + w] - src.npl;
-                for (int j = 0; j < src.r; ++j) {
-                  const double pv = wt * src.oh.Phi[(size_t)j * nfs + c * src.nfree_nodes + fn];
-                  for (int k = 0; k < d.rs; ++k) tm[(size_t)k * src.r + j] += blk[(size_t)k * n + c * d.npl + nid] * pv;
-                }
-              }
+          for (int j = 0; j < src.r; ++j)
+            for (int m = 0; m < n; ++m) {
+              const double pv = rows[(size_t)j * n + m];
+              for (int k = 0; k < d.rs; ++k) tm[(size_t)k * src.r + j] += blk[(size_t)k * n + m] * pv;
+            }
           if (!d.face_tm[f]) {
             d.face_tm[f] = alloc_t(tm.size(), &st);
             if (st) return fail(st, "oom");
@@ -215,20 +208,8 @@ int32_t Ctx::wire() {
       if (d.face_type[f] == kFaceClamped) continue;
       Subdomain &src = *sds[d.proj[f].src];
       if (!src.rom) continue;
-      const FaceProj &P = d.proj[f];
-      const int n = 3 * d.npl;
-      std::vector<double> pp((size_t)src.r * n, 0.0);
-      if (src.oh.Phi.empty()) return fail(OSAM_E_INVALID, "source basis not available on host");
-      const long long nfs = 3 * src.nfree_nodes;
-      for (int c = 0; c < 3; ++c)
-        for (int nid = 0; nid < d.npl; ++nid)
-          for (int w = 0; w < P.width; ++w) {
-            const double wt = P.wt[(size_t)nid * P.width + w];
-            if (wt == 0.0) continue;
-            const long long fn = P.idx[(size_t)nid * P.width + w] - src.npl;
-            for (int k = 0; k < src.r; ++k)
-              pp[(size_t)k * n + c * d.npl + nid] += wt * src.oh.Phi[(size_t)k * nfs + c * src.nfree_nodes + fn];
-          }
+      std::vector<double> pp;
+      if ((st = phi_layer_rows(src, d.proj[f].src_layer, pp))) return st;
       src.piphi_h.push_back(pp);
     }
   }
@@ -720,6 +701,51 @@ int32_t Ctx::get_state(int sdi, int inst, double *u, double *v, double *a) {
 }
 
 // ---------------------------------------------------------------------------
+// Rows of Phi on one free node layer (all 3 components): [r][3 npl], the rows
+// the pointwise projection (an injection) reads when lifting to a neighbour.
+int32_t Ctx::phi_layer_rows(Subdomain &s, int layer, std::vector<double> &out) {
+  const int n = 3 * s.npl;
+  const long long nf = 3 * s.nfree_nodes;
+  if (layer < 1 || layer > s.nzs - 1) return fail(OSAM_E_OUTSIDE, "projection reads a constrained layer");
+  out.assign((size_t)s.r * n, 0.0);
+  if (!s.oh.Phi.empty()) {
+    for (int k = 0; k < s.r; ++k)
+      for (int c = 0; c < 3; ++c)
+        for (int nid = 0; nid < s.npl; ++nid)
+          out[(size_t)k * n + c * s.npl + nid] =
+              s.oh.Phi[(size_t)k * nf + c * s.nfree_nodes + (size_t)(layer - 1) * s.npl + nid];
+    return OSAM_OK;
+  }
+  for (int k = 0; k < s.r; ++k)
+    for (int c = 0; c < 3; ++c) {
+      const size_t off = ((size_t)k * nf + c * s.nfree_nodes + (size_t)(layer - 1) * s.npl) * esize();
+      int32_t st = download(out.data() + (size_t)k * n + c * s.npl, (const char *)s.d_Phi + off, s.npl);
+      if (st) return st;
+    }
+  return OSAM_OK;
+}
+
+template <typename T>
+__global__ void convert_kernel(const double *in, T *out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+int32_t Ctx::install_opinf_device(int sdi, const OpinfHost &oh, const double *phi_dev) {
+  int32_t st = install_opinf(sdi, oh);
+  if (st) return st;
+  Subdomain &d = *sds[sdi];
+  const long long n = 3 * d.nfree_nodes * (long long)oh.r;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (prec == OSAM_FP64)
+    hipLaunchKernelGGL(convert_kernel<double>, dim3(blocks), dim3(256), 0, stream, phi_dev, (double *)d.d_Phi, n);
+  else
+    hipLaunchKernelGGL(convert_kernel<float>, dim3(blocks), dim3(256), 0, stream, phi_dev, (float *)d.d_Phi, n);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(stream));
+  return OSAM_OK;
+}
+
 int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
   Subdomain &d = *sds[sdi];
   int32_t st = OSAM_OK;
@@ -767,6 +793,7 @@ int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
   if (!oh.c.empty() && (st = upload(d.d_c, oh.c.data(), r))) return st;
   if (!oh.Phi.empty() && (st = upload(d.d_Phi, oh.Phi.data(), oh.Phi.size()))) return st;
   d.oh = oh;
+  d.rec = osam_record{};
   d.rom = true;
   d.r = r;
   d.rs = rs;

@@ -433,7 +433,14 @@ int32_t osam_get_opinf(osam_ctx *c, int32_t sdi, double *Phi, double *PhiS, doub
   Subdomain &s = *ctx->sds[sdi];
   if (!s.rom) return ctx->fail(OSAM_E_INVALID, "not an OpInf subdomain");
   const OpinfHost &o = s.oh;
-  if (Phi) std::copy(o.Phi.begin(), o.Phi.end(), Phi);
+  if (Phi) {
+    if (!o.Phi.empty()) {
+      std::copy(o.Phi.begin(), o.Phi.end(), Phi);
+    } else {
+      int32_t st = ctx->download(Phi, s.d_Phi, (size_t)3 * s.nfree_nodes * s.r);
+      if (st) return st;
+    }
+  }
   if (PhiS) std::copy(o.PhiS.begin(), o.PhiS.end(), PhiS);
   if (A) std::copy(o.A.begin(), o.A.end(), A);
   if (H && o.quadratic) std::copy(o.H.begin(), o.H.end(), H);

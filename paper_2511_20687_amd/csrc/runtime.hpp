@@ -92,6 +92,8 @@ struct Ctx {
   int32_t init_pending();
   int32_t get_state(int sd, int inst, double *u, double *v, double *a);
   int32_t install_opinf(int sd, const OpinfHost &oh);
+  int32_t install_opinf_device(int sd, const OpinfHost &oh, const double *phi_dev);
+  int32_t phi_layer_rows(Subdomain &s, int layer, std::vector<double> &out);
   int32_t sync_status();
   int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info);
   int32_t launch_round(const Opts &o);
