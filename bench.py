@@ -1,0 +1,278 @@
+"""Benchmark: coupled Schwarz steps/s of the FOM-OpInf hybrid on one MI355X.
+
+Workload (default): bar 24x24x240 hex8 (150,625 nodes), two z-slabs with 20%
+overlap; subdomain 1 FOM, subdomain 2 linear OpInf r = 40 learned from 2000
+snapshots of a FOM-FOM training run (seeded pulse), boundary basis by the
+1 - 1e-6 energy criterion, lambda by Alg. 3 over the 11-point grid; online run
+of 5000 controller steps, FP32 state, FP64 convergence sums.
+
+One benchmark step = one complete online coupled run (5000 controller steps of
+the multiplicative Schwarz loop).  value = controller steps per second.
+Learning and the training run are set-up (timed separately, reported).
+Also reported: the FOM-FOM run of the same bar on the same GPU, the accuracy of
+the hybrid against it (Eq. mse), FE DOF-updates/s, the FE kernel's achieved
+bandwidth vs the HBM peak, and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# FP32 algorithmic bytes per FE DOF-iteration-update of the explicit step kernel:
+# read P, V0, A0, V1(prev) and write V1, A1, P2 (7 x 4 B) on free DOFs.
+FE_BYTES_PER_DOF = 28.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_context(w, precision, batch=1):
+    from paper_2511_20687_amd import osam
+    ctx = osam.Context(0, precision, batch)
+    osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
+    return ctx
+
+
+def opts_for(w):
+    from paper_2511_20687_amd import osam
+    return osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter)
+
+
+def train_and_learn(w, pulse, precision):
+    """FOM-FOM training run recording subdomain 2 snapshots, then learn_opinf on it."""
+    import torch
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import Bar
+    ctx = build_context(w, precision)
+    rom_sd = w.models.index("opinf")
+    z = ctx.sizes(rom_sd)
+    T = w.train_steps
+    dt_ = torch.float32 if precision == "f32" else torch.float64
+    dev = "cuda:0"
+    U = torch.zeros((1, T, z["n_free"]), dtype=dt_, device=dev)
+    A = torch.zeros((1, T, z["n_free"]), dtype=dt_, device=dev)
+    S = torch.zeros((1, T, z["n_sch"]), dtype=dt_, device=dev)
+    ctx.set_record(rom_sd, 1, T, u=U, a=A, s=S)
+    u0 = pulse.u0(w.bar)
+    v0 = np.zeros_like(u0)
+    ctx.set_initial(0, u0, v0)
+    t0 = time.perf_counter()
+    ctx.run(T - 1, opts_for(w))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    lo, hi = w.layers[rom_sd]
+    npl = (w.bar.nx + 1) * (w.bar.ny + 1)
+    V0 = torch.tensor(v0[:, npl * (lo + 1):npl * hi].reshape(1, -1), dtype=dt_, device=dev)
+    from paper_2511_20687_amd.inputs import lambda_grid_values
+    t0 = time.perf_counter()
+    out = ctx.learn_opinf(rom_sd, U, A, S, V0, 1, T, form=w.form, r=w.r, r_s=0,
+                          energy_bnd=1 - 1e-6, lambdas=lambda_grid_values(11))
+    torch.cuda.synchronize()
+    t_learn = time.perf_counter() - t0
+    del U, A, S
+    return ctx, out, t_train, t_learn
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(every instance and subdomain runs on one device); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import CFG2, draw_pulses
+    w = CFG2
+    pulse = draw_pulses(w.seed, 1)[0]
+    n = w.steps
+    _log(f"workload {w.name}: pulse a={pulse.a:.4e} b={pulse.b:.4f} s={pulse.s}; dt={w.dt:.4e}")
+
+    # ---- set-up: training run + learning (untimed for the metric) ----
+    ctx, learned, t_train, t_learn = train_and_learn(w, pulse, w.precision)
+    _log(f"training run {w.train_steps - 1} steps: {t_train:.2f} s; learning: {t_learn:.2f} s; "
+         f"r={learned['r']} r_s={learned['r_s']} lambda*={learned['lambda_star']:.1e}")
+    opts = opts_for(w)
+    u0 = pulse.u0(w.bar)
+    v0 = np.zeros_like(u0)
+
+    # ---- timed region: K complete online FOM-OpInf runs ----
+    for i in range(args.warmup):
+        ctx.set_initial(0, u0, v0)
+        ctx.run(n, opts)
+        _log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    times, infos = [], []
+    for i in range(args.steps):
+        ctx.set_initial(0, u0, v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.run(n, opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        infos.append(info[0])
+        _log(f"step {i + 1}/{args.steps}: {times[-1] * 1e3:.1f} ms ({n / times[-1]:.0f} steps/s)")
+    total = sum(times)
+    value = args.steps * n / total
+    iters = infos[-1]["total_iters"]
+    z0 = ctx.sizes(0)
+    fe_dofs = z0["n_free"]
+    dof_updates_per_s = fe_dofs * iters / times[-1]
+
+    # ---- FE kernel timing with HIP events (same workload, extra pass) ----
+    ctx.set_initial(0, u0, v0)
+    ctx.set_timing(True)
+    ctx.run(n, opts)
+    fe_ms, fe_launches = ctx.get_timing(0)
+    rom_ms, rom_launches = ctx.get_timing(1)
+    ctx.set_timing(False)
+    fe_avg_us = 1e3 * fe_ms / max(fe_launches, 1)
+    fe_gbs = FE_BYTES_PER_DOF * fe_dofs / (fe_avg_us * 1e-6) / 1e9
+
+    # ---- accuracy vs FOM-FOM and FOM-FOM throughput on the same GPU ----
+    every = 10
+    ncol = n // every + 1
+    dev = "cuda:0"
+    recs = []
+    for sd in range(2):
+        z = ctx.sizes(sd)
+        length = z["n_free"] if sd == 0 else z["r"]
+        t = torch.zeros((1, ncol, length), dtype=torch.float32, device=dev)
+        ctx.set_record(sd, every, ncol, u=t)
+        recs.append(t)
+    ctx.set_initial(0, u0, v0)
+    ctx.run(n, opts)
+    Phi = torch.tensor(ctx.get_opinf(1)["Phi"], dtype=torch.float64, device=dev)
+    hyb = [recs[0][0].double(), (Phi @ recs[1][0].double().T).T]
+    del recs
+    ff = build_context(w, w.precision)
+    frec = []
+    for sd in range(2):
+        z = ff.sizes(sd)
+        t = torch.zeros((1, ncol, z["n_free"]), dtype=torch.float32, device=dev)
+        ff.set_record(sd, every, ncol, u=t)
+        frec.append(t)
+    ff.set_initial(0, u0, v0)
+    ff.run(n, opts)
+    errs = []
+    for sd in range(2):
+        ref = frec[sd][0].double()
+        errs.append(float(torch.linalg.norm(hyb[sd] - ref) / torch.linalg.norm(ref)))
+    del frec, hyb
+    ff2 = build_context(w, w.precision)
+    ff2.set_initial(0, u0, v0)
+    ff2.run(n, opts)      # warm-up
+    ff2.set_initial(0, u0, v0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    finfo = ff2.run(n, opts)
+    torch.cuda.synchronize()
+    t_ff = time.perf_counter() - t0
+    fom_fom_value = n / t_ff
+    _log(f"hybrid {value:.0f} steps/s, FOM-FOM {fom_fom_value:.0f} steps/s, errors {errs}")
+
+    # ---- CPU oracle on a bounded sample ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, pulse, args.cpu_steps, learned)
+
+    line = {
+        "metric": "coupled Schwarz steps/s (FOM-OpInf hybrid, <=1e-3 rel err target vs FOM-FOM)",
+        "value": value,
+        "unit": "controller steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 convergence sums)",
+        "data": "synthetic (seeded Gaussian pulse; operators learned on the GPU from a FOM-FOM run)",
+        "config": {"workload": w.name, "bar": "24x24x240 hex8, [0,0.1]^2x[0,1] m, E=1e9 nu=0.25 rho=1000",
+                   "subdomains": "z node layers 0-144 FOM, 96-240 linear OpInf", "r": learned["r"],
+                   "r_s": learned["r_s"], "lambda_star": learned["lambda_star"],
+                   "controller_steps_per_run": n, "dt": w.dt, "train_snapshots": w.train_steps,
+                   "parallelism": "single GPU"},
+        "schwarz_iters_per_step": iters / n,
+        "fom_fom_steps_per_s": fom_fom_value,
+        "speedup_vs_fom_fom": value / fom_fom_value,
+        "rel_err_vs_fom_fom": {"fom_subdomain": errs[0], "opinf_subdomain": errs[1]},
+        "fe_dof_updates_per_s": dof_updates_per_s,
+        "fe_kernel_avg_us": fe_avg_us,
+        "rom_kernel_avg_us": 1e3 * rom_ms / max(rom_launches, 1),
+        "train_run_s": t_train,
+        "learn_s": t_learn,
+        "roofline": {"bound": "hbm", "achieved": fe_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": fe_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "fe_kernel<float, step>", "bytes_per_dof": FE_BYTES_PER_DOF,
+                     "dofs_per_launch": fe_dofs},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(w, pulse, n_steps, learned):
+    """FP64 oracle, one thread, on the first n_steps controller steps of the same hybrid.
+
+    The oracle's ROM uses seeded synthetic operators of the learned sizes (the
+    per-step cost does not depend on their values)."""
+    from threadpoolctl import threadpool_limits
+    from oracle.newmark import FomModel, SubdomainGeometry
+    from oracle.rom import OpInfModel
+    from oracle.schwarz import Coupled, SchwarzOptions
+    from paper_2511_20687_amd.inputs import synthetic_rom
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        lo, hi = w.layers[0]
+        fom = FomModel(w.bar, lo, hi, w.dt, lateral_fix=w.lateral_fix)
+        g = SubdomainGeometry(w.bar, *w.layers[1], lateral_fix=w.lateral_fix)
+        R = synthetic_rom(7, g.n_free, g.n_sch, learned["r"], max(learned["r_s"], 1), w.dt)
+        rom = OpInfModel(g, R["Phi"], R["PhiS"], R["A"], None, R["B"], None, dt=w.dt)
+        cp = Coupled([fom, rom])
+        u0 = pulse.u0(w.bar)
+        st = cp.initial_states(u0, np.zeros_like(u0))
+        t_setup = time.perf_counter() - t0
+        opts = SchwarzOptions(tol_abs=w.tol_abs, tol_rel=w.tol_rel)
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(n_steps):
+            st, info = cp.step(st, opts)
+            its += info.iters
+        t = time.perf_counter() - t0
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n_steps / t, "unit": "controller steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_steps} controller steps of the same FOM-OpInf hybrid (FP64 numpy/scipy, "
+                      f"one thread; setup {t_setup:.1f} s excluded; {its / n_steps:.2f} Schwarz iterations/step)",
+            "cpu_model": cpu_model, "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

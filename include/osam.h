@@ -27,7 +27,9 @@
  *     A z-face at the bar's end (z_lo == 0 or z_hi == nz) is exterior: clamped
  *     when clamp_ends != 0, traction-free otherwise.  Any other z-face is a
  *     Schwarz (overlap) boundary whose values come from the neighbouring
- *     subdomain that contains it.  Lateral faces are traction-free.
+ *     subdomain that contains it.  Lateral faces (x = 0, Lx or y = 0, Ly) are
+ *     traction-free, or hold the displacement components selected by
+ *     lateral_fix at zero (the effectively-1D bar of Sec. 5.1 fixes x and y).
  *   - Vector fields on the host are float64 structure-of-arrays [3][n_nodes].
  *   - Free-DOF vectors (snapshots, records) use the library layout
  *     [3][free nodes], free nodes = layers z_lo+1 .. z_hi-1 in node order.
@@ -85,6 +87,9 @@ typedef struct {
   int32_t z_lo, z_hi;          /* node-layer range, 0 <= z_lo, z_lo+2 <= z_hi <= nz */
   double E, nu, rho;           /* Young's modulus, Poisson ratio, density   */
   int32_t clamp_ends;          /* exterior z-faces clamped (chi = 0)        */
+  int32_t lateral_fix;         /* components held at zero on lateral faces:
+                                  bit 0 = x, bit 1 = y, bit 2 = z (0 = traction-free);
+                                  the same value for every subdomain          */
   double dt;                   /* time step = controller step              */
   double beta, gamma;          /* Newmark parameters: 0, 0.5               */
 } osam_subdomain_desc;
@@ -202,6 +207,14 @@ int32_t schwarz_step(osam_ctx *ctx, const osam_schwarz_opts *opts, osam_instance
  * Returns OSAM_E_NONFINITE if any instance went non-finite (that instance stops
  * at its last finite step; the others complete).  info: [batch] or NULL. */
 int32_t run(osam_ctx *ctx, int64_t n_steps, const osam_schwarz_opts *opts, osam_instance_info *info);
+
+/* Kernel timing: with enable != 0, every Schwarz-step kernel launch of every
+ * subdomain is bracketed by HIP events on the context stream (adds a little host
+ * overhead; off by default).  Enabling (again) clears the accumulated times. */
+int32_t osam_set_timing(osam_ctx *ctx, int32_t enable);
+/* Device time (ms) summed over the timed launches of subdomain sd's step
+ * kernel and their number (synchronises the stream). */
+int32_t osam_get_timing(osam_ctx *ctx, int32_t sd, double *ms, int64_t *launches);
 
 /* Wait for all queued work of the context (host synchronisation). */
 int32_t osam_sync(osam_ctx *ctx);

@@ -12,8 +12,17 @@ and reduced Schwarz data S^ = Phi_S^T S (r_S x T), find
     at the snapshot times are used (for the explicit central-difference scheme at
     unit stride they equal the second difference quotient of U);
   * compressed quadratic columns q_i q_j, i <= j (width r(r+1)/2);
-  * lambda is absolute, one scalar for all blocks (Remark on per-operator
-    lambda: not used), no column scaling;
+  * lambda is one scalar for all blocks (Remark on per-operator lambda: not
+    used).  The paper fixes neither units nor a normalisation of the data, yet
+    its grid 10^-10..1 only regularises operators of order one: in SI units the
+    stiffness block alone is of order (c/h)^2 ~ 1e11 and every grid value
+    would force it to zero.  The fit is therefore posed in step-normalised
+    time tau = t/dt and amplitude-normalised coordinates q/alpha, s^/alpha,
+    alpha = the largest ||q_j||_2 over all training columns:
+        argmin || dt^2 Qdd/alpha - At Q/alpha - Ht (Q/alpha)^(2) - Bt S^/alpha - ct 1^T ||^2
+               + lambda ||[At Ht Bt ct]||^2,
+    and mapped back with A = At/dt^2, H = Ht/(dt^2 alpha), B = Bt/dt^2,
+    c = alpha ct/dt^2 (dt = 1, alpha = 1 is the raw fit); no centering;
   * when T < p the objective still has a unique minimiser (lambda > 0).
 The ridge problem is solved by its definition as an ordinary least-squares
 problem on the stacked system [D; sqrt(lambda) I] X = [Qdd^T; 0] (library SVD
@@ -81,14 +90,29 @@ def split_operators(X: np.ndarray, r: int, form: str, rS: int, with_c: bool) -> 
                      None if B is None else B.copy(), None if c is None else c.copy())
 
 
+def amplitude_scale(Qs: List[np.ndarray]) -> float:
+    """alpha: the largest column norm ||q_j||_2 over all training trajectories (1 if zero)."""
+    a = max(float(np.max(np.linalg.norm(Q, axis=0))) for Q in Qs)
+    return a if a > 0.0 else 1.0
+
+
 def fit(Qs: List[np.ndarray], Qdds: List[np.ndarray], Shats: List[Optional[np.ndarray]],
-        lam: float, form: str = "linear", with_c: bool = False) -> Operators:
-    D = np.vstack([data_matrix(Q, S, form, with_c) for Q, S in zip(Qs, Shats)])
-    R = np.hstack(Qdds).T
+        lam: float, form: str = "linear", with_c: bool = False, dt: float = 1.0,
+        alpha: float = 1.0) -> Operators:
+    """Ridge fit in the normalised variables (tau = t/dt, q/alpha), returned in physical units."""
+    Qn = [Q / alpha for Q in Qs]
+    Sn = [None if S is None else S / alpha for S in Shats]
+    D = np.vstack([data_matrix(Q, S, form, with_c) for Q, S in zip(Qn, Sn)])
+    R = np.hstack([dt * dt * Qdd / alpha for Qdd in Qdds]).T
     X = ridge(D, R, lam)
     r = Qs[0].shape[0]
     rS = 0 if Shats[0] is None else Shats[0].shape[0]
-    return split_operators(X, r, form, rS, with_c)
+    o = split_operators(X, r, form, rS, with_c)
+    dt2 = dt * dt
+    return Operators(o.A / dt2,
+                     None if o.H is None else o.H / (dt2 * alpha),
+                     None if o.B is None else o.B / dt2,
+                     None if o.c is None else o.c * alpha / dt2)
 
 
 def rollout_frozen(ops: Operators, q0, qd0, qdd0, Shat: Optional[np.ndarray], n_cols: int,
@@ -126,9 +150,10 @@ def select_lambda(trajs: List[dict], lambdas, form: str = "linear", with_c: bool
     Qs = [t["Q"] for t in trajs]
     Qdds = [t["Qdd"] for t in trajs]
     Shats = [t.get("Shat") for t in trajs]
+    alpha = amplitude_scale(Qs)
     E = np.zeros(len(lambdas))
     for li, lam in enumerate(lambdas):
-        ops = fit(Qs, Qdds, Shats, lam, form, with_c)
+        ops = fit(Qs, Qdds, Shats, lam, form, with_c, dt, alpha)
         errs = []
         for t in trajs:
             Qrom = rollout_frozen(ops, t["Q"][:, 0], t["Qd0"], t["Qdd"][:, 0], t.get("Shat"),
@@ -137,4 +162,4 @@ def select_lambda(trajs: List[dict], lambdas, form: str = "linear", with_c: bool
         E[li] = np.mean(errs)
     best = int(np.argmin(E))            # first minimiser = smallest lambda on ties
     lam_star = float(lambdas[best])
-    return lam_star, E, fit(Qs, Qdds, Shats, lam_star, form, with_c)
+    return lam_star, E, fit(Qs, Qdds, Shats, lam_star, form, with_c, dt, alpha)

@@ -280,10 +280,14 @@ int32_t Ctx::set_initial(int inst, const double *u0g, const double *v0g) {
       const bool face = kl == 0 || kl == d.nzs;
       for (int nid = 0; nid < d.npl; ++nid) {
         const long long gid = nid + nxp * nyp * (kl + d.desc.z_lo);
+        const int ix = nid % (int)nxp, iy = nid / (int)nxp;
+        const bool lateral = ix == 0 || ix == g0.nx || iy == 0 || iy == g0.ny;
         for (int c = 0; c < 3; ++c) {
           const size_t li = (size_t)c * d.cs + (size_t)kl * d.npl + nid;
-          u[li] = clamped ? 0.0 : u0g[c * ng + gid];
-          v[li] = face ? 0.0 : v0g[c * ng + gid];
+          // held lateral components are zero on free layers; Schwarz faces keep the IC
+          const bool held = !face && lateral && (d.desc.lateral_fix & (1 << c));
+          u[li] = clamped || held ? 0.0 : u0g[c * ng + gid];
+          v[li] = face || held ? 0.0 : v0g[c * ng + gid];
         }
       }
     }
@@ -573,10 +577,31 @@ int32_t Ctx::launch_rom_sd(int sdi, const Opts &o) {
   return OSAM_OK;
 }
 
+hipEvent_t Ctx::next_event() {
+  if (ev_next == ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev_pool.push_back(e);
+  }
+  return ev_pool[ev_next++];
+}
+
 int32_t Ctx::launch_round(const Opts &o) {
   for (size_t i = 0; i < sds.size(); ++i) {
+    int a = -1;
+    if (timing) {
+      a = (int)ev_next;
+      hipEvent_t e = next_event();
+      if (!e || hipEventRecord(e, stream) != hipSuccess) return fail(OSAM_E_HIP, "event record");
+    }
     int32_t st = sds[i]->rom ? launch_rom_sd((int)i, o) : launch_fe_sd((int)i, o, 0);
     if (st) return st;
+    if (timing) {
+      const int b = (int)ev_next;
+      hipEvent_t e = next_event();
+      if (!e || hipEventRecord(e, stream) != hipSuccess) return fail(OSAM_E_HIP, "event record");
+      ev_used.push_back({(int)i, {a, b}});
+    }
   }
   return OSAM_OK;
 }

@@ -17,8 +17,9 @@
 //  * One thread owns a node column (ix, iy) and marches up a chunk of z-layers
 //    with a rolling two-layer window: 27 loads per node, 150 non-zero FMAs per
 //    interior node (structural zeros of the isotropic stencil are skipped at
-//    compile time).  Interior columns and boundary columns run in separate
-//    workgroups, so interior waves read wave-uniform (scalar) coefficients.
+//    compile time).  Interior columns and the boundary columns (grouped by
+//    stencil case, padded to whole waves) run in separate workgroups, so every
+//    wave reads one coefficient block through scalar loads.
 //  * The displacement at t_k on free nodes is the Newmark predictor, which the
 //    previous step already produced (buffer P); an iteration reads P, V0, A0
 //    and the previous iterate's V1, and writes V1, A1 and the next predictor
@@ -112,9 +113,11 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   } else {
     if (t >= A.n_bnd) return;
     const int col = A.bnd_cols[t];
+    if (col < 0) return;   // padding of a case group
     ix = col % nxp;
     iy = col / nxp;
-    cse = (ix == 0 ? 0 : (ix == nx ? 2 : 1)) + 3 * (iy == 0 ? 0 : (iy == ny ? 2 : 1));
+    // every wave holds one case group: make the case (and the coefficient block) wave-uniform
+    cse = __builtin_amdgcn_readfirstlane((ix == 0 ? 0 : (ix == nx ? 2 : 1)) + 3 * (iy == 0 ? 0 : (iy == ny ? 2 : 1)));
   }
   const T *C = A.coef + cse * 234;
 

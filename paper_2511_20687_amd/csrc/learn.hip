@@ -36,6 +36,8 @@ hipError_t launch_potrf_diag(double *, long long, int, int, int *, hipStream_t);
 hipError_t launch_trsm_panel(double *, long long, int, int, int, const int *, hipStream_t);
 hipError_t launch_trsv_block(const double *, long long, int, int, double *, long long, int, int, hipStream_t);
 hipError_t launch_add_diag(double *, long long, int, double, hipStream_t);
+hipError_t launch_colnorm_max(const double *, int, long long, double *, hipStream_t);
+hipError_t launch_scale(double *, long long, double, double, hipStream_t);
 hipError_t launch_data_matrix(const double *, int, const double *, int, long long, int, int, double *, hipStream_t);
 hipError_t launch_jacobi_round(const double *, double *, const double *, double *, int, int, hipStream_t);
 hipError_t launch_offnorm(const double *, long long, double *, int, hipStream_t);
@@ -313,6 +315,22 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   L.gemm<double, T>(true, false, r, (int)Tt, N, 1.0, Phi, N, Udd, N, 0.0, Qdd, r);
   L.gemm<double, T>(true, false, r, ntraj, N, 1.0, Phi, N, V0, N, 0.0, Qd0, r);
   if (rs > 0) L.gemm<double, T>(true, false, rs, (int)Tt, NS, 1.0, PhiS, NS, S, NS, 0.0, Sh, rs);
+  // normalised variables of the fit: tau = t/dt, q/alpha, s^/alpha (Sec. 4.2.1 leaves
+  // the units open; the regularisation grid of Sec. 5 presumes operators of order one)
+  const double dt = sd.desc.dt, dt2 = dt * dt;
+  double *amax = L.alloc(1);
+  if (L.code) return ctx->fail(L.code, L.err);
+  L.ok(launch_colnorm_max(Q, r, Tt, amax, L.s), "alpha");
+  double alpha = L.down(amax, 1)[0];
+  if (L.code) return ctx->fail(L.code, L.err);
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) {
+    if (!std::isfinite(alpha)) return ctx->fail(OSAM_E_NONFINITE, "non-finite training snapshots");
+    alpha = 1.0;
+  }
+  L.ok(launch_scale(Q, (long long)r * Tt, 1.0, alpha, L.s), "scale");
+  L.ok(launch_scale(Qdd, (long long)r * Tt, dt2, alpha, L.s), "scale");
+  L.ok(launch_scale(Qd0, (long long)r * ntraj, dt, alpha, L.s), "scale");
+  if (rs > 0) L.ok(launch_scale(Sh, (long long)rs * Tt, 1.0, alpha, L.s), "scale");
   double *D = L.alloc((size_t)Tt * p);
   if (L.code) return ctx->fail(L.code, L.err);
   L.ok(launch_data_matrix(Q, r, Sh, rs, Tt, quad, with_c, D, L.s), "data matrix");
@@ -367,7 +385,7 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   if (nlam > 1) {
     double *ro = L.alloc((size_t)nlam * ntraj * 5);
     if (L.code) return ctx->fail(L.code, L.err);
-    L.ok(launch_rollout(Xall, p, r, r2, rs, with_c, Q, Qd0, Qdd, Sh, Tn, ntraj, nlam, sd.desc.dt, ro, L.s),
+    L.ok(launch_rollout(Xall, p, r, r2, rs, with_c, Q, Qd0, Qdd, Sh, Tn, ntraj, nlam, 1.0, ro, L.s),
          "rollout");
     std::vector<double> h = L.down(ro, (size_t)nlam * ntraj * 5);
     if (L.code) return ctx->fail(L.code, L.err);
@@ -389,7 +407,7 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   }
   if (!spd_ok[best]) return ctx->fail(OSAM_E_SINGULAR, "no regularisation parameter gives an SPD system");
 
-  // 5. operators of lambda* (the fit at lambda* is the refit of Alg. 3)
+  // 5. operators of lambda* (the fit at lambda* is the refit of Alg. 3), in physical units
   std::vector<double> X = L.down(Xall + (size_t)best * p * r, (size_t)p * r);
   OpinfHost oh;
   oh.r = r;
@@ -397,21 +415,21 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   oh.quadratic = quad != 0;
   oh.A.assign((size_t)r * r, 0.0);
   for (int i = 0; i < r; ++i)
-    for (int j = 0; j < r; ++j) oh.A[(size_t)i + (size_t)j * r] = X[(size_t)j + (size_t)i * p];
+    for (int j = 0; j < r; ++j) oh.A[(size_t)i + (size_t)j * r] = X[(size_t)j + (size_t)i * p] / dt2;
   if (quad) {
     oh.H.assign((size_t)r * r2, 0.0);
     for (int i = 0; i < r; ++i)
-      for (int m = 0; m < r2; ++m) oh.H[(size_t)i + (size_t)m * r] = X[(size_t)(r + m) + (size_t)i * p];
+      for (int m = 0; m < r2; ++m) oh.H[(size_t)i + (size_t)m * r] = X[(size_t)(r + m) + (size_t)i * p] / (dt2 * alpha);
   }
   if (rs > 0) {
     oh.B.assign((size_t)r * rs, 0.0);
     for (int i = 0; i < r; ++i)
-      for (int l2 = 0; l2 < rs; ++l2) oh.B[(size_t)i + (size_t)l2 * r] = X[(size_t)(r + r2 + l2) + (size_t)i * p];
+      for (int l2 = 0; l2 < rs; ++l2) oh.B[(size_t)i + (size_t)l2 * r] = X[(size_t)(r + r2 + l2) + (size_t)i * p] / dt2;
     oh.PhiS = L.down(PhiS, (size_t)NS * rs);
   }
   if (with_c) {
     oh.c.assign(r, 0.0);
-    for (int i = 0; i < r; ++i) oh.c[i] = X[(size_t)(p - 1) + (size_t)i * p];
+    for (int i = 0; i < r; ++i) oh.c[i] = X[(size_t)(p - 1) + (size_t)i * p] * alpha / dt2;
   }
   if (L.code) return ctx->fail(L.code, L.err);
   int32_t st = ctx->install_opinf_device(sdi, oh, Phi);

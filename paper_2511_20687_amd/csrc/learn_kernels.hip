@@ -608,6 +608,43 @@ hipError_t launch_add_diag(double *A, long long lda, int n, double v, hipStream_
 }
 
 // ---------------------------------------------------------------------------
+// Normalisation of the least-squares data: alpha = max_t ||Q[:, t]||_2 (one
+// workgroup, columns strided over its threads), then x <- (mul * x) / div.
+__global__ void __launch_bounds__(1024) colnorm_max_kernel(const double *Q, int r, long long T, double *out) {
+  __shared__ double red[1024];
+  double m = 0.0;
+  for (long long t = threadIdx.x; t < T; t += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < r; ++i) {
+      const double q = Q[i + t * r];
+      s += q * q;
+    }
+    m = fmax(m, s);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+hipError_t launch_colnorm_max(const double *Q, int r, long long T, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(colnorm_max_kernel, dim3(1), dim3(1024), 0, s, Q, r, T, out);
+  return hipGetLastError();
+}
+
+__global__ void scale_kernel(double *x, long long n, double mul, double div) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (mul * x[i]) / div;
+}
+hipError_t launch_scale(double *x, long long n, double mul, double div, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, mul, div);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Data matrix of Eq. opinf_schwarz_inference, D (T x p, column-major):
 // columns [q_i | q_i q_j (i<=j, row by row) | s^_l | 1].
 __global__ void data_matrix_kernel(const double *Q, int r, const double *Sh, int rs, long long T, int quad,

@@ -25,7 +25,7 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) rom_kernel(RomArgs<T> A) {
+__global__ void __launch_bounds__(1024) rom_kernel(RomArgs<T> A) {
   const int b = blockIdx.x;
   Status *stp = A.status + b;
   if (stp->flags & kFinished) return;
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) rom_kernel(RomArgs<T> A) {
   T *qdd1s = q1s + r;
   T *sh = qdd1s + r;
   T *k2 = sh + (rs > 0 ? rs : 1);
-  __shared__ double red[8][16];
+  __shared__ double red[2][16];
 
   const T *q0 = A.q[s2] + (long long)b * r;
   const T *qd0 = A.qd[s2] + (long long)b * r;
@@ -59,30 +59,23 @@ __global__ void __launch_bounds__(256) rom_kernel(RomArgs<T> A) {
     const RomFaceIn<T> &f = A.fin[fi];
     const bool hold = n_iter == 1 && f.src_sd > A.sd && A.opts.guess == 0;
     if (f.type == kFaceFom) {
+      // g^_k += sum_m Phi_S[m, k] s_m : one wave per mode k, lanes over the face DOFs
       const T *src = f.sface[hold ? (int)(step % 3) : (int)((step + 1) % 3)] + (long long)b * f.n;
-      for (int k0 = 0; k0 < rs; k0 += 8) {
-        double acc[8];
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) acc[kk] = 0.0;
-        for (int m = tid; m < f.n; m += bs) {
-          const T s = src[m];
-#pragma unroll
-          for (int kk = 0; kk < 8; ++kk)
-            if (k0 + kk < rs) acc[kk] += (double)(f.phis[(long long)(k0 + kk) * f.n + m] * s);
+      for (int k = wid; k < rs; k += nw) {
+        const T *ph = f.phis + (long long)k * f.n;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+        int m = lane;
+        for (; m + 192 < f.n; m += 256) {
+          v0 += (double)(ph[m] * src[m]);
+          v1 += (double)(ph[m + 64] * src[m + 64]);
+          v2 += (double)(ph[m + 128] * src[m + 128]);
+          v3 += (double)(ph[m + 192] * src[m + 192]);
         }
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-          const double v = wave_sum_d(acc[kk]);
-          if (lane == 0) red[kk][wid] = v;
-        }
-        __syncthreads();
-        if (tid < 8 && k0 + tid < rs) {
-          double v = 0.0;
-          for (int i = 0; i < nw; ++i) v += red[tid][i];
-          sh[k0 + tid] += (T)v;
-        }
-        __syncthreads();
+        for (; m < f.n; m += 64) v0 += (double)(ph[m] * src[m]);
+        const double v = wave_sum_d((v0 + v1) + (v2 + v3));
+        if (lane == 0) sh[k] += (T)v;
       }
+      __syncthreads();
     } else {
       const T *qs = f.src_q[hold ? s2 : 1 - s2] + (long long)b * f.src_r;
       for (int k = wid; k < rs; k += nw) {
@@ -196,7 +189,7 @@ template <typename T>
 hipError_t launch_rom(const RomArgs<T> &A, int batch, hipStream_t s) {
   const size_t smem = rom_smem_bytes<T>(A.r, A.rs, A.r2);
   if (smem > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rom_kernel<T>, dim3(batch), dim3(256), smem, s, A);
+  hipLaunchKernelGGL(rom_kernel<T>, dim3(batch), dim3(1024), smem, s, A);
   return hipGetLastError();
 }
 template hipError_t launch_rom<float>(const RomArgs<float> &, int, hipStream_t);

@@ -247,6 +247,7 @@ void osam_ctx_destroy(osam_ctx *c) {
   for (void *p : ctx->allocs) hipFree(p);
   ctx->allocs.clear();
   if (ctx->h_status) hipHostFree(ctx->h_status);
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -272,12 +273,15 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   const bool ext_lo = d->z_lo == 0, ext_hi = d->z_hi == d->nz;
   if ((ext_lo || ext_hi) && !d->clamp_ends)
     return ctx->fail(OSAM_E_INVALID, "traction-free exterior z-faces are not supported (clamp_ends = 1)");
+  if (d->lateral_fix < 0 || d->lateral_fix > 7) return ctx->fail(OSAM_E_INVALID, "lateral_fix must be in 0..7");
   if (!ctx->sds.empty()) {
     const auto &d0 = ctx->sds[0]->desc;
     if (d0.nx != d->nx || d0.ny != d->ny || d0.nz != d->nz || d0.Lx != d->Lx || d0.Ly != d->Ly ||
         d0.Lz != d->Lz || d0.dt != d->dt)
       return ctx->fail(OSAM_E_INVALID,
                        "all subdomains must share the global grid and time step in this version");
+    if (d0.lateral_fix != d->lateral_fix)
+      return ctx->fail(OSAM_E_INVALID, "all subdomains must share the lateral boundary condition");
   }
   auto sd = std::make_unique<Subdomain>();
   sd->desc = *d;
@@ -307,16 +311,35 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
         if (interior_zero_h(d27, p, q) && std::fabs(C[(4 * 26 + d26) * 9 + p * 3 + q]) > 1e-12 * cmax)
           return ctx->fail(OSAM_E_INVALID, "interior stencil lacks the expected mirror symmetry");
   }
+  // lateral Dirichlet components: zero rows of every lateral case, so the
+  // acceleration of a held component is exactly zero (u, v start at zero)
+  for (int cse = 0; cse < 9; ++cse) {
+    if (cse == 4) continue;
+    for (int p = 0; p < 3; ++p) {
+      if (!(d->lateral_fix & (1 << p))) continue;
+      for (int d26 = 0; d26 < 26; ++d26)
+        for (int q = 0; q < 3; ++q) C[(cse * 26 + d26) * 9 + p * 3 + q] = 0.0;
+    }
+  }
   int32_t st = OSAM_OK;
   sd->coef = ctx->alloc_t(C.size(), &st);
   if (st) return ctx->fail(st, "out of device memory");
   if ((st = ctx->upload(sd->coef, C.data(), C.size()))) return st;
   // state buffers are allocated when the coupling is wired (FOM subdomains only)
-  // boundary column list
+  // boundary columns grouped by stencil case, every group padded to whole waves
+  // (entries -1), so all lanes of a wave share one coefficient block
   std::vector<int> bnd;
-  for (int iy = 0; iy <= d->ny; ++iy)
-    for (int ix = 0; ix <= d->nx; ++ix)
-      if (ix == 0 || ix == d->nx || iy == 0 || iy == d->ny) bnd.push_back(ix + (d->nx + 1) * iy);
+  for (int cse = 0; cse < 9; ++cse) {
+    if (cse == 4) continue;
+    const size_t start = bnd.size();
+    for (int iy = 0; iy <= d->ny; ++iy)
+      for (int ix = 0; ix <= d->nx; ++ix) {
+        const int cx = ix == 0 ? 0 : (ix == d->nx ? 2 : 1), cy = iy == 0 ? 0 : (iy == d->ny ? 2 : 1);
+        if (cx + 3 * cy == cse) bnd.push_back(ix + (d->nx + 1) * iy);
+      }
+    if (bnd.size() > start)
+      while (bnd.size() % 64) bnd.push_back(-1);
+  }
   sd->n_bnd = (int)bnd.size();
   sd->n_int = (d->nx - 1) * (d->ny - 1);
   sd->bnd_cols = dalloc<int>(ctx, bnd.size(), &st);
@@ -416,6 +439,17 @@ int32_t osam_set_opinf(osam_ctx *c, int32_t sdi, int32_t r, int32_t r_s, const d
   oh.quadratic = H != nullptr;
   const long long nf = 3 * s.nfree_nodes, ns = 3 * s.nsch_nodes;
   oh.Phi.assign(Phi, Phi + (size_t)nf * r);
+  // rows of lateral components held at zero carry no displacement
+  if (s.desc.lateral_fix) {
+    const int nxp = s.desc.nx + 1;
+    for (long long fn = 0; fn < s.nfree_nodes; ++fn) {
+      const int nid = (int)(fn % s.npl), ix = nid % nxp, iy = nid / nxp;
+      if (!(ix == 0 || ix == s.desc.nx || iy == 0 || iy == s.desc.ny)) continue;
+      for (int cc = 0; cc < 3; ++cc)
+        if (s.desc.lateral_fix & (1 << cc))
+          for (int k = 0; k < r; ++k) oh.Phi[(size_t)(cc * s.nfree_nodes + fn) + (size_t)k * nf] = 0.0;
+    }
+  }
   if (r_s > 0) oh.PhiS.assign(PhiS, PhiS + (size_t)ns * r_s);
   // column-major [r x r] -> keep column-major on host; kernels take row-major
   oh.A.assign(A, A + (size_t)r * r);
@@ -458,6 +492,35 @@ int32_t run(osam_ctx *c, int64_t n_steps, const osam_schwarz_opts *opts, osam_in
   Ctx *ctx = reinterpret_cast<Ctx *>(c);
   ctx->err.clear();
   return ctx->run(n_steps, *opts, info);
+}
+
+int32_t osam_set_timing(osam_ctx *c, int32_t enable) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->timing = enable != 0;
+  ctx->ev_used.clear();
+  ctx->ev_next = 0;
+  return OSAM_OK;
+}
+
+int32_t osam_get_timing(osam_ctx *c, int32_t sd, double *ms, int64_t *launches) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  if (sd < 0 || sd >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto &u : ctx->ev_used) {
+    if (u.first != sd) continue;
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, ctx->ev_pool[u.second.first], ctx->ev_pool[u.second.second]));
+    tot += t;
+    ++n;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = n;
+  return OSAM_OK;
 }
 
 int32_t osam_sync(osam_ctx *c) {

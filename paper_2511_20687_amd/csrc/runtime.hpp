@@ -73,6 +73,11 @@ struct Ctx {
   bool wired = false;
   std::string err;
   double avg_iters = 3.0;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<int, int>>> ev_used;   // (sd, (start idx, stop idx))
+  size_t ev_next = 0;
   // scratch
   double *d_scratch = nullptr;
   size_t scratch_n = 0;
@@ -97,6 +102,7 @@ struct Ctx {
   int32_t sync_status();
   int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info);
   int32_t launch_round(const Opts &o);
+  hipEvent_t next_event();
   int32_t launch_fe_sd(int sdi, const Opts &o, int mode);
   int32_t launch_rom_sd(int sdi, const Opts &o);
   int32_t learn(int sd, const osam_opinf_desc &d);

@@ -209,6 +209,9 @@ class Workload:
     tol_rel: float = 1.0e-12
     min_iter: int = 2
     max_iter: int = 32
+    # displacement components held at zero on the lateral faces: x and y, as for
+    # the effectively-1D bar of Sec. 5.1 (empty = traction-free lateral faces)
+    lateral_fix: Tuple[int, ...] = (0, 1)
 
     @property
     def layers(self) -> List[Tuple[int, int]]:
@@ -260,3 +263,24 @@ def random_normal(seed: int, shape, scale: float = 1.0) -> np.ndarray:
     g = SplitMix64(seed)
     rng = np.random.Generator(np.random.PCG64(g.next_u64()))
     return scale * rng.standard_normal(size=shape)
+
+
+def lambda_grid_values(n: int = 11) -> list:
+    """Candidate regularisation parameters of Sec. 5: 10^(-10 + 10 (j-1)/(n-1)), j = 1..n."""
+    if n == 1:
+        return [1e-10]
+    return [10.0 ** (-10.0 + 10.0 * j / (n - 1)) for j in range(n)]
+
+
+def synthetic_rom(seed, n_free, n_sch, r, rs, dt, quadratic=False, with_c=False, scale_b=1.0):
+    """Seeded synthetic OpInf data for parity cases and CPU timing: orthonormal Phi,
+    Phi_S; A = -V diag(w^2) V^T with w dt <= 0.9 (a stable explicit step); small B, H, c."""
+    Phi, _ = np.linalg.qr(random_normal(seed, (n_free, r)))
+    PhiS = np.linalg.qr(random_normal(seed + 1, (n_sch, rs)))[0] if rs else None
+    Vm, _ = np.linalg.qr(random_normal(seed + 2, (r, r)))
+    w2 = (np.linspace(0.05, 0.9, r) / dt) ** 2
+    A = -(Vm * w2) @ Vm.T
+    B = scale_b * (1.0 / dt) ** 2 * 0.01 * random_normal(seed + 3, (r, rs)) if rs else None
+    H = 1e-3 * (1.0 / dt) ** 2 * random_normal(seed + 4, (r, r * (r + 1) // 2)) if quadratic else None
+    c = 1e-6 * (1.0 / dt) ** 2 * random_normal(seed + 5, (r,)) if with_c else None
+    return dict(Phi=Phi, PhiS=PhiS, A=A, B=B, H=H, c=c)

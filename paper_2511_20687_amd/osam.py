@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "OOM", -3: "HIP", -4: "NONFINITE", -
 EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_error",
             "create_subdomain", "osam_couple", "osam_set_initial", "osam_get_state",
             "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
-            "osam_get_opinf", "schwarz_step", "run", "osam_sync"]
+            "osam_get_opinf", "schwarz_step", "run", "osam_set_timing", "osam_get_timing",
+            "osam_sync"]
 
 
 class OsamError(RuntimeError):
@@ -39,8 +40,8 @@ class SubdomainDesc(C.Structure):
                 ("Lx", C.c_double), ("Ly", C.c_double), ("Lz", C.c_double),
                 ("z_lo", C.c_int32), ("z_hi", C.c_int32),
                 ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
-                ("clamp_ends", C.c_int32), ("dt", C.c_double), ("beta", C.c_double),
-                ("gamma", C.c_double)]
+                ("clamp_ends", C.c_int32), ("lateral_fix", C.c_int32), ("dt", C.c_double),
+                ("beta", C.c_double), ("gamma", C.c_double)]
 
 
 class Record(C.Structure):
@@ -114,6 +115,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.schwarz_step.restype = i32
     lib.run.argtypes = [vp, i64, C.POINTER(SchwarzOpts), C.POINTER(InstanceInfo)]
     lib.run.restype = i32
+    lib.osam_set_timing.argtypes = [vp, i32]
+    lib.osam_set_timing.restype = i32
+    lib.osam_get_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64)]
+    lib.osam_get_timing.restype = i32
     lib.osam_sync.argtypes = [vp]
     lib.osam_sync.restype = i32
     _lib = lib
@@ -188,9 +193,13 @@ class Context:
 
     # -- set-up ------------------------------------------------------------
     def create_subdomain(self, nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, dt,
-                         clamp_ends=True, beta=0.0, gamma=0.5) -> int:
-        d = SubdomainDesc(nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, int(clamp_ends), dt, beta,
-                          gamma)
+                         clamp_ends=True, beta=0.0, gamma=0.5, lateral_fix=()) -> int:
+        """lateral_fix: components (0 = x, 1 = y, 2 = z) held at zero on the lateral faces."""
+        mask = 0
+        for c in lateral_fix:
+            mask |= 1 << int(c)
+        d = SubdomainDesc(nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, int(clamp_ends), mask, dt,
+                          beta, gamma)
         sid = C.c_int32()
         self._check(self.lib.create_subdomain(self.h, C.byref(d), C.byref(sid)))
         self.n_sd += 1
@@ -295,6 +304,14 @@ class Context:
             self._check(st)
         return self._info_list(info)
 
+    def set_timing(self, enable: bool):
+        self._check(self.lib.osam_set_timing(self.h, int(enable)))
+
+    def get_timing(self, sd: int):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self.lib.osam_get_timing(self.h, sd, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
     def sync(self):
         self._check(self.lib.osam_sync(self.h))
 
@@ -311,7 +328,17 @@ def free_dof_map(nx: int, ny: int, nzs: int) -> np.ndarray:
     return out.ravel()
 
 
-def add_bar_subdomains(ctx: Context, bar, layers, dt: float) -> List[int]:
+def add_bar_subdomains(ctx: Context, bar, layers, dt: float, lateral_fix=()) -> List[int]:
     """Create one FOM subdomain per node-layer range of a bar (inputs.Bar)."""
     return [ctx.create_subdomain(bar.nx, bar.ny, bar.nz, bar.Lx, bar.Ly, bar.Lz, lo, hi, bar.E, bar.nu,
-                                 bar.rho, dt) for lo, hi in layers]
+                                 bar.rho, dt, lateral_fix=lateral_fix) for lo, hi in layers]
+
+
+def lib_dof_index(nx: int, ny: int, nzs: int, dofs: np.ndarray) -> np.ndarray:
+    """Library free-DOF index [3][free nodes] of node-major DOF ids 3*node + c (node in
+    layers 1..nzs-1 of the subdomain)."""
+    dofs = np.asarray(dofs, dtype=np.int64)
+    npl = (nx + 1) * (ny + 1)
+    nfn = npl * (nzs - 1)
+    node, comp = dofs // 3, dofs % 3
+    return comp * nfn + (node - npl)

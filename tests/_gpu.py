@@ -7,8 +7,8 @@ from oracle.newmark import FomModel
 from oracle.schwarz import Coupled, SchwarzOptions
 
 
-def oracle_fom_coupled(bar: Bar, layers, dt, u0, v0, n_steps, opts=None, record=("u",)):
-    models = [FomModel(bar, lo, hi, dt) for lo, hi in layers]
+def oracle_fom_coupled(bar: Bar, layers, dt, u0, v0, n_steps, opts=None, record=("u",), lateral_fix=()):
+    models = [FomModel(bar, lo, hi, dt, lateral_fix=lateral_fix) for lo, hi in layers]
     out = Coupled(models).run(u0, v0, n_steps, opts or SchwarzOptions(), record=record)
     return models, out
 
@@ -18,6 +18,13 @@ def lib_free_index(bar: Bar, lo: int, hi: int) -> np.ndarray:
     free-DOF vector [3][free nodes] (free nodes = layers 1..nzs-1)."""
     from paper_2511_20687_amd.osam import free_dof_map
     return free_dof_map(bar.nx, bar.ny, hi - lo)
+
+
+def lib_index_of(model) -> np.ndarray:
+    """Library free-DOF index of each oracle free DOF of ``model`` (any lateral condition)."""
+    from paper_2511_20687_amd.osam import lib_dof_index
+    bar = model.bar
+    return lib_dof_index(bar.nx, bar.ny, model.z_hi - model.z_lo, model.free_dofs)
 
 
 def lib_sch_index(bar: Bar, lo: int, hi: int) -> np.ndarray:
@@ -56,16 +63,4 @@ def restrict_free_lib(field_global, bar: Bar, lo: int, hi: int) -> np.ndarray:
     return np.asarray(field_global)[:, gids].reshape(-1)
 
 
-def synthetic_rom(seed, n_free, n_sch, r, rs, dt, quadratic=False, with_c=False, scale_b=1.0):
-    """Seeded synthetic OpInf data: orthonormal Phi, Phi_S; A = -V diag(w^2) V^T with
-    w dt <= 1 (stable explicit Newmark); small B, H, c."""
-    from paper_2511_20687_amd.inputs import random_normal
-    Phi, _ = np.linalg.qr(random_normal(seed, (n_free, r)))
-    PhiS = np.linalg.qr(random_normal(seed + 1, (n_sch, rs)))[0] if rs else None
-    Vm, _ = np.linalg.qr(random_normal(seed + 2, (r, r)))
-    w2 = (np.linspace(0.05, 0.9, r) / dt) ** 2
-    A = -(Vm * w2) @ Vm.T
-    B = scale_b * (1.0 / dt) ** 2 * 0.01 * random_normal(seed + 3, (r, rs)) if rs else None
-    H = 1e-3 * (1.0 / dt) ** 2 * random_normal(seed + 4, (r, r * (r + 1) // 2)) if quadratic else None
-    c = 1e-6 * (1.0 / dt) ** 2 * random_normal(seed + 5, (r,)) if with_c else None
-    return dict(Phi=Phi, PhiS=PhiS, A=A, B=B, H=H, c=c)
+from paper_2511_20687_amd.inputs import synthetic_rom  # noqa: E402,F401

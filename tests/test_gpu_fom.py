@@ -6,18 +6,18 @@ Tolerances (relative space-time L2 of the displacement, Eq. mse): 1e-10 in FP64,
 import numpy as np
 import pytest
 
-from paper_2511_20687_amd.inputs import CFG1, Bar, Pulse, gaussian_pulse_u, slab_layers
+from paper_2511_20687_amd.inputs import CFG1, Bar, Pulse, gaussian_pulse_u, random_normal, slab_layers
 from oracle.schwarz import SchwarzOptions
-from tests._gpu import lib_free_index, lib_sch_index, oracle_fom_coupled, rel_err, torch_dtype
+from tests._gpu import lib_free_index, lib_index_of, lib_sch_index, oracle_fom_coupled, rel_err, torch_dtype
 
 pytestmark = pytest.mark.gpu
 
 
-def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s=False):
+def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s=False, lateral_fix=()):
     import torch
     from paper_2511_20687_amd import osam
     ctx = osam.Context(0, precision, batch)
-    sds = osam.add_bar_subdomains(ctx, bar, layers, dt)
+    sds = osam.add_bar_subdomains(ctx, bar, layers, dt, lateral_fix=lateral_fix)
     dev = torch.device("cuda:0")
     recs = []
     for sd in sds:
@@ -56,6 +56,29 @@ def test_cfg1_fom_fom_matches_oracle(precision, tol):
     if precision == "f64":
         assert info[0]["total_iters"] == int(ref["iters"].sum())
         assert info[0]["max_iters"] == int(ref["iters"].max())
+
+
+@pytest.mark.parametrize("lateral_fix", [(0, 1), (2,), (0, 1, 2)])
+def test_lateral_dirichlet_matches_oracle_f64(lateral_fix):
+    """Lateral faces holding components at zero (Sec. 5.1 holds x and y); a seeded IC with all
+    three components nonzero everywhere, so the held DOFs must be zeroed and stay zero."""
+    bar = Bar(3, 4, 30)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    u0 = 1e-5 * random_normal(71, (3, bar.n_nodes))
+    v0 = 1e-2 * random_normal(72, (3, bar.n_nodes))
+    n = 150
+    print(f"[lateral {lateral_fix}] oracle", flush=True)
+    models, ref = oracle_fom_coupled(bar, layers, dt, u0, v0, n, lateral_fix=lateral_fix)
+    print(f"[lateral {lateral_fix}] gpu", flush=True)
+    ctx, recs, info = _lib_run(bar, layers, dt, u0, v0, n, "f64", lateral_fix=lateral_fix)
+    for i, m in enumerate(models):
+        idx = lib_index_of(m)
+        got = recs[i][0][0]
+        assert rel_err(got[:, idx], ref["u"][i]) <= 1e-10
+        held = np.setdiff1d(np.arange(got.shape[1]), idx)
+        assert held.size > 0 and np.all(got[:, held] == 0.0)
+    assert info[0]["total_iters"] == int(ref["iters"].sum())
 
 
 def test_three_slabs_and_schwarz_records_f64():

@@ -16,7 +16,7 @@ from oracle.opinf import lambda_grid, select_lambda
 from oracle.pod import pod
 from oracle.rom import OpInfModel
 from oracle.schwarz import Coupled, SchwarzOptions
-from tests._gpu import (lib_free_index, lib_sch_index, rel_err, restrict_free_lib, synthetic_rom,
+from tests._gpu import (lib_free_index, lib_index_of, lib_sch_index, rel_err, restrict_free_lib, synthetic_rom,
                         torch_dtype)
 
 pytestmark = pytest.mark.gpu
@@ -138,14 +138,14 @@ def test_pod_of_prescribed_spectrum_matches_oracle():
     assert out2["r"] == int(np.searchsorted(e, 1 - 1e-6) + 1)
 
 
-def _train_oracle_and_gpu(bar, layers, dt, u0, v0, T, precision):
+def _train_oracle_and_gpu(bar, layers, dt, u0, v0, T, precision, lateral_fix=()):
     """FOM-FOM training run on both sides; snapshots of subdomain 1 (U, U'', S, v0)."""
     import torch
     from paper_2511_20687_amd import osam
-    models = [FomModel(bar, lo, hi, dt) for lo, hi in layers]
+    models = [FomModel(bar, lo, hi, dt, lateral_fix=lateral_fix) for lo, hi in layers]
     ref = Coupled(models).run(u0, v0, T - 1, SchwarzOptions(), record=("u", "a", "s", "v"))
     ctx = osam.Context(0, precision, 1)
-    sds = osam.add_bar_subdomains(ctx, bar, layers, dt)
+    sds = osam.add_bar_subdomains(ctx, bar, layers, dt, lateral_fix=lateral_fix)
     z = ctx.sizes(1)
     dev = "cuda:0"
     dt_ = torch_dtype(precision)
@@ -160,8 +160,9 @@ def _train_oracle_and_gpu(bar, layers, dt, u0, v0, T, precision):
     return models, ref, ctx, (U, A, S, V0)
 
 
+@pytest.mark.parametrize("lateral_fix", [(), (0, 1)])
 @pytest.mark.parametrize("form", ["linear", "quadratic"])
-def test_learning_pipeline_matches_oracle(form):
+def test_learning_pipeline_matches_oracle(form, lateral_fix):
     """Train on a FOM-FOM run, learn OpInf for subdomain 2 with Alg. 3, run FOM-OpInf online.
 
     Compared: POD singular values, lambda*, the selected E(lambda), and the online
@@ -173,7 +174,8 @@ def test_learning_pipeline_matches_oracle(form):
     v0 = np.zeros_like(u0)
     T = 400
     r = 8 if form == "linear" else 6
-    models, ref, ctx, (U, A, S, V0) = _train_oracle_and_gpu(bar, layers, dt, u0, v0, T, "f64")
+    print(f"[learn {form} lateral {lateral_fix}]", flush=True)
+    models, ref, ctx, (U, A, S, V0) = _train_oracle_and_gpu(bar, layers, dt, u0, v0, T, "f64", lateral_fix)
     lams = lambda_grid(11)
     out = ctx.learn_opinf(1, U, A, S, V0, 1, T, form=form, r=r, r_s=0, energy_bnd=1 - 1e-6,
                           lambdas=list(lams))
@@ -194,7 +196,7 @@ def test_learning_pipeline_matches_oracle(form):
     fin = np.isfinite(E) & (E < 1.0)
     assert np.allclose(out["E_lambda"][fin], E[fin], rtol=1e-5, atol=1e-9)
     # online FOM-OpInf on both sides, same IC
-    g = SubdomainGeometry(bar, *layers[1])
+    g = SubdomainGeometry(bar, *layers[1], lateral_fix=lateral_fix)
     rom = OpInfModel(g, Phi, PhiS, ops.A, ops.H, ops.B, ops.c, dt=dt)
     on = Coupled([models[0], rom]).run(u0, v0, 300, SchwarzOptions(), record=("u",))
     import torch
@@ -207,10 +209,10 @@ def test_learning_pipeline_matches_oracle(form):
         recs.append(t)
     ctx.set_initial(0, u0, v0)
     ctx.run(300)
-    fom_u = recs[0][0].cpu().numpy()[:, lib_free_index(bar, *layers[0])]
+    fom_u = recs[0][0].cpu().numpy()[:, lib_index_of(models[0])]
     e0 = rel_err(fom_u, on["u"][0])
     Phi_g = ctx.get_opinf(1)["Phi"]
-    rom_u = (Phi_g @ recs[1][0].cpu().numpy().T).T[:, lib_free_index(bar, *layers[1])]
+    rom_u = (Phi_g @ recs[1][0].cpu().numpy().T).T[:, lib_index_of(g)]
     e1 = rel_err(rom_u, on["u"][1])
     print("online errors", e0, e1)
     assert e0 <= 1e-7 and e1 <= 1e-7

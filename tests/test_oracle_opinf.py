@@ -5,7 +5,7 @@ import pytest
 from paper_2511_20687_amd.inputs import Bar, gaussian_pulse_u, random_normal, slab_layers
 from oracle.metrics import rel_l2
 from oracle.newmark import FomModel
-from oracle.opinf import (data_matrix, fit, lambda_grid, ridge, rollout_frozen, select_lambda,
+from oracle.opinf import (amplitude_scale, data_matrix, fit, lambda_grid, ridge, rollout_frozen, select_lambda,
                           trajectory_error)
 from oracle.pod import energy_rank, pod, projection_error
 from oracle.rom import OpInfModel, Operators, kron2, kron2_jacobian
@@ -183,3 +183,48 @@ def test_data_matrix_columns():
     assert D.shape == (3, 2 + 3 + 1 + 1)
     assert np.allclose(D[:, 2:5], kron2(Q).T)
     assert np.allclose(D[:, -1], 1.0)
+
+
+def test_normalised_fit_recovers_intrusive_operators(training):
+    """At lambda = 0 the change of variables (tau = t/dt, q/alpha) does not move the minimiser."""
+    m = training["models"][1]
+    U, A, S, V, Phi, PhiS = _reduce(training)
+    Q = Phi.T @ U
+    alpha = amplitude_scale([Q])
+    assert alpha == np.linalg.norm(Q, axis=0).max()
+    ops = fit([Q], [Phi.T @ A], [PhiS.T @ S], 0.0, dt=training["dt"], alpha=alpha)
+    Minv = 1.0 / m.m_f
+    K_fs = m.K[m.free_dofs][:, m.sch_dofs].toarray()
+    A_int = -Phi.T @ (Minv[:, None] * (m.K_ff @ Phi))
+    B_int = -Phi.T @ (Minv[:, None] * K_fs) @ PhiS
+    assert np.abs(ops.A - A_int).max() <= 1e-8 * np.abs(A_int).max()
+    assert np.abs(ops.B - B_int).max() <= 1e-8 * np.abs(B_int).max()
+
+
+@pytest.mark.parametrize("with_c", [False, True])
+def test_normalised_fit_is_stationary_point_of_scaled_objective(with_c):
+    """First-order conditions of the normalised ridge objective written in physical units:
+    J = ||(dt^2/alpha) E||^2 + lambda dt^4 (||A||^2 + alpha^2 ||H||^2 + ||B||^2 + ||c||^2/alpha^2),
+    E = Qdd - A Q - H Q^(2) - B S^ - c 1^T, so at the minimiser
+    E Q^T = lambda alpha^2 A,  E (Q^(2))^T = lambda alpha^4 H,  E S^^T = lambda alpha^2 B,
+    E 1 = lambda c.  Checked on random data with magnitudes far from one."""
+    r, rs, T = 4, 2, 60
+    Q = 3e-4 * random_normal(41, (r, T))
+    Sh = 2e-4 * random_normal(42, (rs, T))
+    Qdd = 5e6 * random_normal(43, (r, T))
+    dt, lam = 2.5e-6, 1e-3
+    alpha = amplitude_scale([Q])
+    o = fit([Q], [Qdd], [Sh], lam, form="quadratic", with_c=with_c, dt=dt, alpha=alpha)
+    K = kron2(Q)
+    E = Qdd - o.A @ Q - o.H @ K - o.B @ Sh
+    if with_c:
+        E = E - o.c[:, None]
+    scale = np.abs(E).max() * np.abs(Q).max() * T
+    assert np.abs(E @ Q.T - lam * alpha ** 2 * o.A).max() <= 1e-9 * scale
+    assert np.abs(E @ K.T - lam * alpha ** 4 * o.H).max() <= 1e-9 * scale * np.abs(Q).max()
+    assert np.abs(E @ Sh.T - lam * alpha ** 2 * o.B).max() <= 1e-9 * scale
+    if with_c:
+        assert np.abs(E.sum(axis=1) - lam * o.c).max() <= 1e-9 * np.abs(E).max() * T
+    # the raw fit (dt = alpha = 1) with the same lambda is a different, over-regularised model
+    raw = fit([Q], [Qdd], [Sh], lam, form="quadratic", with_c=with_c)
+    assert np.abs(raw.A - o.A).max() > 1e-3 * np.abs(o.A).max()
