@@ -104,7 +104,7 @@ def main():
     from paper_2511_20687_amd import osam
     from paper_2511_20687_amd.inputs import CFG2, draw_pulses
     w = CFG2
-    pulse = draw_pulses(w.seed, 1)[0]
+    pulse = draw_pulses(w.seed, 1, s=w.pulse_width)[0]
     n = w.steps
     _log(f"workload {w.name}: pulse a={pulse.a:.4e} b={pulse.b:.4f} s={pulse.s}; dt={w.dt:.4e}")
 

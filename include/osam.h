@@ -216,6 +216,14 @@ int32_t osam_set_timing(osam_ctx *ctx, int32_t enable);
  * kernel and their number (synchronises the stream). */
 int32_t osam_get_timing(osam_ctx *ctx, int32_t sd, double *ms, int64_t *launches);
 
+/* Launch shape of FOM subdomain sd's step kernel: `block` threads per workgroup
+ * (64, 128 or 256; 0 = automatic) and `kc` z-layers marched per thread
+ * (>= 1; 0 = automatic).  Affects speed only, never results.  OSAM_E_INVALID
+ * for other values or an OpInf subdomain. */
+int32_t osam_set_fe_launch(osam_ctx *ctx, int32_t sd, int32_t block, int32_t kc);
+/* Current launch shape of FOM subdomain sd (any pointer may be NULL). */
+int32_t osam_get_fe_launch(osam_ctx *ctx, int32_t sd, int32_t *block, int32_t *kc);
+
 /* Wait for all queued work of the context (host synchronisation). */
 int32_t osam_sync(osam_ctx *ctx);
 

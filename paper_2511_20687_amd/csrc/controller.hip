@@ -14,14 +14,12 @@ namespace osam {
 
 template <typename T> hipError_t launch_fe(const FeArgs<T> &, int, int, int, hipStream_t);
 template <typename T> hipError_t launch_rom(const RomArgs<T> &, int, hipStream_t);
+hipError_t launch_finish(const Status *, Status *, const FinishArgs &, const Opts &, int, hipStream_t);
 template <typename T>
 hipError_t launch_project(const T *, long long, long long, const T *, long long, long long, double *, int,
                           int, hipStream_t);
 template <typename T>
 hipError_t launch_lift(const T *, long long, long long, int, const T *, T *, long long, long long, hipStream_t);
-template <typename T>
-hipError_t launch_piphi(const T *, long long, long long, int, const int *, const T *, int, int, int, T *,
-                        hipStream_t);
 
 #define HIPCHK(expr)                                                                         \
   do {                                                                                       \
@@ -32,32 +30,20 @@ hipError_t launch_piphi(const T *, long long, long long, int, const int *, const
 double *Ctx::scratch(size_t n, int32_t *st) {
   if (n > scratch_n) {
     dfree(d_scratch);
-    d_scratch = nullptr;
-    void *p = nullptr;
-    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
-      *st = OSAM_E_OOM;
-      scratch_n = 0;
-      return nullptr;
-    }
-    allocs.push_back(p);
-    d_scratch = static_cast<double *>(p);
-    scratch_n = n;
+    d_scratch = static_cast<double *>(arena_alloc(n * sizeof(double), st));
+    scratch_n = d_scratch ? n : 0;
+    if (!d_scratch) return nullptr;
   }
   return d_scratch;
 }
 
 // Launch shape of the FE kernel: columns x z-chunks x instances.  block/kc = 0
-// selects the default heuristic (enough workgroups to fill 256 CUs).
+// selects the default (256 threads, one layer per thread).
 void Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
   const int nl = s.nzs - 1;
-  int bs = block > 0 ? block : (s.n_int < 2048 ? 64 : 256);
+  int bs = block > 0 ? block : 256;
   auto per_chunk = [&](int b) { return (s.n_int + b - 1) / b + (s.n_bnd + b - 1) / b; };
-  if (kc <= 0) {
-    const int target = 2048;
-    const int pc = per_chunk(bs) * batch;
-    int chunks = std::max(1, std::min(nl, (target + pc - 1) / pc));
-    kc = std::max(std::min(4, nl), (nl + chunks - 1) / chunks);
-  }
+  if (kc <= 0) kc = 1;   // one node layer per thread: a single memory round trip
   kc = std::max(1, std::min(kc, nl));
   s.fe_block = bs;
   s.fe_kc = kc;
@@ -420,6 +406,26 @@ int32_t Ctx::init_pending() {
 }
 
 // ---------------------------------------------------------------------------
+// What the decider of a sweep gathers: the FOM subdomains' partial sums and
+// the OpInf subdomains (other than the last) whose sums are in the output status.
+static FinishArgs finish_args(Ctx &c) {
+  FinishArgs F;
+  std::memset(&F, 0, sizeof(F));
+  const int last = (int)c.sds.size() - 1;
+  for (int i = 0; i <= last; ++i) {
+    const Subdomain &d = *c.sds[i];
+    if (d.rom) {
+      if (i != last) F.rom_sd[F.nrom++] = i;
+      continue;
+    }
+    F.sd[F.nfom] = i;
+    F.nblocks[F.nfom] = d.fe_nblocks;
+    F.part[F.nfom] = d.partials;
+    ++F.nfom;
+  }
+  return F;
+}
+
 template <typename T>
 static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T> &A) {
   std::memset(&A, 0, sizeof(A));
@@ -435,6 +441,7 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
     A.a[k] = (T *)s.a[k];
   }
   A.coef = (const T *)s.coef;
+  for (int i = 0; i < 234; ++i) A.ci[i] = (T)s.ci[i];
   A.dt = (T)s.desc.dt;
   A.half_dt = (T)(0.5 * s.desc.dt);
   A.half_dt2 = (T)(0.5 * s.desc.dt * s.desc.dt);
@@ -463,7 +470,6 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.sd = sdi;
   A.opts = o;
   A.partials = s.partials;
-  A.counters = s.counters;
   A.kc = s.fe_kc;
   A.n_chunks = s.fe_chunks;
   A.n_int = s.n_int;
@@ -554,8 +560,10 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
   }
   A.nexp = ne;
   A.status = c.d_status;
+  A.status_out = c.d_status_alt;
   A.sd = sdi;
   A.opts = o;
+  A.finish = finish_args(c);
   A.rec_q = (T *)s.rec.u;
   A.rec_every = s.rec.every;
   A.rec_ncols = s.rec.n_cols;
@@ -603,6 +611,13 @@ int32_t Ctx::launch_round(const Opts &o) {
       ev_used.push_back({(int)i, {a, b}});
     }
   }
+  // a ROM kernel that ends the sweep takes the decision itself
+  if (!sds.back()->rom) {
+    const hipError_t e = launch_finish(d_status, d_status_alt, finish_args(*this), o, batch, stream);
+    if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("finish kernel: ") + hipGetErrorString(e));
+  }
+  // the decider wrote the other buffer: it is the input of the next round
+  std::swap(d_status, d_status_alt);
   return OSAM_OK;
 }
 

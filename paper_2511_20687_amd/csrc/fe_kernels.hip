@@ -1,6 +1,6 @@
 // Matrix-free hex8 explicit Newmark step of one FOM subdomain (all instances),
-// with the FP64 convergence sums of Eq. conv_criterion, the on-device controller
-// decision, and the push of the next-step displacement to the neighbours' faces.
+// with the FP64 convergence sums of Eq. conv_criterion and the push of the
+// next-step displacement to the neighbours' faces.
 //
 // Method: Sec. 2 (lumped-mass Galerkin hex8, Eq. matrix_vector_form_with_dbcs)
 // and Sec. 4.1 (explicit Newmark-beta, beta = 0, gamma = 1/2; Schwarz data on
@@ -14,18 +14,24 @@
 //    4 edges; z-layers 1..nzs-1 always have elements above and below).  The
 //    host folds -1/m (lumped mass) into the blocks: a = sum_d C_d (u_{i+d} - u_i).
 //    Relative displacements keep FP32 accurate (the rows of K sum to zero).
-//  * One thread owns a node column (ix, iy) and marches up a chunk of z-layers
-//    with a rolling two-layer window: 27 loads per node, 150 non-zero FMAs per
-//    interior node (structural zeros of the isotropic stencil are skipped at
-//    compile time).  Interior columns and the boundary columns (grouped by
-//    stencil case, padded to whole waves) run in separate workgroups, so every
-//    wave reads one coefficient block through scalar loads.
+//  * The interior coefficient block travels in the kernel arguments, so it is
+//    read with scalar loads and never occupies vector registers (150 of its 234
+//    entries are used: the isotropic stencil's structural zeros are skipped at
+//    compile time); the 8 boundary cases (edge columns only) read theirs from
+//    memory.  Interior and boundary columns (grouped by case, padded to whole
+//    waves) run in separate workgroups.
+//  * Launch shape: a thread owns one node column and kc consecutive z-layers.
+//    kc = 1 issues every load of the node (three 3x3 neighbourhoods, the state)
+//    at once, one memory round trip per node; kc > 1 marches a rolling
+//    two-layer window up the column (fewer loads per node, one round trip per
+//    layer).  Workgroups are renumbered so each XCD gets a contiguous range of
+//    z-chunks and neighbouring layers meet in the same L2.
 //  * The displacement at t_k on free nodes is the Newmark predictor, which the
 //    previous step already produced (buffer P); an iteration reads P, V0, A0
 //    and the previous iterate's V1, and writes V1, A1 and the next predictor
 //    P2 = P + dt V1 + dt^2/2 A1.  Face layers of P / U0 hold the neighbour's
-//    pushed values.  No atomics on data; FP64 norm partials are summed in a
-//    fixed order by the last workgroup (deterministic).
+//    pushed values.  No atomics or fences: every workgroup stores one pair of
+//    FP64 partial sums, reduced in a fixed order after the sweep.
 //  * Buffer roles rotate with the instance's accepted-step count, so each
 //    instance advances at its own pace and the host never waits per step.
 #include "osam_device.hpp"
@@ -42,6 +48,12 @@ __host__ __device__ constexpr int d27_axis(int d27, int p) {
 }
 __host__ __device__ constexpr bool interior_zero(int d27, int p, int q) {
   return p != q && (d27_axis(d27, p) == 0 || d27_axis(d27, q) == 0);
+}
+// XCD-aware order: hardware hands workgroup i to XCD i % 8; give every XCD a
+// contiguous range of logical blocks (chunk-major, i.e. neighbouring layers).
+__device__ __forceinline__ int xcd_block(int bid, int n) {
+  const int q = n >> 3, rem = n & 7, xcd = bid & 7, slot = bid >> 3;
+  return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
 // 3x3 neighbourhood of node layer L (SoA buffer P, component stride cs).
@@ -64,7 +76,8 @@ __device__ __forceinline__ void load_layer(T (&w)[9][3], const T *P, long long c
 // Contribution of one z-slab (dz = DZ) of the 27-point stencil to the node
 // whose own value is ctr: acc += sum_n C_(dx,dy,DZ) (w[n] - ctr).
 template <typename T, bool INTERIOR, int DZ>
-__device__ __forceinline__ void slab(const T (&w)[9][3], const T (&ctr)[3], const T *C, T (&acc)[3]) {
+__device__ __forceinline__ void slab(const FeArgs<T> &A, const T *C, const T (&w)[9][3], const T (&ctr)[3],
+                                     T (&acc)[3]) {
 #pragma unroll
   for (int n = 0; n < 9; ++n) {
     const int d27 = (DZ + 1) * 9 + n;
@@ -75,8 +88,12 @@ __device__ __forceinline__ void slab(const T (&w)[9][3], const T (&ctr)[3], cons
     for (int p = 0; p < 3; ++p) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        if (INTERIOR && interior_zero(d27, p, q)) continue;
-        acc[p] += C[d26 * 9 + p * 3 + q] * du[q];
+        if (INTERIOR) {
+          if (interior_zero(d27, p, q)) continue;
+          acc[p] += A.ci[d26 * 9 + p * 3 + q] * du[q];
+        } else {
+          acc[p] += C[d26 * 9 + p * 3 + q] * du[q];
+        }
       }
     }
   }
@@ -88,22 +105,105 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-template <typename T, int MODE, bool INTERIOR>
+// Per-thread view of one instance's buffers in the roles of its current step.
+template <typename T>
+struct Roles {
+  T *U0, *P, *P2, *V0, *V1, *A0, *A1;
+  const T *Pin, *Flo, *Fhi;
+  int rP, rP2;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ Roles<T> roles(const FeArgs<T> &A, int b, long long step, int n_iter) {
+  Roles<T> R;
+  const long long boff = (long long)b * A.is;
+  const int s3 = (int)(step % 3), s2 = (int)(step % 2);
+  // U0 = u[s%3], P = u[(s+1)%3], P2 = u[(s+2)%3]; V0 = v[s%2], V1 = v[(s+1)%2]
+  R.rP = (s3 + 1) % 3;
+  R.rP2 = (s3 + 2) % 3;
+  R.U0 = A.u[s3] + boff;
+  R.P = A.u[R.rP] + boff;
+  R.P2 = A.u[R.rP2] + boff;
+  R.V0 = A.v[s2] + boff;
+  R.V1 = A.v[1 - s2] + boff;
+  R.A0 = A.a[s2] + boff;
+  R.A1 = A.a[1 - s2] + boff;
+  // Face layers: HOLD at iteration 1 when the source comes later in the sweep
+  // reads the neighbour's value at t_{k-1} (role U0), otherwise at t_k (role P).
+  R.Pin = (MODE == kModeInit) ? R.U0 : R.P;
+  R.Flo = R.Pin;
+  R.Fhi = R.Pin;
+  if (MODE == kModeStep && n_iter == 1 && A.opts.guess == 0) {
+    if (A.face_src[0] > A.sd) R.Flo = R.U0;
+    if (A.face_src[1] > A.sd) R.Fhi = R.U0;
+  }
+  return R;
+}
+
+// Newmark update of node (layer k, column nid0) from its acceleration, with
+// the convergence sums, records and pushes.
+template <typename T, int MODE>
+__device__ __forceinline__ void update_node(const FeArgs<T> &A, const Roles<T> &R, int b, int k, int nid0,
+                                            const T (&ctr)[3], const T (&acc)[3], const T (&v0)[3],
+                                            const T (&a0)[3], const T (&old)[3], int n_iter, bool rec,
+                                            long long rbase, double &acc_abs, double &acc_den) {
+  const long long cs = A.cs;
+  const long long id = (long long)k * A.npl + nid0;
+  T out[3];   // value pushed to neighbours: the displacement at the next step
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T a1 = acc[c];
+    if (MODE == kModeInit) {
+      R.A0[c * cs + id] = a1;
+      out[c] = ctr[c] + A.dt * v0[c] + A.half_dt2 * a1;
+      R.P[c * cs + id] = out[c];
+    } else {
+      const T p = ctr[c];
+      const T v1 = v0[c] + A.half_dt * (a0[c] + a1);
+      double dlt;
+      if (n_iter >= 2)
+        dlt = (double)A.dt * ((double)v1 - (double)old[c]);   // old = previous iterate's V1
+      else   // iterate 0 = state at t_{k-1} (only tested when min_iter = 1); old = U0
+        dlt = ((double)p - (double)old[c]) + (double)A.dt * ((double)v1 - (double)v0[c]);
+      acc_abs += dlt * dlt;
+      const double den = (double)p + (double)A.dt * (double)v1;
+      acc_den += den * den;
+      R.V1[c * cs + id] = v1;
+      R.A1[c * cs + id] = a1;
+      out[c] = p + A.dt * v1 + A.half_dt2 * a1;
+      R.P2[c * cs + id] = out[c];
+    }
+    if (rec) {
+      const long long ro = rbase + (long long)c * A.nfree_nodes + (long long)(k - 1) * A.npl + nid0;
+      if (A.rec_u) A.rec_u[ro] = ctr[c];
+      if (A.rec_a) A.rec_a[ro] = a1;
+    }
+  }
+  // push to the faces fed by this layer (next-step role: P2, or P when initialising)
+  for (int e = 0; e < A.npush; ++e) {
+    const PushDev<T> &Pd = A.push[e];
+    if (Pd.layer != k) continue;
+    T *dst = Pd.role[MODE == kModeInit ? R.rP : R.rP2] + (long long)b * Pd.is + nid0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c * Pd.cs] = out[c];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void record_face(const FeArgs<T> &A, int b, int f, int nid0, const T (&w)[9][3],
+                                            long long rcol) {
+  const long long so = ((long long)b * A.rec_ncols + rcol) * 3 * A.nsch_nodes + (f ? A.face_off_hi : 0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) A.rec_s[so + (long long)c * A.nsch_nodes + nid0] = w[4][c];
+}
+
+// Column (ix, iy), layers k0 .. k1-1 (ONE: the single layer k0, every load issued at once).
+template <typename T, int MODE, bool INTERIOR, bool ONE>
 __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int chunk, long long step,
                                            int iter, double &acc_abs, double &acc_den) {
   const int nx = A.nx, ny = A.ny, nxp = nx + 1, npl = A.npl, nzs = A.nzs;
   const long long cs = A.cs;
-  const long long boff = (long long)b * A.is;
-  const int s3 = (int)(step % 3), s2 = (int)(step % 2);
-  // roles: U0 = u[s%3], P = u[(s+1)%3], P2 = u[(s+2)%3]; V0 = v[s%2], V1 = v[(s+1)%2]
-  const int rP = (s3 + 1) % 3, rP2 = (s3 + 2) % 3;
-  T *U0 = A.u[s3] + boff;
-  T *P = A.u[rP] + boff;
-  T *P2 = A.u[rP2] + boff;
-  T *V0 = A.v[s2] + boff, *V1 = A.v[1 - s2] + boff;
-  T *A0 = A.a[s2] + boff, *A1 = A.a[1 - s2] + boff;
   const int n_iter = iter + 1;
-
   int ix, iy, cse;
   if (INTERIOR) {
     if (t >= A.n_int) return;
@@ -120,103 +220,68 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
     cse = __builtin_amdgcn_readfirstlane((ix == 0 ? 0 : (ix == nx ? 2 : 1)) + 3 * (iy == 0 ? 0 : (iy == ny ? 2 : 1)));
   }
   const T *C = A.coef + cse * 234;
-
-  // Face layers: HOLD at iteration 1 when the source comes later in the sweep
-  // reads the neighbour's value at t_{k-1} (role U0), otherwise at t_k (role P).
-  const T *Pin = (MODE == kModeInit) ? U0 : P;
-  const T *Flo = Pin, *Fhi = Pin;
-  if (MODE == kModeStep && n_iter == 1 && A.opts.guess == 0) {
-    if (A.face_src[0] > A.sd) Flo = U0;
-    if (A.face_src[1] > A.sd) Fhi = U0;
-  }
+  const Roles<T> R = roles<T, MODE>(A, b, step, n_iter);
   const int k0 = 1 + chunk * A.kc;
-  const int k1 = min(k0 + A.kc, nzs);
+  const int k1 = ONE ? k0 + 1 : min(k0 + A.kc, nzs);
   const int nid0 = ix + nxp * iy;
-
-  // rolling window: cur = layer k, nxt = layer k+1; acc holds the partial force
-  // of layer k from layers k-1 and k until layer k+1 arrives.
-  T cur[9][3], nxt[9][3], acc[3], ctr[3];
-  load_layer<T, INTERIOR>(nxt, k0 == 1 ? Flo : Pin, cs, k0 - 1, npl, nxp, ix, iy, nx, ny);
-  load_layer<T, INTERIOR>(cur, Pin, cs, k0, npl, nxp, ix, iy, nx, ny);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    ctr[c] = cur[4][c];
-    acc[c] = T(0);
-  }
-  slab<T, INTERIOR, -1>(nxt, ctr, C, acc);
-  slab<T, INTERIOR, 0>(cur, ctr, C, acc);
 
   const long long rcol = (MODE == kModeInit) ? 0 : (step + 1) / (A.rec_every > 0 ? A.rec_every : 1);
   const bool rec = A.rec_every > 0 && rcol < A.rec_ncols &&
                    (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
   const long long rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
-  if (rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) {
-    const long long so = ((long long)b * A.rec_ncols + rcol) * 3 * A.nsch_nodes;
+
+  if (ONE) {
+    const int k = k0;
+    T w0[9][3], w1[9][3], w2[9][3], v0[3], a0[3], old[3], acc[3], ctr[3];
+    load_layer<T, INTERIOR>(w0, k == 1 ? R.Flo : R.Pin, cs, k - 1, npl, nxp, ix, iy, nx, ny);
+    load_layer<T, INTERIOR>(w1, R.Pin, cs, k, npl, nxp, ix, iy, nx, ny);
+    load_layer<T, INTERIOR>(w2, k + 1 == nzs ? R.Fhi : R.Pin, cs, k + 1, npl, nxp, ix, iy, nx, ny);
+    const long long id = (long long)k * npl + nid0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) A.rec_s[so + (long long)c * A.nsch_nodes + nid0] = nxt[4][c];
+    for (int c = 0; c < 3; ++c) {
+      v0[c] = R.V0[c * cs + id];
+      a0[c] = MODE == kModeInit ? T(0) : R.A0[c * cs + id];
+      old[c] = MODE == kModeInit ? T(0) : (n_iter >= 2 ? R.V1[c * cs + id] : R.U0[c * cs + id]);
+      ctr[c] = w1[4][c];
+      acc[c] = T(0);
+    }
+    slab<T, INTERIOR, -1>(A, C, w0, ctr, acc);
+    slab<T, INTERIOR, 0>(A, C, w1, ctr, acc);
+    slab<T, INTERIOR, 1>(A, C, w2, ctr, acc);
+    update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
+    if (rec && A.rec_s) {
+      if (k == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, w0, rcol);
+      if (k == nzs - 1 && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, w2, rcol);
+    }
+    return;
   }
 
+  // rolling window: cur = layer k, nxt = layer k+1; acc holds the partial force
+  // of layer k from layers k-1 and k until layer k+1 arrives.
+  T cur[9][3], nxt[9][3], acc[3], ctr[3];
+  load_layer<T, INTERIOR>(nxt, k0 == 1 ? R.Flo : R.Pin, cs, k0 - 1, npl, nxp, ix, iy, nx, ny);
+  load_layer<T, INTERIOR>(cur, R.Pin, cs, k0, npl, nxp, ix, iy, nx, ny);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ctr[c] = cur[4][c];
+    acc[c] = T(0);
+  }
+  slab<T, INTERIOR, -1>(A, C, nxt, ctr, acc);
+  slab<T, INTERIOR, 0>(A, C, cur, ctr, acc);
+  if (rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, nxt, rcol);
+
   for (int k = k0; k < k1; ++k) {
-    // keep the stencil coefficients out of registers: re-read every layer
-    __asm__ volatile("" ::: "memory");
-    load_layer<T, INTERIOR>(nxt, k + 1 == nzs ? Fhi : Pin, cs, k + 1, npl, nxp, ix, iy, nx, ny);
-    slab<T, INTERIOR, 1>(nxt, ctr, C, acc);
     const long long id = (long long)k * npl + nid0;
-    T out[3];   // value pushed to neighbours: the displacement at the next step
-    if (MODE == kModeInit) {
+    T v0[3], a0[3], old[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T a1 = acc[c];
-        const T u0 = ctr[c];
-        const T v0 = V0[c * cs + id];
-        A0[c * cs + id] = a1;
-        out[c] = u0 + A.dt * v0 + A.half_dt2 * a1;
-        P[c * cs + id] = out[c];
-        if (rec) {
-          const long long ro = rbase + (long long)c * A.nfree_nodes + (long long)(k - 1) * npl + nid0;
-          if (A.rec_u) A.rec_u[ro] = u0;
-          if (A.rec_a) A.rec_a[ro] = a1;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T a1 = acc[c];
-        const T p = ctr[c];
-        const T v0 = V0[c * cs + id];
-        const T a0 = A0[c * cs + id];
-        const T v1 = v0 + A.half_dt * (a0 + a1);
-        double dlt;
-        if (n_iter >= 2) {
-          const T v1old = V1[c * cs + id];
-          dlt = (double)A.dt * ((double)v1 - (double)v1old);
-        } else {
-          // iterate 0 = state at t_{k-1} (only tested when min_iter = 1)
-          const T u0 = U0[c * cs + id];
-          dlt = ((double)p - (double)u0) + (double)A.dt * ((double)v1 - (double)v0);
-        }
-        acc_abs += dlt * dlt;
-        const double den = (double)p + (double)A.dt * (double)v1;
-        acc_den += den * den;
-        V1[c * cs + id] = v1;
-        A1[c * cs + id] = a1;
-        out[c] = p + A.dt * v1 + A.half_dt2 * a1;
-        P2[c * cs + id] = out[c];
-        if (rec) {
-          const long long ro = rbase + (long long)c * A.nfree_nodes + (long long)(k - 1) * npl + nid0;
-          if (A.rec_u) A.rec_u[ro] = p;
-          if (A.rec_a) A.rec_a[ro] = a1;
-        }
-      }
+    for (int c = 0; c < 3; ++c) {
+      v0[c] = R.V0[c * cs + id];
+      a0[c] = MODE == kModeInit ? T(0) : R.A0[c * cs + id];
+      old[c] = MODE == kModeInit ? T(0) : (n_iter >= 2 ? R.V1[c * cs + id] : R.U0[c * cs + id]);
     }
-    // push to the faces fed by this layer (next-step role: P2, or P when initialising)
-    for (int e = 0; e < A.npush; ++e) {
-      const PushDev<T> &Pd = A.push[e];
-      if (Pd.layer != k) continue;
-      T *dst = Pd.role[MODE == kModeInit ? rP : rP2] + (long long)b * Pd.is + nid0;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) dst[c * Pd.cs] = out[c];
-    }
+    load_layer<T, INTERIOR>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, cs, k + 1, npl, nxp, ix, iy, nx, ny);
+    slab<T, INTERIOR, 1>(A, C, nxt, ctr, acc);
+    update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (k + 1 < k1) {
       // start layer k+1: contributions of layers k (dz = -1) and k+1 (dz = 0)
 #pragma unroll
@@ -224,26 +289,21 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
         ctr[c] = nxt[4][c];
         acc[c] = T(0);
       }
-      slab<T, INTERIOR, -1>(cur, ctr, C, acc);
-      slab<T, INTERIOR, 0>(nxt, ctr, C, acc);
+      slab<T, INTERIOR, -1>(A, C, cur, ctr, acc);
+      slab<T, INTERIOR, 0>(A, C, nxt, ctr, acc);
 #pragma unroll
       for (int n = 0; n < 9; ++n)
 #pragma unroll
         for (int c = 0; c < 3; ++c) cur[n][c] = nxt[n][c];
     }
   }
-  if (rec && A.rec_s && k1 == nzs && A.face_src[1] >= 0) {
-    const long long so = ((long long)b * A.rec_ncols + rcol) * 3 * A.nsch_nodes;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      A.rec_s[so + (long long)c * A.nsch_nodes + A.face_off_hi + nid0] = nxt[4][c];
-  }
+  if (rec && A.rec_s && k1 == nzs && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, nxt, rcol);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool ONE>
 __global__ void __launch_bounds__(256) fe_kernel(FeArgs<T> A) {
   const int b = blockIdx.y;
-  Status *stp = A.status + b;
+  const Status *stp = A.status + b;
   const int flags = stp->flags;
   if (MODE == kModeStep && (flags & kFinished)) return;
   if (MODE == kModeInit && !(flags & kNeedInit)) return;
@@ -251,21 +311,21 @@ __global__ void __launch_bounds__(256) fe_kernel(FeArgs<T> A) {
   const int iter = stp->iter;
 
   double acc_abs = 0.0, acc_den = 0.0;
-  const int bx = blockIdx.x;
+  const int bx = xcd_block(blockIdx.x, A.nblocks);
   if (bx < A.int_blocks * A.n_chunks) {
     const int t = (bx % A.int_blocks) * blockDim.x + threadIdx.x;
-    fe_columns<T, MODE, true>(A, b, t, bx / A.int_blocks, step, iter, acc_abs, acc_den);
+    fe_columns<T, MODE, true, ONE>(A, b, t, bx / A.int_blocks, step, iter, acc_abs, acc_den);
   } else {
     const int bb = bx - A.int_blocks * A.n_chunks;
     const int nbb = A.nblocks / A.n_chunks - A.int_blocks;
     const int t = (bb % nbb) * blockDim.x + threadIdx.x;
-    fe_columns<T, MODE, false>(A, b, t, bb / nbb, step, iter, acc_abs, acc_den);
+    fe_columns<T, MODE, false, ONE>(A, b, t, bb / nbb, step, iter, acc_abs, acc_den);
   }
   if (MODE == kModeInit) return;
 
-  // deterministic block reduction of the two FP64 sums
+  // fixed-order workgroup reduction of the two FP64 sums; the sweep's finisher
+  // adds the workgroups' partials (no fences or atomics here)
   __shared__ double red[2][16];
-  __shared__ int is_last;
   acc_abs = wave_sum(acc_abs);
   acc_den = wave_sum(acc_den);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -283,52 +343,31 @@ __global__ void __launch_bounds__(256) fe_kernel(FeArgs<T> A) {
     double *pp = A.partials + ((long long)b * A.nblocks + bx) * 2;
     pp[0] = sa;
     pp[1] = sd;
-    __threadfence();
-    const unsigned prev = __hip_atomic_fetch_add(A.counters + b, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned)(A.nblocks - 1));
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  // last workgroup of this instance: sum the partials in a fixed order
-  double sa = 0.0, sd = 0.0;
-  const double *pp = A.partials + (long long)b * A.nblocks * 2;
-  for (int i = threadIdx.x; i < A.nblocks; i += blockDim.x) {
-    sa += __builtin_nontemporal_load(pp + 2 * i);
-    sd += __builtin_nontemporal_load(pp + 2 * i + 1);
-  }
-  sa = wave_sum(sa);
-  sd = wave_sum(sd);
-  __syncthreads();
-  if (lane == 0) {
-    red[0][wid] = sa;
-    red[1][wid] = sd;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double ta = 0.0, td = 0.0;
-    for (int i = 0; i < nw; ++i) {
-      ta += red[0][i];
-      td += red[1][i];
-    }
-    Status &S = *stp;
-    S.sd_abs2[A.sd] = ta;
-    S.sd_den2[A.sd] = td;
-    A.counters[b] = 0u;
-    decide(S, A.sd, A.opts);
-    __threadfence();
-  }
+}
+
+__global__ void __launch_bounds__(64) finish_kernel(const Status *in, Status *out, FinishArgs F, Opts o) {
+  finish_sweep(in, out, F, o, blockIdx.x);
+}
+
+hipError_t launch_finish(const Status *in, Status *out, const FinishArgs &F, const Opts &o, int batch,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3(batch), dim3(64), 0, s, in, out, F, o);
+  return hipGetLastError();
 }
 
 // Host-side launcher -------------------------------------------------------
 template <typename T>
 hipError_t launch_fe(const FeArgs<T> &A, int batch, int block, int mode, hipStream_t s) {
   dim3 grid(A.nblocks, batch);
-  if (mode == kModeInit)
-    hipLaunchKernelGGL((fe_kernel<T, kModeInit>), grid, dim3(block), 0, s, A);
-  else
-    hipLaunchKernelGGL((fe_kernel<T, kModeStep>), grid, dim3(block), 0, s, A);
+  const bool one = A.kc == 1;
+  if (mode == kModeInit) {
+    if (one) hipLaunchKernelGGL((fe_kernel<T, kModeInit, true>), grid, dim3(block), 0, s, A);
+    else hipLaunchKernelGGL((fe_kernel<T, kModeInit, false>), grid, dim3(block), 0, s, A);
+  } else {
+    if (one) hipLaunchKernelGGL((fe_kernel<T, kModeStep, true>), grid, dim3(block), 0, s, A);
+    else hipLaunchKernelGGL((fe_kernel<T, kModeStep, false>), grid, dim3(block), 0, s, A);
+  }
   return hipGetLastError();
 }
 

@@ -36,10 +36,12 @@ __device__ inline void decide(Status &st, int sd, const Opts &o) {
   if (sd != o.nsd - 1) return;
   const int n = st.iter + 1;
   double a = 0.0, d = 0.0;
-  for (int i = 0; i < o.nsd; ++i) {
-    a += st.sd_abs2[i];
-    d += st.sd_den2[i];
-  }
+#pragma unroll
+  for (int i = 0; i < kMaxSd; ++i)
+    if (i < o.nsd) {
+      a += st.sd_abs2[i];
+      d += st.sd_den2[i];
+    }
   const bool tested = n >= o.min_iter;
   if (!isfinite(d) || (tested && !isfinite(a))) {
     st.abs2 = a;
@@ -65,6 +67,92 @@ __device__ inline void decide(Status &st, int sd, const Opts &o) {
   } else {
     st.iter = n;
   }
+}
+
+// End of a Schwarz sweep.  Every FOM step kernel leaves one pair of FP64
+// partial sums per workgroup, every OpInf kernel that does not end the sweep
+// leaves its two sums in the output status; the decider (one wave) reduces the
+// FOM partials in a fixed order and takes the decision.  Running it after the
+// sweep, instead of in a "last workgroup" of each FOM kernel, avoids
+// device-scope fences and atomics, which serialise across the XCDs' separate L2
+// caches.  The status is double-buffered per round: every kernel of a round
+// reads `in`, the decider writes the whole of `out` (also for finished
+// instances), so a kernel with several workgroups can decide without racing
+// the status reads of its other workgroups.
+struct FinishArgs {
+  int nfom, nrom;
+  int sd[kMaxSd];
+  int nblocks[kMaxSd];
+  const double *part[kMaxSd];   // [batch][nblocks][2]
+  int rom_sd[kMaxSd];           // OpInf subdomains whose sums are in `out` already
+};
+
+__device__ __forceinline__ double wave_sum64(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Sums of FOM subdomain k's partials, computed by one wave (lane 0 holds them).
+// Loads are issued in batches of 16 per lane before any is consumed.
+__device__ inline double2 fom_sums(const FinishArgs &F, int k, int b, int lane) {
+  constexpr int U = 16;
+  const int nb = F.nblocks[k];
+  const double2 *pp = reinterpret_cast<const double2 *>(F.part[k]) + (long long)b * nb;
+  double sa = 0.0, sd = 0.0;
+  for (int base = 0; base < nb; base += 64 * U) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = pp[min(base + u * 64 + lane, nb - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (base + u * 64 + lane < nb) {
+        sa += v[u].x;
+        sd += v[u].y;
+      }
+  }
+  return make_double2(wave_sum64(sa), wave_sum64(sd));
+}
+
+// The decider: called by one whole wave (lane 0 writes `out`).  own_sd >= 0
+// with own_abs2/own_den2: the calling OpInf kernel's own sums.
+// pre (optional): the FOM sums already reduced by the caller, [abs2, den2] per FOM subdomain.
+__device__ inline void finish_sweep(const Status *in, Status *out, const FinishArgs &F, const Opts &o, int b,
+                                    int own_sd = -1, double own_abs2 = 0.0, double own_den2 = 0.0,
+                                    const double *pre = nullptr) {
+  const int lane = threadIdx.x & 63;
+  Status s = in[b];
+  if (!(s.flags & kFinished)) {
+    // per-subdomain sums, written with compile-time indices only (no private-memory indexing)
+    for (int k = 0; k < F.nfom; ++k) {
+      const double2 t = pre ? make_double2(pre[2 * k], pre[2 * k + 1]) : fom_sums(F, k, b, lane);
+      const int j = F.sd[k];
+#pragma unroll
+      for (int i = 0; i < kMaxSd; ++i)
+        if (i == j) {
+          s.sd_abs2[i] = t.x;
+          s.sd_den2[i] = t.y;
+        }
+    }
+    for (int k = 0; k < F.nrom; ++k) {
+      const int j = F.rom_sd[k];
+      const double ta = out[b].sd_abs2[j], td = out[b].sd_den2[j];
+#pragma unroll
+      for (int i = 0; i < kMaxSd; ++i)
+        if (i == j) {
+          s.sd_abs2[i] = ta;
+          s.sd_den2[i] = td;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxSd; ++i)
+      if (i == own_sd) {
+        s.sd_abs2[i] = own_abs2;
+        s.sd_den2[i] = own_den2;
+      }
+    decide(s, o.nsd - 1, o);
+  }
+  if (lane == 0) out[b] = s;
 }
 
 // Faces and pushes.  All subdomains share one global grid, so a Schwarz face of
@@ -96,6 +184,7 @@ struct FeArgs {
   T *v[2];
   T *a[2];
   const T *coef;           // [9 cases][26 offsets][3][3]: -K_d / m
+  T ci[234];               // the interior case's block of coef (read by scalar loads)
   T dt, half_dt, half_dt2;
   int face_src[2];         // source subdomain of the low / high face, -1 if clamped
   int npush;
@@ -104,7 +193,6 @@ struct FeArgs {
   int sd;
   Opts opts;
   double *partials;        // [batch][nblocks][2]
-  unsigned *counters;      // [batch]
   int kc, n_chunks, n_int, n_bnd, int_blocks, nblocks;
   const int *bnd_cols;     // boundary columns (ids in the layer)
   // records: [batch][ncols][len]
@@ -145,9 +233,11 @@ struct RomArgs {
   int nfaces, nexp;
   RomFaceIn<T> fin[2];
   RomExport<T> ex[2];
-  Status *status;
+  Status *status;          // this round's input status
+  Status *status_out;      // written by the decider of the round
   int sd;
   Opts opts;
+  FinishArgs finish;       // used when this is the last subdomain of the sweep
   T *rec_q;
   long long rec_every, rec_ncols;
 };

@@ -32,9 +32,6 @@ hipError_t launch_project(const T *, long long, long long, const T *, long long,
                           int, hipStream_t);
 template <typename T>
 hipError_t launch_lift(const T *, long long, long long, int, const T *, T *, long long, long long, hipStream_t);
-template <typename T>
-hipError_t launch_piphi(const T *, long long, long long, int, const int *, const T *, int, int, int, T *,
-                        hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Element stiffness of a box hex8 (hx, hy, hz), isotropic linear elasticity
@@ -133,25 +130,49 @@ int32_t Ctx::fail(int32_t code, const std::string &msg) {
   return code;
 }
 
+// Device memory comes from large 2 MiB-aligned blocks carved by the context
+// (first fit over freed chunks, no coalescing): the many small per-subdomain
+// buffers then share large pages instead of each holding its own small-page
+// allocation, which keeps the kernels' address-translation misses down.
+void *Ctx::arena_alloc(size_t bytes, int32_t *st) {
+  constexpr size_t kAlign = 256, kPage = size_t(2) << 20, kBlock = size_t(64) << 20;
+  bytes = (std::max<size_t>(bytes, 1) + kAlign - 1) / kAlign * kAlign;
+  for (auto &c : chunks)
+    if (c.free && c.bytes >= bytes) {
+      c.free = false;
+      return c.ptr;
+    }
+  if (!arena_cur || arena_used + bytes > arena_cap) {
+    const size_t cap = std::max(kBlock, (bytes + kPage - 1) / kPage * kPage);
+    void *raw = nullptr;
+    if (hipMalloc(&raw, cap + kPage) != hipSuccess) {
+      *st = OSAM_E_OOM;
+      return nullptr;
+    }
+    allocs.push_back(raw);
+    const uintptr_t a = (reinterpret_cast<uintptr_t>(raw) + kPage - 1) / kPage * kPage;
+    arena_cur = reinterpret_cast<char *>(a);
+    arena_cap = cap;
+    arena_used = 0;
+  }
+  char *p = arena_cur + arena_used;
+  arena_used += bytes;
+  chunks.push_back({p, bytes, false});
+  return p;
+}
+
 template <typename T>
 static T *dalloc(Ctx *ctx, size_t n, int32_t *st) {
-  void *p = nullptr;
-  if (n == 0) n = 1;
-  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
-    *st = OSAM_E_OOM;
-    return nullptr;
-  }
-  ctx->allocs.push_back(p);
-  return static_cast<T *>(p);
+  return static_cast<T *>(ctx->arena_alloc(n * sizeof(T), st));
 }
 
 void Ctx::dfree(void *p) {
   if (!p) return;
-  auto it = std::find(allocs.begin(), allocs.end(), p);
-  if (it != allocs.end()) {
-    hipFree(p);
-    allocs.erase(it);
-  }
+  for (auto &c : chunks)
+    if (c.ptr == p) {
+      c.free = true;
+      return;
+    }
 }
 
 size_t Ctx::esize() const { return prec == OSAM_FP64 ? 8 : 4; }
@@ -224,6 +245,7 @@ int32_t osam_ctx_create(osam_ctx **out, int32_t device, int32_t precision, int32
   }
   int32_t st = OSAM_OK;
   ctx->d_status = dalloc<Status>(ctx, batch, &st);
+  if (st == OSAM_OK) ctx->d_status_alt = dalloc<Status>(ctx, batch, &st);
   if (st != OSAM_OK) {
     osam_ctx_destroy(reinterpret_cast<osam_ctx *>(ctx));
     return st;
@@ -234,6 +256,7 @@ int32_t osam_ctx_create(osam_ctx **out, int32_t device, int32_t precision, int32
   }
   std::memset(ctx->h_status, 0, sizeof(Status) * batch);
   hipMemcpy(ctx->d_status, ctx->h_status, sizeof(Status) * batch, hipMemcpyHostToDevice);
+  hipMemcpy(ctx->d_status_alt, ctx->h_status, sizeof(Status) * batch, hipMemcpyHostToDevice);
   ctx->initialized.assign(batch, 0);
   *out = reinterpret_cast<osam_ctx *>(ctx);
   return OSAM_OK;
@@ -321,6 +344,7 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
         for (int q = 0; q < 3; ++q) C[(cse * 26 + d26) * 9 + p * 3 + q] = 0.0;
     }
   }
+  std::copy(C.begin() + 4 * 234, C.begin() + 5 * 234, sd->ci);
   int32_t st = OSAM_OK;
   sd->coef = ctx->alloc_t(C.size(), &st);
   if (st) return ctx->fail(st, "out of device memory");
@@ -345,9 +369,6 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   sd->bnd_cols = dalloc<int>(ctx, bnd.size(), &st);
   if (st) return ctx->fail(st, "out of device memory");
   HIPCHK(hipMemcpy(sd->bnd_cols, bnd.data(), bnd.size() * sizeof(int), hipMemcpyHostToDevice));
-  sd->counters = dalloc<unsigned>(ctx, ctx->batch, &st);
-  if (st) return ctx->fail(st, "out of device memory");
-  HIPCHK(hipMemset(sd->counters, 0, sizeof(unsigned) * ctx->batch));
   ctx->choose_fe_launch(*sd, 0, 0);
   sd->partials = dalloc<double>(ctx, (size_t)ctx->batch * sd->max_nblocks * 2, &st);
   if (st) return ctx->fail(st, "out of device memory");
@@ -520,6 +541,30 @@ int32_t osam_get_timing(osam_ctx *c, int32_t sd, double *ms, int64_t *launches) 
   }
   if (ms) *ms = tot;
   if (launches) *launches = n;
+  return OSAM_OK;
+}
+
+int32_t osam_set_fe_launch(osam_ctx *c, int32_t sd, int32_t block, int32_t kc) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  ctx->err.clear();
+  if (sd < 0 || sd >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  Subdomain &s = *ctx->sds[sd];
+  if (s.rom) return ctx->fail(OSAM_E_INVALID, "not a FOM subdomain");
+  if (!(block == 0 || block == 64 || block == 128 || block == 256) || kc < 0)
+    return ctx->fail(OSAM_E_INVALID, "block must be 0, 64, 128 or 256 and kc >= 0");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->choose_fe_launch(s, block, kc);
+  return OSAM_OK;
+}
+
+int32_t osam_get_fe_launch(osam_ctx *c, int32_t sd, int32_t *block, int32_t *kc) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  if (sd < 0 || sd >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  const Subdomain &s = *ctx->sds[sd];
+  if (block) *block = s.fe_block;
+  if (kc) *kc = s.fe_kc;
   return OSAM_OK;
 }
 

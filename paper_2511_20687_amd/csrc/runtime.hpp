@@ -37,9 +37,9 @@ struct Subdomain {
   // FOM buffers
   void *u[3] = {}, *v[2] = {}, *a[2] = {};
   void *coef = nullptr;
+  double ci[234];              // interior case of coef, for the kernel arguments
   int *bnd_cols = nullptr;
   int n_int = 0, n_bnd = 0;
-  unsigned *counters = nullptr;
   double *partials = nullptr;
   int fe_block = 256, fe_kc = 8, fe_chunks = 1, fe_int_blocks = 0, fe_nblocks = 0, max_nblocks = 0;
   // OpInf
@@ -65,9 +65,19 @@ struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<std::unique_ptr<Subdomain>> sds;
-  Status *d_status = nullptr;
+  Status *d_status = nullptr;       // status every kernel of the next round reads
+  Status *d_status_alt = nullptr;   // written by that round's decider; swapped after each round
   Status *h_status = nullptr;   // pinned mirror
-  std::vector<void *> allocs;
+  std::vector<void *> allocs;   // hipMalloc'ed arena blocks (freed at destroy)
+  struct Chunk {
+    char *ptr;
+    size_t bytes;
+    bool free;
+  };
+  std::vector<Chunk> chunks;    // carved pieces of the blocks
+  char *arena_cur = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  void *arena_alloc(size_t bytes, int32_t *st);
   std::vector<char> initialized;
   bool coupled = false;
   bool wired = false;

@@ -212,6 +212,8 @@ class Workload:
     # displacement components held at zero on the lateral faces: x and y, as for
     # the effectively-1D bar of Sec. 5.1 (empty = traction-free lateral faces)
     lateral_fix: Tuple[int, ...] = (0, 1)
+    # width s of the seeded Gaussian pulses (Sec. 5.1's Symmetric Gaussian uses 0.02)
+    pulse_width: float = 0.02
 
     @property
     def layers(self) -> List[Tuple[int, int]]:
@@ -226,7 +228,8 @@ class Workload:
         return replace(self, bar=replace(self.bar, nx=nx, ny=ny, nz=nz), **kw)
 
 
-CFG1 = Workload("fom_fom_bar_4x4x40_f64", Bar(4, 4, 40), 2, ("fom", "fom"), 1000, "f64")
+CFG1 = Workload("fom_fom_bar_4x4x40_f64", Bar(4, 4, 40), 2, ("fom", "fom"), 1000, "f64",
+                pulse_width=0.05)
 CFG2 = Workload("fom_opinf_bar_24x24x240_r40", Bar(24, 24, 240), 2, ("fom", "opinf"), 5000,
                 "f32", form="linear", r=40, seed=2, train_steps=2000, tol_rel=1.0e-6)
 CFG3 = Workload("opinf_opinf_bar_48x48x480_r100_b256", Bar(48, 48, 480), 2, ("opinf", "opinf"),

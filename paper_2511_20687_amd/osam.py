@@ -26,6 +26,7 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "create_subdomain", "osam_couple", "osam_set_initial", "osam_get_state",
             "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
             "osam_get_opinf", "schwarz_step", "run", "osam_set_timing", "osam_get_timing",
+            "osam_set_fe_launch", "osam_get_fe_launch",
             "osam_sync"]
 
 
@@ -119,6 +120,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_set_timing.restype = i32
     lib.osam_get_timing.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64)]
     lib.osam_get_timing.restype = i32
+    lib.osam_set_fe_launch.argtypes = [vp, i32, i32, i32]
+    lib.osam_set_fe_launch.restype = i32
+    lib.osam_get_fe_launch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
+    lib.osam_get_fe_launch.restype = i32
     lib.osam_sync.argtypes = [vp]
     lib.osam_sync.restype = i32
     _lib = lib
@@ -311,6 +316,14 @@ class Context:
         ms, n = C.c_double(), C.c_int64()
         self._check(self.lib.osam_get_timing(self.h, sd, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def set_fe_launch(self, sd: int, block: int = 0, kc: int = 0):
+        self._check(self.lib.osam_set_fe_launch(self.h, sd, block, kc))
+
+    def get_fe_launch(self, sd: int):
+        b, k = C.c_int32(), C.c_int32()
+        self._check(self.lib.osam_get_fe_launch(self.h, sd, C.byref(b), C.byref(k)))
+        return b.value, k.value
 
     def sync(self):
         self._check(self.lib.osam_sync(self.h))

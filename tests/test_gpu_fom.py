@@ -34,20 +34,23 @@ def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s
     return ctx, [(ru.cpu().numpy(), None if rs is None else rs.cpu().numpy()) for ru, rs in recs], info
 
 
+@pytest.mark.parametrize("lateral", ["workload", "traction-free"])
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
-def test_cfg1_fom_fom_matches_oracle(precision, tol):
-    """Bar 4x4x40, two slabs with 20% overlap, 1000 explicit steps."""
+def test_cfg1_fom_fom_matches_oracle(precision, tol, lateral):
+    """Bar 4x4x40, two slabs with 20% overlap, 1000 explicit steps, pulse (1e-3, 0.25, 0.05);
+    lateral faces as in the workload (x, y held) and traction-free."""
     w = CFG1
     bar, dt, layers = w.bar, w.dt, w.layers
-    u0 = Pulse().u0(bar)
+    lf = w.lateral_fix if lateral == "workload" else ()
+    u0 = Pulse(1e-3, 0.25, w.pulse_width).u0(bar)
     v0 = np.zeros_like(u0)
     n = w.steps
-    print(f"[cfg1 {precision}] oracle", flush=True)
-    models, ref = oracle_fom_coupled(bar, layers, dt, u0, v0, n)
-    print(f"[cfg1 {precision}] gpu", flush=True)
-    ctx, recs, info = _lib_run(bar, layers, dt, u0, v0, n, precision)
-    for i, (lo, hi) in enumerate(layers):
-        got = recs[i][0][0][:, lib_free_index(bar, lo, hi)]
+    print(f"[cfg1 {precision} {lateral}] oracle", flush=True)
+    models, ref = oracle_fom_coupled(bar, layers, dt, u0, v0, n, lateral_fix=lf)
+    print(f"[cfg1 {precision} {lateral}] gpu", flush=True)
+    ctx, recs, info = _lib_run(bar, layers, dt, u0, v0, n, precision, lateral_fix=lf)
+    for i, m in enumerate(models):
+        got = recs[i][0][0][:, lib_index_of(m)]
         err = rel_err(got, ref["u"][i])
         print(f"subdomain {i}: rel err {err:.3e}")
         assert err <= tol
