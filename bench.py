@@ -148,6 +148,8 @@ def main():
     ctx.set_timing(False)
     fe_avg_us = 1e3 * fe_ms / max(fe_launches, 1)
     fe_gbs = FE_BYTES_PER_DOF * fe_dofs / (fe_avg_us * 1e-6) / 1e9
+    from paper_2511_20687_amd.profiling import read_traffic
+    traffic_bytes, traffic_src = read_traffic()
 
     # ---- accuracy vs FOM-FOM and FOM-FOM throughput on the same GPU ----
     every = 10
@@ -224,9 +226,11 @@ def main():
         "train_run_s": t_train,
         "learn_s": t_learn,
         "roofline": {"bound": "hbm", "achieved": fe_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fe_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": fe_gbs / HBM_PEAK_GBS, "traffic": traffic_bytes,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_source": traffic_src,
                      "kernel": "fe_kernel<float, step>", "bytes_per_dof": FE_BYTES_PER_DOF,
-                     "dofs_per_launch": fe_dofs},
+                     "dofs_per_launch": fe_dofs, "algorithmic_bytes_per_launch": FE_BYTES_PER_DOF * fe_dofs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

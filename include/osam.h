@@ -209,8 +209,9 @@ int32_t schwarz_step(osam_ctx *ctx, const osam_schwarz_opts *opts, osam_instance
 int32_t run(osam_ctx *ctx, int64_t n_steps, const osam_schwarz_opts *opts, osam_instance_info *info);
 
 /* Kernel timing: with enable != 0, every Schwarz-step kernel launch of every
- * subdomain is bracketed by HIP events on the context stream (adds a little host
- * overhead; off by default).  Enabling (again) clears the accumulated times. */
+ * subdomain records a pair of HIP events stamped with that kernel's own start
+ * and end (hipExtLaunchKernel; a little host overhead, off by default).
+ * Enabling (again) clears the accumulated times. */
 int32_t osam_set_timing(osam_ctx *ctx, int32_t enable);
 /* Device time (ms) summed over the timed launches of subdomain sd's step
  * kernel and their number (synchronises the stream). */

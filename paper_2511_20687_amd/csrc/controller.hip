@@ -12,8 +12,10 @@
 
 namespace osam {
 
-template <typename T> hipError_t launch_fe(const FeArgs<T> &, int, int, int, hipStream_t);
-template <typename T> hipError_t launch_rom(const RomArgs<T> &, int, hipStream_t);
+template <typename T>
+hipError_t launch_fe(const FeArgs<T> &, int, int, int, hipStream_t, hipEvent_t = nullptr, hipEvent_t = nullptr);
+template <typename T>
+hipError_t launch_rom(const RomArgs<T> &, int, hipStream_t, hipEvent_t = nullptr, hipEvent_t = nullptr);
 hipError_t launch_finish(const Status *, Status *, const FinishArgs &, const Opts &, int, hipStream_t);
 template <typename T>
 hipError_t launch_project(const T *, long long, long long, const T *, long long, long long, double *, int,
@@ -487,17 +489,17 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.face_off_hi = s.face_off_hi;
 }
 
-int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode) {
+int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0, hipEvent_t ev1) {
   Subdomain &s = *sds[sdi];
   hipError_t e;
   if (prec == OSAM_FP64) {
     FeArgs<double> A;
     fill_fe_args<double>(*this, s, sdi, o, A);
-    e = launch_fe<double>(A, batch, s.fe_block, mode, stream);
+    e = launch_fe<double>(A, batch, s.fe_block, mode, stream, ev0, ev1);
   } else {
     FeArgs<float> A;
     fill_fe_args<float>(*this, s, sdi, o, A);
-    e = launch_fe<float>(A, batch, s.fe_block, mode, stream);
+    e = launch_fe<float>(A, batch, s.fe_block, mode, stream, ev0, ev1);
   }
   if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("fe kernel: ") + hipGetErrorString(e));
   return OSAM_OK;
@@ -569,17 +571,17 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
   A.rec_ncols = s.rec.n_cols;
 }
 
-int32_t Ctx::launch_rom_sd(int sdi, const Opts &o) {
+int32_t Ctx::launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0, hipEvent_t ev1) {
   Subdomain &s = *sds[sdi];
   hipError_t e;
   if (prec == OSAM_FP64) {
     RomArgs<double> A;
     fill_rom_args<double>(*this, s, sdi, o, A);
-    e = launch_rom<double>(A, batch, stream);
+    e = launch_rom<double>(A, batch, stream, ev0, ev1);
   } else {
     RomArgs<float> A;
     fill_rom_args<float>(*this, s, sdi, o, A);
-    e = launch_rom<float>(A, batch, stream);
+    e = launch_rom<float>(A, batch, stream, ev0, ev1);
   }
   if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("rom kernel: ") + hipGetErrorString(e));
   return OSAM_OK;
@@ -596,20 +598,18 @@ hipEvent_t Ctx::next_event() {
 
 int32_t Ctx::launch_round(const Opts &o) {
   for (size_t i = 0; i < sds.size(); ++i) {
-    int a = -1;
+    // timing: the events are stamped with the kernel's own start and end
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing) {
-      a = (int)ev_next;
-      hipEvent_t e = next_event();
-      if (!e || hipEventRecord(e, stream) != hipSuccess) return fail(OSAM_E_HIP, "event record");
-    }
-    int32_t st = sds[i]->rom ? launch_rom_sd((int)i, o) : launch_fe_sd((int)i, o, 0);
-    if (st) return st;
-    if (timing) {
+      const int a = (int)ev_next;
+      e0 = next_event();
       const int b = (int)ev_next;
-      hipEvent_t e = next_event();
-      if (!e || hipEventRecord(e, stream) != hipSuccess) return fail(OSAM_E_HIP, "event record");
+      e1 = next_event();
+      if (!e0 || !e1) return fail(OSAM_E_HIP, "event create");
       ev_used.push_back({(int)i, {a, b}});
     }
+    int32_t st = sds[i]->rom ? launch_rom_sd((int)i, o, e0, e1) : launch_fe_sd((int)i, o, 0, e0, e1);
+    if (st) return st;
   }
   // a ROM kernel that ends the sweep takes the decision itself
   if (!sds.back()->rom) {

@@ -34,6 +34,8 @@
 //    FP64 partial sums, reduced in a fixed order after the sweep.
 //  * Buffer roles rotate with the instance's accepted-step count, so each
 //    instance advances at its own pace and the host never waits per step.
+#include <hip/hip_ext.h>
+
 #include "osam_device.hpp"
 
 namespace osam {
@@ -357,21 +359,23 @@ hipError_t launch_finish(const Status *in, Status *out, const FinishArgs &F, con
 }
 
 // Host-side launcher -------------------------------------------------------
+// ev0/ev1 (optional): events stamped with the kernel's own start and end.
 template <typename T>
-hipError_t launch_fe(const FeArgs<T> &A, int batch, int block, int mode, hipStream_t s) {
+hipError_t launch_fe(const FeArgs<T> &A, int batch, int block, int mode, hipStream_t s, hipEvent_t ev0,
+                     hipEvent_t ev1) {
   dim3 grid(A.nblocks, batch);
   const bool one = A.kc == 1;
   if (mode == kModeInit) {
-    if (one) hipLaunchKernelGGL((fe_kernel<T, kModeInit, true>), grid, dim3(block), 0, s, A);
-    else hipLaunchKernelGGL((fe_kernel<T, kModeInit, false>), grid, dim3(block), 0, s, A);
+    if (one) hipExtLaunchKernelGGL((fe_kernel<T, kModeInit, true>), grid, dim3(block), 0, s, ev0, ev1, 0, A);
+    else hipExtLaunchKernelGGL((fe_kernel<T, kModeInit, false>), grid, dim3(block), 0, s, ev0, ev1, 0, A);
   } else {
-    if (one) hipLaunchKernelGGL((fe_kernel<T, kModeStep, true>), grid, dim3(block), 0, s, A);
-    else hipLaunchKernelGGL((fe_kernel<T, kModeStep, false>), grid, dim3(block), 0, s, A);
+    if (one) hipExtLaunchKernelGGL((fe_kernel<T, kModeStep, true>), grid, dim3(block), 0, s, ev0, ev1, 0, A);
+    else hipExtLaunchKernelGGL((fe_kernel<T, kModeStep, false>), grid, dim3(block), 0, s, ev0, ev1, 0, A);
   }
   return hipGetLastError();
 }
 
-template hipError_t launch_fe<float>(const FeArgs<float> &, int, int, int, hipStream_t);
-template hipError_t launch_fe<double>(const FeArgs<double> &, int, int, int, hipStream_t);
+template hipError_t launch_fe<float>(const FeArgs<float> &, int, int, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_fe<double>(const FeArgs<double> &, int, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace osam

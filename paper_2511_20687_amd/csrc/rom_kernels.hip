@@ -14,6 +14,8 @@
 //
 // This variant serves small batches: H (q (x) q) is evaluated with one wave per
 // output row from the compressed quadratic vector staged in LDS.
+#include <hip/hip_ext.h>
+
 #include "osam_device.hpp"
 
 namespace osam {
@@ -330,17 +332,17 @@ size_t rom_smem_bytes(int r, int rs, int r2) {
 }
 
 template <typename T>
-hipError_t launch_rom(const RomArgs<T> &A, int batch, hipStream_t s) {
+hipError_t launch_rom(const RomArgs<T> &A, int batch, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const size_t smem = rom_smem_bytes<T>(A.r, A.rs, A.r2);
   if (smem > 65536) return hipErrorInvalidValue;
   int rows = 0;
   for (int e = 0; e < A.nexp; ++e) rows = rows > 3 * A.ex[e].npl ? rows : 3 * A.ex[e].npl;
   const int G = rows > 0 ? (rows + kRomThreads - 1) / kRomThreads : 1;
-  hipLaunchKernelGGL(rom_kernel<T>, dim3(G, batch), dim3(kRomThreads), smem, s, A);
+  hipExtLaunchKernelGGL(rom_kernel<T>, dim3(G, batch), dim3(kRomThreads), (uint32_t)smem, s, ev0, ev1, 0, A);
   return hipGetLastError();
 }
-template hipError_t launch_rom<float>(const RomArgs<float> &, int, hipStream_t);
-template hipError_t launch_rom<double>(const RomArgs<double> &, int, hipStream_t);
+template hipError_t launch_rom<float>(const RomArgs<float> &, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_rom<double>(const RomArgs<double> &, int, hipStream_t, hipEvent_t, hipEvent_t);
 template size_t rom_smem_bytes<float>(int, int, int);
 template size_t rom_smem_bytes<double>(int, int, int);
 

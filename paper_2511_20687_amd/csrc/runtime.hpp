@@ -113,8 +113,8 @@ struct Ctx {
   int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info);
   int32_t launch_round(const Opts &o);
   hipEvent_t next_event();
-  int32_t launch_fe_sd(int sdi, const Opts &o, int mode);
-  int32_t launch_rom_sd(int sdi, const Opts &o);
+  int32_t launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+  int32_t launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
   int32_t learn(int sd, const osam_opinf_desc &d);
 };
 

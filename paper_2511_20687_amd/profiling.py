@@ -1,0 +1,142 @@
+"""Profiling helpers for the FE step kernel on the 24x24x240 bar (FOM-OpInf coupling).
+
+Used under rocprofv3 to produce the summaries in profiles/:
+
+    python -m paper_2511_20687_amd.profiling workload [steps]   # coupled run, synthetic r=40 OpInf
+    python -m paper_2511_20687_amd.profiling copy               # plain copy of 256 MiB (calibration)
+    python -m paper_2511_20687_amd.profiling summarize OUTDIR   # counters -> profiles/*.txt
+
+The workload runs exactly the FE kernel work of the bench (same subdomain, launch shape and
+coupling pattern); the OpInf operators are seeded synthetic ones of the learned sizes, so no
+training run is needed.  The calibration copy lets the FETCH_SIZE / WRITE_SIZE counters
+be scaled to bytes: scale = known bytes / counted bytes of the copy kernel.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 256 << 20
+FE_SOURCES = ("paper_2511_20687_amd/csrc/fe_kernels.hip", "paper_2511_20687_amd/csrc/osam_device.hpp")
+
+
+def fe_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in FE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(steps: int = 200) -> None:
+    import torch
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import CFG2, draw_pulses, synthetic_rom
+    w = CFG2
+    ctx = osam.Context(0, w.precision, 1)
+    osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
+    z = ctx.sizes(1)
+    R = synthetic_rom(w.seed, z["n_free"], z["n_sch"], w.r, 1, w.dt)
+    ctx.set_opinf(1, R["Phi"], R["PhiS"], R["A"], None, R["B"])
+    u0 = draw_pulses(w.seed, 1, s=w.pulse_width)[0].u0(w.bar)
+    ctx.set_initial(0, u0, np.zeros_like(u0))
+    info = ctx.run(steps, osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel))
+    torch.cuda.synchronize()
+    print(f"workload done: {steps} steps, {info[0]['total_iters']} Schwarz iterations, "
+          f"{z['n_free']} FE DOFs", flush=True)
+
+
+def copy() -> None:
+    import torch
+    n = COPY_BYTES // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copy done: {COPY_BYTES} bytes x 3", flush=True)
+
+
+def _counter_rows(d: str):
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def _mean_counter(rows, name_part, counter):
+    vals = [float(r["Counter_Value"]) for r in rows
+            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def summarize(outdir: str) -> None:
+    """outdir holds the rocprofv3 results of four passes: fetch_copy, write_copy, fetch_fe, write_fe."""
+    get = lambda sub: _counter_rows(os.path.join(outdir, sub))
+    fc, nfc = _mean_counter(get("fetch_copy"), "copy", "FETCH_SIZE")
+    wc, nwc = _mean_counter(get("write_copy"), "copy", "WRITE_SIZE")
+    ff, nff = _mean_counter(get("fetch_fe"), "fe_kernel<float, 0", "FETCH_SIZE")
+    wf, nwf = _mean_counter(get("write_fe"), "fe_kernel<float, 0", "WRITE_SIZE")
+    kib = COPY_BYTES / 1024.0
+    sf = kib / fc if fc else None
+    sw = kib / wc if wc else None
+    fetch_b = ff * sf * 1024 if (ff and sf) else None
+    write_b = wf * sw * 1024 if (wf and sw) else None
+    lines = [
+        "# FE step kernel HBM traffic (rocprofv3 --pmc), 24x24x240 bar, Omega_1 268125 FE DOFs, FP32",
+        f"kernel_source_sha256_16={fe_source_hash()}",
+        f"copy_bytes={COPY_BYTES}",
+        f"copy_fetch_kib_per_dispatch={fc} (n={nfc})",
+        f"copy_write_kib_per_dispatch={wc} (n={nwc})",
+        f"fetch_scale={sf}",
+        f"write_scale={sw}",
+        f"fe_fetch_kib_per_dispatch={ff} (n={nff})",
+        f"fe_write_kib_per_dispatch={wf} (n={nwf})",
+        f"fe_fetch_bytes_per_launch={fetch_b}",
+        f"fe_write_bytes_per_launch={write_b}",
+        f"fe_traffic_bytes_per_launch={None if fetch_b is None or write_b is None else fetch_b + write_b}",
+        "algorithmic_bytes_per_launch=" + str(28 * 268125),
+    ]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    path = os.path.join(ROOT, "profiles", "fe_kernel_bar24x24x240_traffic.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def read_traffic():
+    """(traffic bytes per FE launch, details) from the committed summary, or (None, reason)
+    when it is missing or was taken for another version of the FE kernel source."""
+    path = os.path.join(ROOT, "profiles", "fe_kernel_bar24x24x240_traffic.txt")
+    if not os.path.exists(path):
+        return None, "no PMC summary"
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k] = v.split(" ")[0]
+    if kv.get("kernel_source_sha256_16") != fe_source_hash():
+        return None, "FE kernel changed since the counters were taken"
+    try:
+        return float(kv["fe_traffic_bytes_per_launch"]), path
+    except (KeyError, ValueError):
+        return None, "incomplete PMC summary"
+
+
+if __name__ == "__main__":
+    cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
+    if cmd == "workload":
+        workload(int(sys.argv[2]) if len(sys.argv) > 2 else 200)
+    elif cmd == "copy":
+        copy()
+    elif cmd == "summarize":
+        summarize(sys.argv[2])
+    else:
+        raise SystemExit(f"unknown command {cmd}")
