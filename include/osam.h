@@ -111,6 +111,12 @@ int32_t osam_couple(osam_ctx *ctx);
  * q''0 = f(q0, g^0) (OpInf, Sec. 4.2).  Resets the instance's step counter. */
 int32_t osam_set_initial(osam_ctx *ctx, int32_t inst, const double *u0, const double *v0);
 
+/* Replace the reduced initial state (q0, q'0) of OpInf subdomain sd, instance
+ * inst, after osam_set_initial and before the first step (OSAM_E_ORDER otherwise):
+ * q''0 = f(q0, g^0) is recomputed with the g^0 of the initial condition, and the
+ * FOM neighbours' faces at t_1 with it.  Host float64 [r] each. */
+int32_t osam_set_reduced(osam_ctx *ctx, int32_t sd, int32_t inst, const double *q0, const double *qd0);
+
 /* Current accepted state of subdomain sd, instance inst, as host float64
  * [3][n_nodes] arrays (any may be NULL).  OpInf subdomains return the lifted
  * field Phi q on free DOFs, the imposed Schwarz data and zero Dirichlet DOFs. */
@@ -207,6 +213,43 @@ int32_t schwarz_step(osam_ctx *ctx, const osam_schwarz_opts *opts, osam_instance
  * Returns OSAM_E_NONFINITE if any instance went non-finite (that instance stops
  * at its last finite step; the others complete).  info: [batch] or NULL. */
 int32_t run(osam_ctx *ctx, int64_t n_steps, const osam_schwarz_opts *opts, osam_instance_info *info);
+
+/* Trajectory misfit of the coupled rollout and its gradient (discrete adjoint).
+ *
+ * Not a passage of the paper: a calibration tool around its method.  With the
+ * explicit scheme (Sec. 4.1, beta = 0) every accepted step of the multiplicative
+ * Schwarz loop (Alg. 1) is the explicit map in which each subdomain advances
+ * with the neighbours' displacements at t_k (their Newmark predictors) as
+ * Schwarz data (Sec. 4.2: Pi Phi q for an OpInf source, Phi_S^T s for an OpInf
+ * destination).  run_adjoint differentiates that map exactly (the iteration
+ * counts and the convergence test do not enter it).
+ *
+ *   J = 1/2 sum_{k = every, 2 every, ... <= n_steps} [ sum_FOM ||u_k - u_obs,k||^2
+ *                                                     + sum_OpInf ||q_k - q_obs,k||^2 ]
+ *
+ * over the free DOFs of FOM subdomains and the reduced coordinates of OpInf
+ * subdomains (for an orthonormal Phi, ||Phi q - u||^2 = ||q - Phi^T u||^2 + const).
+ * The rollout starts from instance 0's current accepted state (batch must be 1)
+ * and leaves the context's state unchanged.  Gradients are taken with respect to
+ * the OpInf operators A, H, B, c and the initial state (q0, q'0 of OpInf, u0, v0 on
+ * FOM free DOFs); the initial accelerations are functions of these, the Schwarz
+ * data at t_0 are constants.  The state is stored every checkpoint_every steps
+ * and each segment is recomputed once. */
+typedef struct {
+  int64_t every;              /* observed steps k = every, 2 every, ... (every >= 1) */
+  const void *obs[8];         /* per subdomain id, device, context precision, or NULL:
+                                 FOM [n_obs][n_free] (free-DOF layout), OpInf [n_obs][r],
+                                 n_obs = n_steps / every */
+} osam_misfit;
+typedef struct {
+  double *dA[8], *dH[8], *dB[8], *dc[8];  /* OpInf subdomains: host float64, layouts of
+                                             osam_set_opinf (column-major); NULL = skip */
+  double *dq0[8], *dqd0[8];               /* OpInf: host float64 [r] */
+  void *du0[8], *dv0[8];                  /* FOM: device [n_free], context precision */
+} osam_grads;
+/* *J receives the misfit.  OSAM_E_INVALID for batch != 1 or bad sizes. */
+int32_t run_adjoint(osam_ctx *ctx, int64_t n_steps, int64_t checkpoint_every, const osam_misfit *misfit,
+                    double *J, const osam_grads *grads);
 
 /* Kernel timing: with enable != 0, every Schwarz-step kernel launch of every
  * subdomain records a pair of HIP events stamped with that kernel's own start

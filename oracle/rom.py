@@ -150,7 +150,7 @@ class OpInfModel:
 
     def field(self, st: RomState) -> np.ndarray:
         """Lifted nodal field: Phi q on free DOFs, imposed Schwarz data, zero Dirichlet."""
-        u = np.zeros(self.n_dofs, dtype=np.result_type(st.q, self.Phi))
+        u = np.zeros(self.n_dofs, dtype=np.result_type(st.q, self.Phi, st.s))
         u[self.free_dofs] = self.Phi @ st.q
         u[self.sch_dofs] = st.s
         return u

@@ -251,6 +251,54 @@ static void kron2_host(const std::vector<double> &q, std::vector<double> &k) {
     for (int j = i; j < r; ++j) k.push_back(q[i] * q[j]);
 }
 
+// Reduced initial state of OpInf subdomain i, instance inst: q0, q'0 given,
+// q''0 = f(q0, g^0) with the stored g^0, the first recorded column, and the
+// FOM neighbours' faces at t_1 = (Pi Phi) of the reduced predictor.
+int32_t Ctx::rom_start(int i, int inst, const std::vector<double> &q, const std::vector<double> &qd) {
+  Subdomain &d = *sds[i];
+  int32_t st = OSAM_OK;
+  const std::vector<double> &gh = d.gh0[inst];
+  std::vector<double> qdd(d.r, 0.0), k2;
+  kron2_host(q, k2);
+  const int r2 = d.r * (d.r + 1) / 2;
+  for (int i2 = 0; i2 < d.r; ++i2) {
+    double s = d.oh.c.empty() ? 0.0 : d.oh.c[i2];
+    for (int j = 0; j < d.r; ++j) s += d.oh.A[(size_t)j * d.r + i2] * q[j];
+    if (d.oh.quadratic)
+      for (int m = 0; m < r2; ++m) s += d.oh.H[(size_t)m * d.r + i2] * k2[m];
+    for (int l = 0; l < d.rs; ++l) s += d.oh.B[(size_t)l * d.r + i2] * gh[l];
+    qdd[i2] = s;
+  }
+  const size_t off = (size_t)inst * d.r * esize();
+  if ((st = upload((char *)d.q[0] + off, q.data(), d.r))) return st;
+  if ((st = upload((char *)d.qd[0] + off, qd.data(), d.r))) return st;
+  if ((st = upload((char *)d.qdd[0] + off, qdd.data(), d.r))) return st;
+  if (d.rec.every > 0 && d.rec.u && d.rec.n_cols > 0) {
+    if ((st = upload((char *)d.rec.u + (size_t)inst * d.rec.n_cols * d.r * esize(), q.data(), d.r))) return st;
+  }
+  std::vector<double> q1(d.r);
+  for (int k = 0; k < d.r; ++k) q1[k] = q[k] + d.desc.dt * qd[k] + 0.5 * d.desc.dt * d.desc.dt * qdd[k];
+  int e = 0;
+  for (size_t i2 = 0; i2 < sds.size(); ++i2) {
+    Subdomain &fd = *sds[i2];
+    if (fd.rom) continue;
+    for (int f = 0; f < 2; ++f) {
+      if (fd.face_type[f] == kFaceClamped || fd.proj[f].src != i) continue;
+      const std::vector<double> &pp = d.piphi_h[e++];
+      const int n = 3 * fd.npl;
+      std::vector<double> sv(n, 0.0);
+      for (int k = 0; k < d.r; ++k)
+        for (int m = 0; m < n; ++m) sv[m] += pp[(size_t)k * n + m] * q1[k];
+      const size_t lay = (size_t)(f == 0 ? 0 : fd.nzs) * fd.npl;
+      for (int c = 0; c < 3; ++c) {
+        const size_t o = ((size_t)inst * fd.is + (size_t)c * fd.cs + lay) * esize();
+        if ((st = upload((char *)fd.u[1] + o, sv.data() + (size_t)c * fd.npl, fd.npl))) return st;
+      }
+    }
+  }
+  return OSAM_OK;
+}
+
 int32_t Ctx::set_initial(int inst, const double *u0g, const double *v0g) {
   int32_t st = wire();
   if (st) return st;
@@ -325,47 +373,9 @@ int32_t Ctx::set_initial(int inst, const double *u0g, const double *v0g) {
         for (long long m = 0; m < ns; ++m) s += d.oh.PhiS[(size_t)k * ns + m] * s0[m];
         gh[k] = s;
       }
-      std::vector<double> qdd(d.r, 0.0), k2;
-      kron2_host(q, k2);
-      const int r2 = d.r * (d.r + 1) / 2;
-      for (int i2 = 0; i2 < d.r; ++i2) {
-        double s = d.oh.c.empty() ? 0.0 : d.oh.c[i2];
-        for (int j = 0; j < d.r; ++j) s += d.oh.A[(size_t)j * d.r + i2] * q[j];
-        if (d.oh.quadratic)
-          for (int m = 0; m < r2; ++m) s += d.oh.H[(size_t)m * d.r + i2] * k2[m];
-        for (int l = 0; l < d.rs; ++l) s += d.oh.B[(size_t)l * d.r + i2] * gh[l];
-        qdd[i2] = s;
-      }
-      const size_t off = (size_t)inst * d.r * esize();
-      if ((st = upload((char *)d.q[0] + off, q.data(), d.r))) return st;
-      if ((st = upload((char *)d.qd[0] + off, qd.data(), d.r))) return st;
-      if ((st = upload((char *)d.qdd[0] + off, qdd.data(), d.r))) return st;
-      if (d.rec.every > 0 && d.rec.u && d.rec.n_cols > 0) {
-        if ((st = upload((char *)d.rec.u + (size_t)inst * d.rec.n_cols * d.r * esize(), q.data(), d.r)))
-          return st;
-      }
-      // the FOM neighbours' faces at t_1: (Pi Phi) of the reduced predictor
-      std::vector<double> q1(d.r);
-      for (int k = 0; k < d.r; ++k)
-        q1[k] = q[k] + d.desc.dt * qd[k] + 0.5 * d.desc.dt * d.desc.dt * qdd[k];
-      int e = 0;
-      for (size_t i2 = 0; i2 < sds.size(); ++i2) {
-        Subdomain &fd = *sds[i2];
-        if (fd.rom) continue;
-        for (int f = 0; f < 2; ++f) {
-          if (fd.face_type[f] == kFaceClamped || fd.proj[f].src != (int)i) continue;
-          const std::vector<double> &pp = d.piphi_h[e++];
-          const int n = 3 * fd.npl;
-          std::vector<double> sv(n, 0.0);
-          for (int k = 0; k < d.r; ++k)
-            for (int m = 0; m < n; ++m) sv[m] += pp[(size_t)k * n + m] * q1[k];
-          const size_t lay = (size_t)(f == 0 ? 0 : fd.nzs) * fd.npl;
-          for (int c = 0; c < 3; ++c) {
-            const size_t off = ((size_t)inst * fd.is + (size_t)c * fd.cs + lay) * esize();
-            if ((st = upload((char *)fd.u[1] + off, sv.data() + (size_t)c * fd.npl, fd.npl))) return st;
-          }
-        }
-      }
+      if ((int)d.gh0.size() < batch) d.gh0.resize(batch);
+      d.gh0[inst] = gh;
+      if ((st = rom_start((int)i, inst, q, qd))) return st;
       // own faces fed by a FOM: role U0 (t_0) holds the IC
       for (int f = 0; f < 2; ++f) {
         if (!d.sface[f][0]) continue;

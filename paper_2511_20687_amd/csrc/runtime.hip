@@ -544,6 +544,21 @@ int32_t osam_get_timing(osam_ctx *c, int32_t sd, double *ms, int64_t *launches) 
   return OSAM_OK;
 }
 
+int32_t osam_set_reduced(osam_ctx *c, int32_t sdi, int32_t inst, const double *q0, const double *qd0) {
+  if (!c || !q0 || !qd0) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  ctx->err.clear();
+  if (sdi < 0 || sdi >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  if (inst < 0 || inst >= ctx->batch) return ctx->fail(OSAM_E_INVALID, "bad instance");
+  Subdomain &d = *ctx->sds[sdi];
+  if (!d.rom) return ctx->fail(OSAM_E_INVALID, "not an OpInf subdomain");
+  if (!ctx->initialized[inst] || !(ctx->h_status[inst].flags & kNeedInit) || (int)d.gh0.size() <= inst)
+    return ctx->fail(OSAM_E_ORDER, "osam_set_reduced must follow osam_set_initial before any step");
+  std::vector<double> q(q0, q0 + d.r), qd(qd0, qd0 + d.r);
+  hipSetDevice(ctx->device);
+  return ctx->rom_start(sdi, inst, q, qd);
+}
+
 int32_t osam_set_fe_launch(osam_ctx *c, int32_t sd, int32_t block, int32_t kc) {
   if (!c) return OSAM_E_INVALID;
   Ctx *ctx = reinterpret_cast<Ctx *>(c);

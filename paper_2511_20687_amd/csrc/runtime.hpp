@@ -38,6 +38,7 @@ struct Subdomain {
   void *u[3] = {}, *v[2] = {}, *a[2] = {};
   void *coef = nullptr;
   double ci[234];              // interior case of coef, for the kernel arguments
+  std::vector<std::vector<double>> gh0;   // OpInf: g^ at t_0 per instance (from the initial condition)
   int *bnd_cols = nullptr;
   int n_int = 0, n_bnd = 0;
   double *partials = nullptr;
@@ -113,6 +114,8 @@ struct Ctx {
   int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info);
   int32_t launch_round(const Opts &o);
   hipEvent_t next_event();
+  int32_t rom_start(int i, int inst, const std::vector<double> &q, const std::vector<double> &qd);
+  int32_t run_adjoint(int64_t n, int64_t K, const osam_misfit &m, double *J, const osam_grads &g);
   int32_t launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
   int32_t launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
   int32_t learn(int sd, const osam_opinf_desc &d);

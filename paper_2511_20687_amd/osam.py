@@ -26,7 +26,7 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "create_subdomain", "osam_couple", "osam_set_initial", "osam_get_state",
             "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
             "osam_get_opinf", "schwarz_step", "run", "osam_set_timing", "osam_get_timing",
-            "osam_set_fe_launch", "osam_get_fe_launch",
+            "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
             "osam_sync"]
 
 
@@ -58,6 +58,17 @@ class OpinfDesc(C.Structure):
                 ("sigma_out", C.POINTER(C.c_double)), ("E_lambda_out", C.POINTER(C.c_double)),
                 ("lambda_star_out", C.POINTER(C.c_double)), ("r_out", C.POINTER(C.c_int32)),
                 ("rs_out", C.POINTER(C.c_int32))]
+
+
+class Misfit(C.Structure):
+    _fields_ = [("every", C.c_int64), ("obs", C.c_void_p * 8)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("dA", C.POINTER(C.c_double) * 8), ("dH", C.POINTER(C.c_double) * 8),
+                ("dB", C.POINTER(C.c_double) * 8), ("dc", C.POINTER(C.c_double) * 8),
+                ("dq0", C.POINTER(C.c_double) * 8), ("dqd0", C.POINTER(C.c_double) * 8),
+                ("du0", C.c_void_p * 8), ("dv0", C.c_void_p * 8)]
 
 
 class SchwarzOpts(C.Structure):
@@ -115,6 +126,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.schwarz_step.argtypes = [vp, C.POINTER(SchwarzOpts), C.POINTER(InstanceInfo)]
     lib.schwarz_step.restype = i32
     lib.run.argtypes = [vp, i64, C.POINTER(SchwarzOpts), C.POINTER(InstanceInfo)]
+    lib.osam_set_reduced.argtypes = [vp, i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.osam_set_reduced.restype = i32
+    lib.run_adjoint.argtypes = [vp, i64, i64, C.POINTER(Misfit), C.POINTER(C.c_double), C.POINTER(Grads)]
+    lib.run_adjoint.restype = i32
     lib.run.restype = i32
     lib.osam_set_timing.argtypes = [vp, i32]
     lib.osam_set_timing.restype = i32
@@ -164,6 +179,7 @@ class Context:
     def __init__(self, device: int = 0, precision: str = "f64", batch: int = 1, stream=None):
         self.lib = load_library()
         self.precision = precision
+        self.device = device
         self.batch = batch
         h = C.c_void_p()
         prec = {"f64": 0, "f32": 1}[precision]
@@ -309,6 +325,55 @@ class Context:
             self._check(st)
         return self._info_list(info)
 
+    def set_reduced(self, sd: int, inst: int, q0, qd0):
+        """Reduced initial state of an OpInf subdomain (after set_initial, before any step)."""
+        q0, qd0 = _f64(q0), _f64(qd0)
+        self._check(self.lib.osam_set_reduced(self.h, sd, inst, _dptr(q0), _dptr(qd0)))
+
+    def run_adjoint(self, n_steps: int, checkpoint_every: int, every: int, obs: dict):
+        """Misfit J and its gradient (see run_adjoint in osam.h).
+
+        obs: {subdomain id: device tensor [n_obs, n_free] (FOM) or [n_obs, r] (OpInf)}.
+        Returns (J, grads) with grads[sd] = dict(A, H, B, c, q0, qd0) (numpy float64, the
+        layouts of set_opinf) for OpInf subdomains and dict(u0, v0) (device tensors
+        [n_free]) for FOM subdomains."""
+        import torch
+        m = Misfit()
+        m.every = every
+        keep = []
+        for sd, t in obs.items():
+            t = t.contiguous()
+            keep.append(t)
+            m.obs[sd] = t.data_ptr()
+        g = Grads()
+        out = {}
+        for sd in range(self.n_sd):
+            z = self.sizes(sd)
+            if z["r"] > 0:
+                r, rs = z["r"], z["r_s"]
+                d = dict(A=np.zeros((r, r), order="F"), B=np.zeros((r, max(rs, 1)), order="F"),
+                         H=np.zeros((r, r * (r + 1) // 2), order="F"), c=np.zeros(r),
+                         q0=np.zeros(r), qd0=np.zeros(r))
+                g.dA[sd] = _dptr(d["A"])
+                g.dH[sd] = _dptr(d["H"])
+                g.dB[sd] = _dptr(d["B"])
+                g.dc[sd] = _dptr(d["c"])
+                g.dq0[sd] = _dptr(d["q0"])
+                g.dqd0[sd] = _dptr(d["qd0"])
+                if rs == 0:
+                    d["B"] = np.zeros((r, 0))
+            else:
+                dtp = torch.float64 if self.precision == "f64" else torch.float32
+                d = dict(u0=torch.zeros(z["n_free"], dtype=dtp, device=f"cuda:{self.device}"),
+                         v0=torch.zeros(z["n_free"], dtype=dtp, device=f"cuda:{self.device}"))
+                g.du0[sd] = d["u0"].data_ptr()
+                g.dv0[sd] = d["v0"].data_ptr()
+            out[sd] = d
+        J = C.c_double()
+        self._check(self.lib.run_adjoint(self.h, n_steps, checkpoint_every, C.byref(m), C.byref(J), C.byref(g)))
+        del keep
+        return J.value, out
+
     def set_timing(self, enable: bool):
         self._check(self.lib.osam_set_timing(self.h, int(enable)))
 
@@ -355,3 +420,41 @@ def lib_dof_index(nx: int, ny: int, nzs: int, dofs: np.ndarray) -> np.ndarray:
     nfn = npl * (nzs - 1)
     node, comp = dofs // 3, dofs % 3
     return comp * nfn + (node - npl)
+
+
+def rollout_misfit_function():
+    """torch.autograd.Function computing the trajectory misfit J of a coupled run and,
+    in backward, its gradient through run_adjoint.
+
+    apply(ctx_osam, sd, n_steps, checkpoint_every, every, obs, u0_global, v0_global,
+          Phi, PhiS, A, H, B, c, q0, qd0) -> J  (scalar float64 tensor)
+
+    A, H, B, c (float64, the layouts of set_opinf; H/c may be None), q0, qd0 (float64 [r]) are
+    differentiable; set_opinf, set_initial and set_reduced are called in forward, so the
+    context is left at the initial state of these inputs.  The forward J comes from the
+    same adjoint pass that backward uses (computed once, cached)."""
+    import torch
+
+    class RolloutMisfit(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, octx, sd, n_steps, K, every, obs, u0g, v0g, Phi, PhiS, A, H, B, c, q0, qd0):
+            npy = lambda t: None if t is None else t.detach().cpu().numpy().astype(np.float64)
+            octx.set_opinf(sd, Phi, PhiS, npy(A), npy(H), npy(B), npy(c))
+            octx.set_initial(0, u0g, v0g)
+            octx.set_reduced(sd, 0, npy(q0), npy(qd0))
+            J, grads = octx.run_adjoint(n_steps, K, every, obs)
+            fctx.grads = grads[sd]
+            fctx.has = (H is not None, c is not None)
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, gJ):
+            g = fctx.grads
+            s = float(gJ)
+            t = lambda a: torch.tensor(np.asarray(a) * s, dtype=torch.float64)
+            dH = t(g["H"]) if fctx.has[0] else None
+            dc = t(g["c"]) if fctx.has[1] else None
+            return (None, None, None, None, None, None, None, None, None, None,
+                    t(g["A"]), dH, t(g["B"]), dc, t(g["q0"]), t(g["qd0"]))
+
+    return RolloutMisfit

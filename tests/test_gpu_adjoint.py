@@ -1,0 +1,178 @@
+"""GPU adjoint of the coupled rollout (run_adjoint) against the FP64 oracle.
+
+The oracle evaluates J by its own multiplicative Schwarz loop and differentiates it by the
+complex step (oracle/misfit.py); the GPU differentiates the converged explicit map by a
+checkpointed discrete adjoint.  Checked: J, directional derivatives along seeded random
+directions in every parameter block, central differences of the GPU's own J, the
+torch.autograd wrapper, and J against a plain Schwarz run of the library.
+"""
+import numpy as np
+import pytest
+
+from paper_2511_20687_amd.inputs import Bar, gaussian_pulse_u, random_normal, slab_layers, synthetic_rom
+from oracle.misfit import directional_derivative, fom_state, misfit, rom_state
+from oracle.newmark import FomModel, SubdomainGeometry
+from oracle.rom import OpInfModel
+from tests._gpu import lib_index_of, torch_dtype
+
+pytestmark = pytest.mark.gpu
+R_ = 5
+
+
+def _setup(lateral_fix=(), quadratic=True):
+    bar = Bar(2, 2, 20)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    fom = FomModel(bar, *layers[0], dt, lateral_fix=lateral_fix)
+    g = SubdomainGeometry(bar, *layers[1], lateral_fix=lateral_fix)
+    R = synthetic_rom(21, g.n_free, g.n_sch, R_, 3, dt, quadratic=quadratic, with_c=True)
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.4, 0.08)
+    v0 = np.zeros_like(u0)
+    n, every = 40, 4
+    obs_o = {0: 1e-4 * random_normal(22, (n // every, fom.n_free)), 1: 1e-4 * random_normal(23, (n // every, R_))}
+    return dict(bar=bar, dt=dt, layers=layers, fom=fom, g=g, R=R, u0=u0, v0=v0, n=n, every=every, obs_o=obs_o,
+                lf=lateral_fix)
+
+
+def _lib_rom(P, A=None, H=None, B=None, c=None):
+    """Operators and bases in the library layouts (free DOFs [3][nodes], Schwarz [3][nodes])."""
+    from paper_2511_20687_amd import osam
+    bar, layers, R, g = P["bar"], P["layers"], P["R"], P["g"]
+    nzs = layers[1][1] - layers[1][0]
+    li = lib_index_of(g)
+    Phi = np.zeros((3 * (bar.nx + 1) * (bar.ny + 1) * (nzs - 1), R_))
+    Phi[li] = R["Phi"]
+    npl = (bar.nx + 1) * (bar.ny + 1)
+    PhiS = np.zeros_like(R["PhiS"])
+    PhiS[(np.arange(npl)[:, None] + npl * np.arange(3)[None, :]).ravel()] = R["PhiS"]
+    return (Phi, PhiS, R["A"] if A is None else A, R["H"] if H is None else H, R["B"] if B is None else B,
+            R["c"] if c is None else c)
+
+
+def _gpu(P, precision="f64"):
+    import torch
+    from paper_2511_20687_amd import osam
+    ctx = osam.Context(0, precision, 1)
+    osam.add_bar_subdomains(ctx, P["bar"], P["layers"], P["dt"], lateral_fix=P["lf"])
+    ctx.set_opinf(1, *_lib_rom(P))
+    ctx.set_initial(0, P["u0"], P["v0"])
+    fom, dev, dtp = P["fom"], "cuda:0", torch_dtype(precision)
+    nf_lib = ctx.sizes(0)["n_free"]
+    o0 = np.zeros((P["obs_o"][0].shape[0], nf_lib))
+    o0[:, lib_index_of(fom)] = P["obs_o"][0]
+    obs = {0: torch.tensor(o0, dtype=dtp, device=dev), 1: torch.tensor(P["obs_o"][1], dtype=dtp, device=dev)}
+    return ctx, obs
+
+
+def _oracle_J(P, d, eps):
+    R, fom, g, dt = P["R"], P["fom"], P["g"], P["dt"]
+    A = R["A"] + eps * d["A"]
+    H = None if R["H"] is None else R["H"] + eps * d["H"]
+    B, c = R["B"] + eps * d["B"], R["c"] + eps * d["c"]
+    rom = OpInfModel(g, R["Phi"], R["PhiS"], A, H, B, c, dt=dt)
+    st0 = fom.initial_state(P["u0"], P["v0"])   # clamped-end DOFs zeroed, as the library does
+    ul, vl = st0.u.astype(complex), st0.v.astype(complex)
+    ul[fom.free_dofs] += eps * d["u0"]
+    vl[fom.free_dofs] += eps * d["v0"]
+    s0 = g.restrict(P["u0"])[g.sch_dofs]
+    q0 = R["Phi"].T @ g.restrict(P["u0"])[g.free_dofs] + eps * d["q0"]
+    qd0 = R["Phi"].T @ g.restrict(P["v0"])[g.free_dofs] + eps * d["qd0"]
+    st = [fom_state(fom, ul, vl), rom_state(rom, q0, qd0, s0)]
+    return misfit([fom, rom], st, P["n"], P["every"], P["obs_o"])
+
+
+def _direction(P, seed):
+    R, fom = P["R"], P["fom"]
+    sc = lambda a: np.abs(a).max()
+    d = {k: 1e-3 * sc(R[k]) * random_normal(seed + i, R[k].shape) for i, k in enumerate(("A", "B", "c"))}
+    d["H"] = None if R["H"] is None else 1e-3 * sc(R["H"]) * random_normal(seed + 7, R["H"].shape)
+    d["u0"] = 1e-6 * random_normal(seed + 3, (fom.n_free,))
+    d["v0"] = 1e-3 * random_normal(seed + 4, (fom.n_free,))
+    d["q0"] = 1e-6 * random_normal(seed + 5, (R_,))
+    d["qd0"] = 1e-3 * random_normal(seed + 6, (R_,))
+    return d
+
+
+def _dot(P, grads, d):
+    gr, gf = grads[1], grads[0]
+    li = lib_index_of(P["fom"])
+    s = sum(float(np.sum(gr[k] * d[k])) for k in ("A", "B", "c", "q0", "qd0"))
+    if d["H"] is not None:
+        s += float(np.sum(gr["H"] * d["H"]))
+    s += float(np.dot(gf["u0"].cpu().numpy()[li], d["u0"])) + float(np.dot(gf["v0"].cpu().numpy()[li], d["v0"]))
+    return s
+
+
+@pytest.mark.parametrize("lateral_fix", [(), (0, 1)])
+def test_adjoint_matches_oracle_complex_step_f64(lateral_fix):
+    P = _setup(lateral_fix)
+    print(f"[adjoint f64 lateral {lateral_fix}]", flush=True)
+    ctx, obs = _gpu(P)
+    J, grads = ctx.run_adjoint(P["n"], 7, P["every"], obs)
+    J_o = float(np.real(_oracle_J(P, _direction(P, 50), 0.0)))
+    print("J gpu", J, "oracle", J_o)
+    assert abs(J - J_o) <= 1e-12 * abs(J_o)
+    for seed in (50, 60, 70):
+        d = _direction(P, seed)
+        dd_o = directional_derivative(lambda e: _oracle_J(P, d, e))
+        dd_g = _dot(P, grads, d)
+        print("directional", seed, dd_g, dd_o)
+        assert abs(dd_g - dd_o) <= 1e-8 * abs(dd_o)
+    # every block on its own (a wrong transpose in one block cannot hide behind the others)
+    for blk in ("A", "H", "B", "c", "q0", "qd0", "u0", "v0"):
+        d = _direction(P, 80)
+        for k in d:
+            if k != blk and d[k] is not None:
+                d[k] = np.zeros_like(d[k])
+        dd_o = directional_derivative(lambda e: _oracle_J(P, d, e))
+        dd_g = _dot(P, grads, d)
+        assert abs(dd_g - dd_o) <= 1e-8 * abs(dd_o) + 1e-30, (blk, dd_g, dd_o)
+
+
+def test_adjoint_central_differences_and_autograd_f64():
+    import torch
+    from paper_2511_20687_amd import osam
+    P = _setup()
+    ctx, obs = _gpu(P)
+    Phi, PhiS, A, H, B, c = _lib_rom(P)
+    q0 = P["R"]["Phi"].T @ P["g"].restrict(P["u0"])[P["g"].free_dofs]
+    qd0 = np.zeros(R_)
+    F = osam.rollout_misfit_function()
+    tA, tH, tB, tc = (torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in (A, H, B, c))
+    tq, tqd = (torch.tensor(x, dtype=torch.float64, requires_grad=True) for x in (q0, qd0))
+    J = F.apply(ctx, 1, P["n"], 9, P["every"], obs, P["u0"], P["v0"], Phi, PhiS, tA, tH, tB, tc, tq, tqd)
+    J.backward()
+    d = _direction(P, 90)
+    gd = sum(float(torch.sum(t.grad * torch.tensor(d[k]))) for t, k in ((tA, "A"), (tH, "H"), (tB, "B"), (tc, "c")))
+    gd += float(torch.sum(tqd.grad * torch.tensor(d["qd0"]))) + float(torch.sum(tq.grad * torch.tensor(d["q0"])))
+    eps = 1e-3
+    Js = []
+    for sgn in (1, -1):
+        Jx = F.apply(ctx, 1, P["n"], 9, P["every"], obs, P["u0"], P["v0"], Phi, PhiS,
+                     *(torch.tensor(x + sgn * eps * d[k]) for x, k in ((A, "A"), (H, "H"), (B, "B"), (c, "c"),
+                                                                      (q0, "q0"), (qd0, "qd0"))))
+        Js.append(float(Jx))
+    fd = (Js[0] - Js[1]) / (2 * eps)
+    print("fd", fd, "adjoint", gd)
+    assert abs(fd - gd) <= 1e-6 * abs(gd)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_adjoint_misfit_equals_schwarz_run(precision, tol):
+    """J of the adjoint's forward pass equals J from the records of an ordinary run."""
+    import torch
+    P = _setup()
+    ctx, obs = _gpu(P, precision)
+    J, _ = ctx.run_adjoint(P["n"], 16, P["every"], obs)
+    dev, dtp, n, ev = "cuda:0", torch_dtype(precision), P["n"], P["every"]
+    ru = torch.zeros((1, n // ev + 1, ctx.sizes(0)["n_free"]), dtype=dtp, device=dev)
+    rq = torch.zeros((1, n // ev + 1, R_), dtype=dtp, device=dev)
+    ctx.set_record(0, ev, n // ev + 1, u=ru)
+    ctx.set_record(1, ev, n // ev + 1, u=rq)
+    ctx.set_initial(0, P["u0"], P["v0"])
+    ctx.run(n)
+    du = (ru[0, 1:].double() - obs[0].double()).cpu().numpy()
+    dq = (rq[0, 1:].double() - obs[1].double()).cpu().numpy()
+    J_run = 0.5 * (np.sum(du * du) + np.sum(dq * dq))
+    print("J adjoint", J, "J run", J_run)
+    assert abs(J - J_run) <= tol * J_run
