@@ -245,7 +245,8 @@ typedef struct {
   double *dA[8], *dH[8], *dB[8], *dc[8];  /* OpInf subdomains: host float64, layouts of
                                              osam_set_opinf (column-major); NULL = skip */
   double *dq0[8], *dqd0[8];               /* OpInf: host float64 [r] */
-  void *du0[8], *dv0[8];                  /* FOM: device [n_free], context precision */
+  void *du0[8], *dv0[8];                  /* FOM: device [n_free], context precision; 0 on
+                                             components held by lateral_fix (not parameters) */
 } osam_grads;
 /* *J receives the misfit.  OSAM_E_INVALID for batch != 1 or bad sizes. */
 int32_t run_adjoint(osam_ctx *ctx, int64_t n_steps, int64_t checkpoint_every, const osam_misfit *misfit,

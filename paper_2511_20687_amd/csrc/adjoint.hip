@@ -462,6 +462,9 @@ static int32_t adjoint_impl(Ctx *ctx, int64_t n, int64_t K, const osam_misfit &M
     Subdomain &d = *ctx->sds[i];
     if (!X.rom) {
       const long long nf = d.nfree_nodes;
+      // held lateral components start at zero whatever u0, v0 say: no gradient there
+      B.ok(launch_fom_elem<T>(X.G, 6, X.U, nullptr, nullptr, nullptr, T(0), T(0), s), "mask");
+      B.ok(launch_fom_elem<T>(X.G, 6, X.V, nullptr, nullptr, nullptr, T(0), T(0), s), "mask");
       for (int c = 0; c < 3; ++c) {
         if (Gr.du0[i])
           B.ok(hipMemcpyAsync((T *)Gr.du0[i] + c * nf, X.U + c * d.cs + d.npl, nf * sizeof(T),

@@ -64,6 +64,7 @@ __global__ void __launch_bounds__(256) stencil_kernel(SlabGeo<T> G, const T *__r
 //   mode 3: y += x0                              (accumulate)
 //   mode 4: x1 += a1 y ; x2 += a2 y  (y read)    (adjoint predictor: V += dt U, Aa' += h U)
 //   mode 5: x0 += a1 x1 ; y = a1 x1              (adjoint velocity: Aa += g V, Aa' = g V)
+//   mode 6: y = 0 on held comps                  (gradients: held components are not parameters)
 template <typename T>
 __global__ void __launch_bounds__(256) fom_elem_kernel(SlabGeo<T> G, int mode, T *y, T *x0, T *x1, T *x2, T a1,
                                                        T a2) {
@@ -76,11 +77,13 @@ __global__ void __launch_bounds__(256) fom_elem_kernel(SlabGeo<T> G, int mode, T
   switch (mode) {
     case 0: y[id] = x0[id] + a1 * x1[id] + a2 * x2[id]; break;
     case 1: y[id] = x0[id] + a1 * (x1[id] + x2[id]); break;
-    case 2: {
+    case 2:
+    case 6: {
       const int col = (int)(r % G.npl), nxp = G.nx + 1, ix = col % nxp, iy = col / nxp;
       const int cse = node_case(ix, iy, G.nx, G.ny);
       const bool held = cse != 4 && ((G.held >> c) & 1);
-      y[id] = held ? T(0) : x0[id] / G.mass[cse];
+      if (mode == 2) y[id] = held ? T(0) : x0[id] / G.mass[cse];
+      else if (held) y[id] = T(0);
       break;
     }
     case 3: y[id] += x0[id]; break;
