@@ -120,7 +120,6 @@ static int32_t adjoint_impl(Ctx *ctx, int64_t n, int64_t K, const osam_misfit &M
       G.npl = d.npl;
       G.cs = d.cs;
       G.coef = (const T *)d.coef;
-      for (int k = 0; k < 234; ++k) G.ci[k] = (T)d.ci[k];
       const double me = D.rho * (D.Lx / D.nx) * (D.Ly / D.ny) * (D.Lz / D.nz) / 8.0;
       for (int cy = 0; cy < 3; ++cy)
         for (int cx = 0; cx < 3; ++cx) G.mass[cx + 3 * cy] = (T)(me * (cx == 1 ? 2 : 1) * (cy == 1 ? 2 : 1) * 2);

@@ -9,7 +9,6 @@ struct SlabGeo {
   int nx, ny, nzs, npl;
   long long cs;            // component stride of a [3][cs] field
   const T *coef;           // [9 cases][234]
-  T ci[234];               // interior case (kernel arguments)
   T mass[9];               // lumped mass of a node of each case on a full layer
   int held;                // lateral components held at zero (bit mask)
 };

@@ -453,7 +453,7 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
     A.a[k] = (T *)s.a[k];
   }
   A.coef = (const T *)s.coef;
-  for (int i = 0; i < 234; ++i) A.ci[i] = (T)s.ci[i];
+  for (int i = 0; i < 27; ++i) A.cb[i] = (T)s.cb[i];
   A.dt = (T)s.desc.dt;
   A.half_dt = (T)(0.5 * s.desc.dt);
   A.half_dt2 = (T)(0.5 * s.desc.dt * s.desc.dt);

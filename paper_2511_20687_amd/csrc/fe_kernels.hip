@@ -85,6 +85,12 @@ __device__ __forceinline__ Roles<T> roles(const FeArgs<T> &A, int b, long long s
   return R;
 }
 
+template <typename T>
+__device__ __forceinline__ Strides strides(const FeArgs<T> &A) {
+  return Strides{(unsigned)(A.cs * (long long)sizeof(T)), (unsigned)A.npl * (unsigned)sizeof(T),
+                 (unsigned)(A.nx + 1) * (unsigned)sizeof(T)};
+}
+
 // Newmark update of node (layer k, column nid0) from its acceleration, with
 // the convergence sums, records and pushes.
 template <typename T, int MODE>
@@ -92,16 +98,17 @@ __device__ __forceinline__ void update_node(const FeArgs<T> &A, const Roles<T> &
                                             const T (&ctr)[3], const T (&acc)[3], const T (&v0)[3],
                                             const T (&a0)[3], const T (&old)[3], int n_iter, bool rec,
                                             long long rbase, double &acc_abs, double &acc_den) {
-  const long long cs = A.cs;
-  const long long id = (long long)k * A.npl + nid0;
+  const Strides B = strides(A);
+  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T);
   T out[3];   // value pushed to neighbours: the displacement at the next step
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const T a1 = acc[c];
+    const unsigned so = (unsigned)k * B.npl + c * B.cs;   // wave-uniform part of the offset
     if (MODE == kModeInit) {
-      R.A0[c * cs + id] = a1;
+      Field<T>(R.A0).st(a1, vo, so);
       out[c] = ctr[c] + A.dt * v0[c] + A.half_dt2 * a1;
-      R.P[c * cs + id] = out[c];
+      Field<T>(R.P).st(out[c], vo, so);
     } else {
       const T p = ctr[c];
       const T v1 = v0[c] + A.half_dt * (a0[c] + a1);
@@ -113,10 +120,10 @@ __device__ __forceinline__ void update_node(const FeArgs<T> &A, const Roles<T> &
       acc_abs += dlt * dlt;
       const double den = (double)p + (double)A.dt * (double)v1;
       acc_den += den * den;
-      R.V1[c * cs + id] = v1;
-      R.A1[c * cs + id] = a1;
+      Field<T>(R.V1).st(v1, vo, so);
+      Field<T>(R.A1).st(a1, vo, so);
       out[c] = p + A.dt * v1 + A.half_dt2 * a1;
-      R.P2[c * cs + id] = out[c];
+      Field<T>(R.P2).st(out[c], vo, so);
     }
     if (rec) {
       const long long ro = rbase + (long long)c * A.nfree_nodes + (long long)(k - 1) * A.npl + nid0;
@@ -140,6 +147,30 @@ __device__ __forceinline__ void record_face(const FeArgs<T> &A, int b, int f, in
   const long long so = ((long long)b * A.rec_ncols + rcol) * 3 * A.nsch_nodes + (f ? A.face_off_hi : 0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) A.rec_s[so + (long long)c * A.nsch_nodes + nid0] = w[4][c];
+}
+
+// v0, a0 and the previous iterate (V1, or U0 at the first iteration) of one node.
+template <typename T, int MODE>
+__device__ __forceinline__ void state_loads(const Roles<T> &R, const Strides &B, int k, int nid0, int n_iter,
+                                            T (&v0)[3], T (&a0)[3], T (&old)[3]) {
+  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T);
+  const Field<T> FV(R.V0), FA(R.A0), FO(n_iter >= 2 ? R.V1 : R.U0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const unsigned so = (unsigned)k * B.npl + c * B.cs;
+    v0[c] = FV.ld(vo, so);
+    a0[c] = MODE == kModeInit ? T(0) : FA.ld(vo, so);
+    old[c] = MODE == kModeInit ? T(0) : FO.ld(vo, so);
+  }
+}
+
+// One layer's 3x3 neighbourhood: interior columns through wave-uniform row bases,
+// boundary columns (clamped indices) through per-lane addresses.
+template <typename T, bool INTERIOR>
+__device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B, long long cs, int L, int npl,
+                                      int nxp, int ix, int iy, int nx, int ny, int nid0) {
+  if (INTERIOR) load_layer_uniform<T>(w, P, B, L, (unsigned)(nid0 - nxp - 1) * (unsigned)sizeof(T));
+  else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
 }
 
 // Column (ix, iy), layers k0 .. k1-1 (ONE: the single layer k0, every load issued at once).
@@ -169,30 +200,32 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   const int k0 = 1 + chunk * A.kc;
   const int k1 = ONE ? k0 + 1 : min(k0 + A.kc, nzs);
   const int nid0 = ix + nxp * iy;
+  const Strides B = strides(A);
 
-  const long long rcol = (MODE == kModeInit) ? 0 : (step + 1) / (A.rec_every > 0 ? A.rec_every : 1);
-  const bool rec = A.rec_every > 0 && rcol < A.rec_ncols &&
-                   (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
-  const long long rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
+  // records (the division only when recording is on)
+  long long rcol = 0, rbase = 0;
+  bool rec = false;
+  if (A.rec_every > 0) {
+    rcol = (MODE == kModeInit) ? 0 : (step + 1) / A.rec_every;
+    rec = rcol < A.rec_ncols && (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
+    rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
+  }
 
   if (ONE) {
     const int k = k0;
     T w0[9][3], w1[9][3], w2[9][3], v0[3], a0[3], old[3], acc[3], ctr[3];
-    load_layer<T, INTERIOR>(w0, k == 1 ? R.Flo : R.Pin, cs, k - 1, npl, nxp, ix, iy, nx, ny);
-    load_layer<T, INTERIOR>(w1, R.Pin, cs, k, npl, nxp, ix, iy, nx, ny);
-    load_layer<T, INTERIOR>(w2, k + 1 == nzs ? R.Fhi : R.Pin, cs, k + 1, npl, nxp, ix, iy, nx, ny);
-    const long long id = (long long)k * npl + nid0;
+    layer<T, INTERIOR>(w0, k == 1 ? R.Flo : R.Pin, B, cs, k - 1, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR>(w1, R.Pin, B, cs, k, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR>(w2, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
+    state_loads<T, MODE>(R, B, k, nid0, n_iter, v0, a0, old);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      v0[c] = R.V0[c * cs + id];
-      a0[c] = MODE == kModeInit ? T(0) : R.A0[c * cs + id];
-      old[c] = MODE == kModeInit ? T(0) : (n_iter >= 2 ? R.V1[c * cs + id] : R.U0[c * cs + id]);
       ctr[c] = w1[4][c];
       acc[c] = T(0);
     }
-    slab<T, INTERIOR, -1>(A.ci, C, w0, ctr, acc);
-    slab<T, INTERIOR, 0>(A.ci, C, w1, ctr, acc);
-    slab<T, INTERIOR, 1>(A.ci, C, w2, ctr, acc);
+    slab<T, INTERIOR, -1>(A.cb, C, w0, ctr, acc);
+    slab<T, INTERIOR, 0>(A.cb, C, w1, ctr, acc);
+    slab<T, INTERIOR, 1>(A.cb, C, w2, ctr, acc);
     update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (rec && A.rec_s) {
       if (k == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, w0, rcol);
@@ -204,28 +237,22 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   // rolling window: cur = layer k, nxt = layer k+1; acc holds the partial force
   // of layer k from layers k-1 and k until layer k+1 arrives.
   T cur[9][3], nxt[9][3], acc[3], ctr[3];
-  load_layer<T, INTERIOR>(nxt, k0 == 1 ? R.Flo : R.Pin, cs, k0 - 1, npl, nxp, ix, iy, nx, ny);
-  load_layer<T, INTERIOR>(cur, R.Pin, cs, k0, npl, nxp, ix, iy, nx, ny);
+  layer<T, INTERIOR>(nxt, k0 == 1 ? R.Flo : R.Pin, B, cs, k0 - 1, npl, nxp, ix, iy, nx, ny, nid0);
+  layer<T, INTERIOR>(cur, R.Pin, B, cs, k0, npl, nxp, ix, iy, nx, ny, nid0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     ctr[c] = cur[4][c];
     acc[c] = T(0);
   }
-  slab<T, INTERIOR, -1>(A.ci, C, nxt, ctr, acc);
-  slab<T, INTERIOR, 0>(A.ci, C, cur, ctr, acc);
+  slab<T, INTERIOR, -1>(A.cb, C, nxt, ctr, acc);
+  slab<T, INTERIOR, 0>(A.cb, C, cur, ctr, acc);
   if (rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, nxt, rcol);
 
   for (int k = k0; k < k1; ++k) {
-    const long long id = (long long)k * npl + nid0;
     T v0[3], a0[3], old[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      v0[c] = R.V0[c * cs + id];
-      a0[c] = MODE == kModeInit ? T(0) : R.A0[c * cs + id];
-      old[c] = MODE == kModeInit ? T(0) : (n_iter >= 2 ? R.V1[c * cs + id] : R.U0[c * cs + id]);
-    }
-    load_layer<T, INTERIOR>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, cs, k + 1, npl, nxp, ix, iy, nx, ny);
-    slab<T, INTERIOR, 1>(A.ci, C, nxt, ctr, acc);
+    state_loads<T, MODE>(R, B, k, nid0, n_iter, v0, a0, old);
+    layer<T, INTERIOR>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
+    slab<T, INTERIOR, 1>(A.cb, C, nxt, ctr, acc);
     update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (k + 1 < k1) {
       // start layer k+1: contributions of layers k (dz = -1) and k+1 (dz = 0)
@@ -234,8 +261,8 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
         ctr[c] = nxt[4][c];
         acc[c] = T(0);
       }
-      slab<T, INTERIOR, -1>(A.ci, C, cur, ctr, acc);
-      slab<T, INTERIOR, 0>(A.ci, C, nxt, ctr, acc);
+      slab<T, INTERIOR, -1>(A.cb, C, cur, ctr, acc);
+      slab<T, INTERIOR, 0>(A.cb, C, nxt, ctr, acc);
 #pragma unroll
       for (int n = 0; n < 9; ++n)
 #pragma unroll

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/osam.h"
+#include "stencil.hpp"
 #include "osam_device.hpp"
 #include "runtime.hpp"
 
@@ -112,9 +113,33 @@ static void stencil_coefficients(const osam_subdomain_desc &d, std::vector<doubl
     }
 }
 
-static bool interior_zero_h(int d27, int p, int q) {
-  const int dd[3] = {d27 % 3 - 1, (d27 % 9) / 3 - 1, d27 / 9 - 1};
-  return p != q && (dd[p] == 0 || dd[q] == 0);
+// The 27 distinct values of the interior block (structure: box_index, box_sign),
+// checked against every entry: false if the block does not have that structure.
+static bool box_coefficients(const double *Ci, double cb[27]) {
+  double cmax = 0.0;
+  for (int i = 0; i < 234; ++i) cmax = std::max(cmax, std::fabs(Ci[i]));
+  bool have[27] = {};
+  for (int d27 = 0; d27 < 27; ++d27) {
+    if (d27 == 13) continue;
+    const int d26 = d27 < 13 ? d27 : d27 - 1;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        const double v = Ci[d26 * 9 + p * 3 + q];
+        const int bi = box_index(d27, p, q);
+        if (bi < 0) {
+          if (std::fabs(v) > 1e-12 * cmax) return false;
+          continue;
+        }
+        const double x = v * box_sign(d27, p, q);
+        if (!have[bi]) {
+          cb[bi] = x;
+          have[bi] = true;
+        } else if (std::fabs(x - cb[bi]) > 1e-12 * cmax) {
+          return false;
+        }
+      }
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -324,16 +349,8 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   // stencil coefficients
   std::vector<double> C;
   stencil_coefficients(*d, C);
-  double cmax = 0.0;
-  for (double v : C) cmax = std::max(cmax, std::fabs(v));
-  for (int d27 = 0; d27 < 27; ++d27) {
-    if (d27 == 13) continue;
-    const int d26 = d27 < 13 ? d27 : d27 - 1;
-    for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q)
-        if (interior_zero_h(d27, p, q) && std::fabs(C[(4 * 26 + d26) * 9 + p * 3 + q]) > 1e-12 * cmax)
-          return ctx->fail(OSAM_E_INVALID, "interior stencil lacks the expected mirror symmetry");
-  }
+  if (!box_coefficients(C.data() + 4 * 234, sd->cb))
+    return ctx->fail(OSAM_E_INVALID, "interior stencil lacks the mirror symmetries of a box element");
   // lateral Dirichlet components: zero rows of every lateral case, so the
   // acceleration of a held component is exactly zero (u, v start at zero)
   for (int cse = 0; cse < 9; ++cse) {
@@ -344,7 +361,6 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
         for (int q = 0; q < 3; ++q) C[(cse * 26 + d26) * 9 + p * 3 + q] = 0.0;
     }
   }
-  std::copy(C.begin() + 4 * 234, C.begin() + 5 * 234, sd->ci);
   int32_t st = OSAM_OK;
   sd->coef = ctx->alloc_t(C.size(), &st);
   if (st) return ctx->fail(st, "out of device memory");

@@ -37,7 +37,7 @@ struct Subdomain {
   // FOM buffers
   void *u[3] = {}, *v[2] = {}, *a[2] = {};
   void *coef = nullptr;
-  double ci[234];              // interior case of coef, for the kernel arguments
+  double cb[27];               // the interior block's distinct values (kernel arguments)
   std::vector<std::vector<double>> gh0;   // OpInf: g^ at t_0 per instance (from the initial condition)
   int *bnd_cols = nullptr;
   int n_int = 0, n_bnd = 0;

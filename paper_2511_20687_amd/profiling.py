@@ -3,6 +3,7 @@
 Used under rocprofv3 to produce the summaries in profiles/:
 
     python -m paper_2511_20687_amd.profiling workload [steps]   # coupled run, synthetic r=40 OpInf
+    python -m paper_2511_20687_amd.profiling large [steps [block kc]]  # 64x64x640, OpInf-FOM-OpInf, B=16
     python -m paper_2511_20687_amd.profiling copy               # plain copy of 256 MiB (calibration)
     python -m paper_2511_20687_amd.profiling summarize OUTDIR   # counters -> profiles/*.txt
 
@@ -50,6 +51,49 @@ def workload(steps: int = 200) -> None:
     torch.cuda.synchronize()
     print(f"workload done: {steps} steps, {info[0]['total_iters']} Schwarz iterations, "
           f"{z['n_free']} FE DOFs", flush=True)
+
+
+def large_context(steps: int = 0):
+    """The 64x64x640 three-subdomain hybrid (quadratic OpInf r=120 outer subdomains, FOM middle)
+    with 16 instances of the seeded multi-pulse initial velocity; OpInf operators are seeded
+    synthetic ones of the sizes this configuration learns (H 120 x 7260)."""
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import CFG5, draw_multi_pulse_v, synthetic_rom
+    w = CFG5
+    ctx = osam.Context(0, w.precision, w.batch)
+    osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
+    for i, kind in enumerate(w.models):
+        if kind != "opinf":
+            continue
+        z = ctx.sizes(i)
+        R = synthetic_rom(w.seed + 10 * i, z["n_free"], z["n_sch"], w.r, 20, w.dt, quadratic=True)
+        ctx.set_opinf(i, R["Phi"], R["PhiS"], R["A"], R["H"], R["B"])
+        del R
+    u0 = np.zeros((3, w.bar.n_nodes))
+    for b, mp in enumerate(draw_multi_pulse_v(w.seed, w.batch)):
+        ctx.set_initial(b, u0, mp.v0(w.bar))
+    return w, ctx
+
+
+def large(steps: int = 20, block: int = 0, kc: int = 0) -> None:
+    import torch
+    from paper_2511_20687_amd import osam
+    w, ctx = large_context()
+    fom = w.models.index("fom")
+    if block or kc:
+        ctx.set_fe_launch(fom, block, kc)
+    nf = ctx.sizes(fom)["n_free"]
+    opts = osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel)
+    ctx.run(2, opts)                                   # warm-up
+    ctx.set_timing(True)
+    info = ctx.run(steps, opts)
+    torch.cuda.synchronize()
+    ms, n = ctx.get_timing(fom)
+    us = 1e3 * ms / max(n, 1)
+    alg = 28.0 * nf * w.batch
+    print(f"large done: {steps} steps, {info[0]['total_iters']} Schwarz iterations (instance 0), "
+          f"FE launches {n}, FE avg {us:.1f} us, {nf} FE DOFs x {w.batch} instances, "
+          f"algorithmic {alg / 1e6:.1f} MB per launch -> {alg / (us * 1e-6) / 1e9:.0f} GB/s", flush=True)
 
 
 def copy() -> None:
@@ -134,6 +178,9 @@ if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
     if cmd == "workload":
         workload(int(sys.argv[2]) if len(sys.argv) > 2 else 200)
+    elif cmd == "large":
+        a = [int(x) for x in sys.argv[2:5]]
+        large(*a)
     elif cmd == "copy":
         copy()
     elif cmd == "summarize":
