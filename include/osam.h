@@ -57,7 +57,12 @@ typedef enum {
   OSAM_E_ORDER = -7      /* call-order violation (e.g. run before set_initial) */
 } osam_status;
 
-typedef enum { OSAM_FP64 = 0, OSAM_FP32 = 1 } osam_precision;
+/* OSAM_FP32_BF16H: as OSAM_FP32, except that the reduced operator contraction
+ * [A | H] [q; q (x) q] of OpInf subdomains takes BF16 operands with FP32
+ * accumulation on the matrix cores (Eq. opinf_model_schwarz; the rounding of the
+ * operands is the only difference, so results differ from OSAM_FP32 by about
+ * 2^-9 relative in that term). */
+typedef enum { OSAM_FP64 = 0, OSAM_FP32 = 1, OSAM_FP32_BF16H = 2 } osam_precision;
 typedef enum { OSAM_GUESS_HOLD = 0, OSAM_GUESS_PREDICTOR = 1 } osam_guess;
 typedef enum { OSAM_LINEAR = 0, OSAM_QUADRATIC = 1 } osam_form;
 
@@ -268,6 +273,20 @@ int32_t osam_get_timing(osam_ctx *ctx, int32_t sd, double *ms, int64_t *launches
 int32_t osam_set_fe_launch(osam_ctx *ctx, int32_t sd, int32_t block, int32_t kc);
 /* Current launch shape of FOM subdomain sd (any pointer may be NULL). */
 int32_t osam_get_fe_launch(osam_ctx *ctx, int32_t sd, int32_t *block, int32_t *kc);
+
+/* Evaluation path of OpInf subdomain sd's step in FP32 contexts (Sec. 4.2,
+ * Eq. opinf_model_schwarz): 0 automatic (batched for batch >= 8 or
+ * r(r+1)/2 >= 1024), 1 fused (one kernel per Schwarz iteration; every
+ * workgroup of an instance re-evaluates the reduced right-hand side), 2 batched
+ * (f0 = A q + H (q (x) q) + c once per controller step on the matrix cores over
+ * tiles of 16 instances, g^ of FOM-fed faces split over the face DOFs).  The
+ * explicit predictor q(t_k) is fixed within a step, so both paths compute the
+ * same map; they differ by FP32 rounding order only.  OSAM_FP32_BF16H contexts
+ * always use the batched path; FP64 contexts always the fused one.  Takes
+ * effect for the following steps.  OSAM_E_INVALID for other values. */
+int32_t osam_set_rom_path(osam_ctx *ctx, int32_t sd, int32_t path);
+/* The path subdomain sd's step uses once wired: 1 fused, 2 batched (0 for a FOM). */
+int32_t osam_get_rom_path(osam_ctx *ctx, int32_t sd, int32_t *path);
 
 /* Wait for all queued work of the context (host synchronisation). */
 int32_t osam_sync(osam_ctx *ctx);

@@ -133,6 +133,92 @@ int32_t Ctx::couple() {
 // ---------------------------------------------------------------------------
 // Wiring: face-value buffers of OpInf subdomains fed by a FOM, Phi_S face
 // blocks and ROM-to-ROM transfer matrices, Pi Phi export rows.
+// Batched OpInf path (FP32 contexts, rom_pre_kernels.hip), chosen per subdomain:
+// always in the BF16-H precision, on request, or automatically for batches of
+// 8 and more or a compressed quadratic width of 1024 and more.  Builds A (FP32)
+// and H (FP32, or BF16 in the BF16-H precision) in MFMA fragment order, the
+// quadratic pair table and the partial-sum buffers.
+static uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+int32_t Ctx::setup_pre(Subdomain &d) {
+  HIPCHK(hipStreamSynchronize(stream));
+  void *old[] = {d.pre_fa, d.pre_fh, d.pre_pairs, d.pre_f0, d.pre_g};
+  for (void *p : old) dfree(p);
+  d.pre_fa = nullptr;
+  d.pre_fh = nullptr;
+  d.pre_pairs = nullptr;
+  d.pre_f0 = nullptr;
+  d.pre_g = nullptr;
+  d.pre = false;
+  if (!d.rom) return OSAM_OK;
+  const int r = d.r, rs = d.rs, r2 = d.oh.quadratic ? r * (r + 1) / 2 : 0;
+  const bool bf16 = prec == OSAM_FP32_BF16H;
+  const bool want = prec != OSAM_FP64 && r <= 256 && rs <= 512 &&
+                    (bf16 || d.rom_path == 2 || (d.rom_path == 0 && (batch >= 8 || r2 >= 1024)));
+  if (!want) return OSAM_OK;
+  d.pre_prec = bf16 ? 1 : 0;
+  d.pre_nrt = (r + 15) / 16;
+  d.pre_nkba = (r + 3) / 4;
+  d.pre_nkbh = r2 > 0 ? (bf16 ? (r2 + 15) / 16 : (r2 + 3) / 4) : 0;
+  const int nit = (batch + 15) / 16, nkb = d.pre_nkba + d.pre_nkbh;
+  d.pre_ks = std::max(1, std::min((512 + d.pre_nrt * nit - 1) / (d.pre_nrt * nit), std::max(1, nkb / 8)));
+  auto Aij = [&](int i, int k) -> double { return i < r && k < r ? d.oh.A[(size_t)k * r + i] : 0.0; };
+  auto Him = [&](int i, int m) -> double { return i < r && m < r2 ? d.oh.H[(size_t)m * r + i] : 0.0; };
+  int32_t st = OSAM_OK;
+  // lane l of the 16x16x4 block (rt, kb) holds M[16 rt + l % 16][4 kb + l / 16]
+  {
+    std::vector<float> fa((size_t)d.pre_nrt * d.pre_nkba * 64);
+    for (int rt = 0; rt < d.pre_nrt; ++rt)
+      for (int kb = 0; kb < d.pre_nkba; ++kb)
+        for (int l = 0; l < 64; ++l)
+          fa[((size_t)rt * d.pre_nkba + kb) * 64 + l] = (float)Aij(rt * 16 + l % 16, kb * 4 + l / 16);
+    d.pre_fa = static_cast<float *>(arena_alloc(fa.size() * 4, &st));
+    if (st) return fail(st, "out of device memory");
+    HIPCHK(hipMemcpy(d.pre_fa, fa.data(), fa.size() * 4, hipMemcpyHostToDevice));
+  }
+  if (r2 > 0 && !bf16) {
+    std::vector<float> fh((size_t)d.pre_nrt * d.pre_nkbh * 64);
+    for (int rt = 0; rt < d.pre_nrt; ++rt)
+      for (int kb = 0; kb < d.pre_nkbh; ++kb)
+        for (int l = 0; l < 64; ++l)
+          fh[((size_t)rt * d.pre_nkbh + kb) * 64 + l] = (float)Him(rt * 16 + l % 16, kb * 4 + l / 16);
+    d.pre_fh = arena_alloc(fh.size() * 4, &st);
+    if (st) return fail(st, "out of device memory");
+    HIPCHK(hipMemcpy(d.pre_fh, fh.data(), fh.size() * 4, hipMemcpyHostToDevice));
+  } else if (r2 > 0) {
+    // lane l of the 16x16x16 block (rt, kb) holds H[16 rt + l % 16][16 kb + 4 (l / 16) + j], j < 4
+    std::vector<uint16_t> fh((size_t)d.pre_nrt * d.pre_nkbh * 64 * 4);
+    for (int rt = 0; rt < d.pre_nrt; ++rt)
+      for (int kb = 0; kb < d.pre_nkbh; ++kb)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 4; ++j)
+            fh[(((size_t)rt * d.pre_nkbh + kb) * 64 + l) * 4 + j] =
+                bf16_rne((float)Him(rt * 16 + l % 16, kb * 16 + 4 * (l / 16) + j));
+    d.pre_fh = arena_alloc(fh.size() * 2, &st);
+    if (st) return fail(st, "out of device memory");
+    HIPCHK(hipMemcpy(d.pre_fh, fh.data(), fh.size() * 2, hipMemcpyHostToDevice));
+  }
+  std::vector<int> pr(std::max(r2, 1), 0);
+  for (int i = 0, m = 0; i < r && r2 > 0; ++i)
+    for (int j = i; j < r; ++j) pr[m++] = i | (j << 16);
+  d.pre_pairs = static_cast<int *>(arena_alloc(pr.size() * sizeof(int), &st));
+  d.pre_f0 = static_cast<float *>(arena_alloc((size_t)d.pre_ks * batch * r * sizeof(float), &st));
+  long long nfd = 0;
+  for (int f = 0; f < 2; ++f)
+    if (d.face_type[f] != kFaceClamped && !sds[d.proj[f].src]->rom) nfd += 3LL * d.npl;
+  d.pre_gs = nfd > 0 && rs > 0 ? (int)std::max(1LL, std::min(64LL, (nfd + 2047) / 2048)) : 0;
+  if (d.pre_gs > 0) d.pre_g = static_cast<double *>(arena_alloc((size_t)d.pre_gs * batch * rs * sizeof(double), &st));
+  if (st) return fail(st, "out of device memory");
+  HIPCHK(hipMemcpy(d.pre_pairs, pr.data(), pr.size() * sizeof(int), hipMemcpyHostToDevice));
+  d.pre = true;
+  return OSAM_OK;
+}
+
 int32_t Ctx::wire() {
   if (wired) return OSAM_OK;
   int32_t st = OSAM_OK;
@@ -233,6 +319,8 @@ int32_t Ctx::wire() {
     }
   }
   HIPCHK(hipStreamSynchronize(stream));
+  for (int i = 0; i < S; ++i)
+    if (sds[i]->rom && (st = setup_pre(*sds[i]))) return st;
   wired = true;
   return OSAM_OK;
 }
@@ -525,6 +613,18 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
   A.H = (const T *)s.d_H;
   A.B = s.rs > 0 ? (const T *)s.d_B : nullptr;
   A.c = (const T *)s.d_c;
+  if (s.pre) {   // f0 (and the FOM-fed g^) arrive as partial sums
+    A.A = nullptr;
+    A.H = nullptr;
+    A.c = nullptr;
+    A.r2 = 0;
+    A.f0part = (const T *)s.pre_f0;
+    A.f0_ks = s.pre_ks;
+    A.f0_stride = (long long)c.batch * s.r;
+    A.gpart = s.pre_g;
+    A.g_gs = s.pre_gs;
+    A.g_stride = (long long)c.batch * s.rs;
+  }
   for (int k = 0; k < 2; ++k) {
     A.q[k] = (T *)s.q[k];
     A.qd[k] = (T *)s.qd[k];
@@ -538,6 +638,7 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
     if (s.face_type[f] == kFaceClamped || s.rs == 0) continue;
     const FaceProj &P = s.proj[f];
     const Subdomain &src = *c.sds[P.src];
+    if (s.pre_g && !src.rom) continue;   // summed by rom_ghat_kernel
     RomFaceIn<T> &F = A.fin[nf++];
     F.src_sd = P.src;
     F.n = 3 * s.npl;
@@ -581,9 +682,56 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
   A.rec_ncols = s.rec.n_cols;
 }
 
+static void fill_pre_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomPreArgs &P) {
+  std::memset(&P, 0, sizeof(P));
+  P.r = s.r;
+  P.rs = s.rs;
+  P.r2 = s.oh.quadratic ? s.r * (s.r + 1) / 2 : 0;
+  P.batch = c.batch;
+  P.prec = s.pre_prec;
+  P.nkba = s.pre_nkba;
+  P.nkbh = s.pre_nkbh;
+  P.nrt = s.pre_nrt;
+  P.ks = s.pre_ks;
+  P.nit = (c.batch + 15) / 16;
+  P.frag_a = s.pre_fa;
+  P.frag_h = s.pre_fh;
+  P.pairs = s.pre_pairs;
+  P.c = (const float *)s.d_c;
+  for (int k = 0; k < 2; ++k) {
+    P.q[k] = (const float *)s.q[k];
+    P.qd[k] = (const float *)s.qd[k];
+    P.qdd[k] = (const float *)s.qdd[k];
+  }
+  P.dt = (float)s.desc.dt;
+  P.half_dt2 = (float)(0.5 * s.desc.dt * s.desc.dt);
+  P.f0part = s.pre_f0;
+  int nf = 0;
+  for (int f = 0; f < 2 && s.pre_g; ++f) {
+    if (s.face_type[f] == kFaceClamped || c.sds[s.proj[f].src]->rom) continue;
+    P.fn[nf] = 3LL * s.npl;
+    P.fsrc[nf] = s.proj[f].src;
+    P.phis[nf] = (const float *)s.face_phis[f];
+    for (int k = 0; k < 3; ++k) P.sface[nf][k] = (const float *)s.sface[f][k];
+    ++nf;
+  }
+  P.nface = nf;
+  P.gs = s.pre_gs;
+  P.gpart = s.pre_g;
+  P.status = c.d_status;
+  P.sd = sdi;
+  P.opts = o;
+}
+
 int32_t Ctx::launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0, hipEvent_t ev1) {
   Subdomain &s = *sds[sdi];
   hipError_t e;
+  if (s.pre) {
+    RomPreArgs P;
+    fill_pre_args(*this, s, sdi, o, P);
+    e = launch_rom_pre(P, stream);
+    if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("batched OpInf kernels: ") + hipGetErrorString(e));
+  }
   if (prec == OSAM_FP64) {
     RomArgs<double> A;
     fill_rom_args<double>(*this, s, sdi, o, A);
@@ -804,7 +952,7 @@ int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
   // free any previous OpInf data and the FOM state buffers
   void *old[] = {d.d_A, d.d_H, d.d_B, d.d_c, d.d_Phi, d.q[0], d.q[1], d.qd[0], d.qd[1], d.qdd[0], d.qdd[1],
                  d.u[0], d.u[1], d.u[2], d.v[0], d.v[1], d.a[0], d.a[1], d.face_phis[0], d.face_phis[1],
-                 d.face_tm[0], d.face_tm[1]};
+                 d.face_tm[0], d.face_tm[1], d.pre_fa, d.pre_fh, d.pre_pairs, d.pre_f0, d.pre_g};
   HIPCHK(hipStreamSynchronize(stream));
   for (void *p : old) dfree(p);
   d.d_A = d.d_H = d.d_B = d.d_c = d.d_Phi = nullptr;
@@ -812,6 +960,12 @@ int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
   for (int k = 0; k < 3; ++k) d.u[k] = nullptr;
   for (int k = 0; k < 2; ++k) d.v[k] = d.a[k] = nullptr;
   for (int k = 0; k < 2; ++k) d.face_phis[k] = d.face_tm[k] = nullptr;
+  d.pre_fa = nullptr;
+  d.pre_fh = nullptr;
+  d.pre_pairs = nullptr;
+  d.pre_f0 = nullptr;
+  d.pre_g = nullptr;
+  d.pre = false;
   // row-major copies for the kernels
   std::vector<double> Ar((size_t)r * r), Hr, Br;
   for (int i = 0; i < r; ++i)

@@ -240,6 +240,39 @@ struct RomArgs {
   FinishArgs finish;       // used when this is the last subdomain of the sweep
   T *rec_q;
   long long rec_every, rec_ncols;
+  // batched path: f0 = A q + H (q (x) q) + c and g^ of the FOM-fed faces come
+  // precomputed as partial sums (A, H, c and FOM faces are then absent above)
+  const T *f0part;         // [f0_ks][batch][r] or null
+  int f0_ks;
+  const double *gpart;     // [g_gs][batch][rs] or null
+  int g_gs;
+  long long f0_stride, g_stride;   // batch * r, batch * rs
 };
+
+// Batched OpInf parts (FP32 contexts): f0 on the matrix cores, g^ of FOM faces.
+struct RomPreArgs {
+  int r, rs, r2, batch;
+  int prec;                // 0: FP32 operands, 1: BF16 operands (FP32 accumulation)
+  int nkba, nkbh;          // K blocks of A (FP32, 4 wide) and of H (4 wide FP32 / 16 wide BF16)
+  int nrt, ks, nit;        // row tiles of 16, K splits, instance tiles of 16
+  const float *frag_a;     // A in MFMA fragment order (FP32)
+  const void *frag_h;      // H in MFMA fragment order (FP32 or BF16), null when linear
+  const int *pairs;        // compressed quadratic index m -> i | j << 16
+  const float *c;
+  const float *q[2], *qd[2], *qdd[2];
+  float dt, half_dt2;
+  float *f0part;           // [ks][batch][r]
+  int nface, gs;           // FOM-fed faces, DOF splits
+  long long fn[2];
+  int fsrc[2];
+  const float *phis[2];
+  const float *sface[2][3];
+  double *gpart;           // [gs][batch][rs]
+  const Status *status;
+  int sd;
+  Opts opts;
+};
+
+hipError_t launch_rom_pre(const RomPreArgs &P, hipStream_t s);
 
 }  // namespace osam

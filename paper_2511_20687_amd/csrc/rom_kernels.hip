@@ -12,8 +12,9 @@
 // projection touches are kept.  The convergence sums use reduced coordinates
 // (Phi has orthonormal columns).
 //
-// This variant serves small batches: H (q (x) q) is evaluated with one wave per
-// output row from the compressed quadratic vector staged in LDS.
+// Fused path (small batches): A q + H (q (x) q) is evaluated with one wave per
+// output row from the compressed quadratic vector staged in LDS.  Batched path
+// (rom_pre_kernels.hip): f0 and the FOM-fed g^ arrive as partial sums.
 #include <hip/hip_ext.h>
 
 #include "osam_device.hpp"
@@ -92,6 +93,15 @@ __global__ void __launch_bounds__(kRomThreads) rom_kernel(RomArgs<T> A) {
     xqdd[p] = A.qdd[p][qo + tq];
   }
   if (A.c) x_c = A.c[tq];
+  // batched path: this row's f0 and this thread's mode of g^ (partial sums, fixed order)
+  T x_f0 = T(0);
+  double x_g = 0.0;
+  if (A.f0part)
+    for (int k = 0; k < A.f0_ks; ++k) x_f0 += A.f0part[k * A.f0_stride + qo + tq];
+  if (A.gpart && rs > 0) {
+    const int tg = min(tid, rs - 1);
+    for (int k = 0; k < A.g_gs; ++k) x_g += A.gpart[k * A.g_stride + (long long)b * rs + tg];
+  }
   T arow[kRowsPerWave][2], brow[kRowsPerWave];
   const int l0 = min(lane, r - 1), l1 = min(lane + 64, r - 1), lb = min(lane, rs > 0 ? rs - 1 : 0);
 #pragma unroll
@@ -99,8 +109,10 @@ __global__ void __launch_bounds__(kRomThreads) rom_kernel(RomArgs<T> A) {
     const int i = wid + kRomWaves * j;
     arow[j][0] = arow[j][1] = brow[j] = T(0);
     if (i < r) {   // wave-uniform
-      arow[j][0] = A.A[(long long)i * r + l0];
-      if (r > 64) arow[j][1] = A.A[(long long)i * r + l1];
+      if (A.A) {
+        arow[j][0] = A.A[(long long)i * r + l0];
+        if (r > 64) arow[j][1] = A.A[(long long)i * r + l1];
+      }
       if (A.B) brow[j] = A.B[(long long)i * rs + lb];
     }
   }
@@ -159,8 +171,11 @@ __global__ void __launch_bounds__(kRomThreads) rom_kernel(RomArgs<T> A) {
   }
 
   // ---- 2. predictor q(t_k) = q + dt q' + dt^2/2 q''
-  if (tid < r) q1s[tid] = x_q0 + A.dt * x_qd0 + A.half_dt2 * x_qdd0;
-  for (int k = tid; k < rs; k += kRomThreads) sh[k] = T(0);
+  if (tid < r) {
+    q1s[tid] = x_q0 + A.dt * x_qd0 + A.half_dt2 * x_qdd0;
+    qdd1s[tid] = x_f0;   // rows add A q + H (q (x) q) + B g^ below
+  }
+  for (int k = tid; k < rs; k += kRomThreads) sh[k] = k == tid ? (T)x_g : T(0);
 
   // ---- 3. reduced boundary input g^ (and the FOM partial sums, same reduction)
   {
@@ -260,7 +275,7 @@ __global__ void __launch_bounds__(kRomThreads) rom_kernel(RomArgs<T> A) {
     for (int l = 64 + lane; l < rs; l += 64) s += A.B[(long long)i * rs + l] * sh[l];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) qdd1s[i] = s;
+    if (lane == 0) qdd1s[i] += s;
   }
   __syncthreads();
 

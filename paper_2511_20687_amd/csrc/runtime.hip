@@ -248,7 +248,7 @@ int32_t osam_version(void) { return 10000; }
 int32_t osam_ctx_create(osam_ctx **out, int32_t device, int32_t precision, int32_t batch, void *stream) {
   if (!out) return OSAM_E_INVALID;
   *out = nullptr;
-  if (precision != OSAM_FP64 && precision != OSAM_FP32) return OSAM_E_INVALID;
+  if (precision != OSAM_FP64 && precision != OSAM_FP32 && precision != OSAM_FP32_BF16H) return OSAM_E_INVALID;
   if (batch < 1) return OSAM_E_INVALID;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return OSAM_E_HIP;
@@ -596,6 +596,28 @@ int32_t osam_get_fe_launch(osam_ctx *c, int32_t sd, int32_t *block, int32_t *kc)
   const Subdomain &s = *ctx->sds[sd];
   if (block) *block = s.fe_block;
   if (kc) *kc = s.fe_kc;
+  return OSAM_OK;
+}
+
+int32_t osam_set_rom_path(osam_ctx *c, int32_t sd, int32_t path) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  if (sd < 0 || sd >= (int)ctx->sds.size() || path < 0 || path > 2)
+    return ctx->fail(OSAM_E_INVALID, "bad subdomain id or path");
+  Subdomain &s = *ctx->sds[sd];
+  s.rom_path = path;
+  if (ctx->wired && s.rom) return ctx->setup_pre(s);
+  return OSAM_OK;
+}
+
+int32_t osam_get_rom_path(osam_ctx *c, int32_t sd, int32_t *path) {
+  if (!c || !path) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  if (sd < 0 || sd >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  int32_t st = ctx->wire();
+  if (st) return st;
+  const Subdomain &s = *ctx->sds[sd];
+  *path = !s.rom ? 0 : (s.pre ? 2 : 1);
   return OSAM_OK;
 }
 

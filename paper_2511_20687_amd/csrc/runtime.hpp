@@ -48,6 +48,16 @@ struct Subdomain {
   int r = 0, rs = 0;
   OpinfHost oh;
   void *d_A = nullptr, *d_H = nullptr, *d_B = nullptr, *d_c = nullptr;   // row-major
+  // batched OpInf path: f0 = A q + H (q (x) q) + c once per step on the matrix
+  // cores, g^ of FOM-fed faces split over the face DOFs (FP32 contexts)
+  int rom_path = 0;                // 0 automatic, 1 fused, 2 batched
+  bool pre = false;                // batched path wired
+  float *pre_fa = nullptr;         // A in MFMA fragment order (FP32)
+  void *pre_fh = nullptr;          // H in MFMA fragment order (FP32 or BF16)
+  int *pre_pairs = nullptr;        // compressed quadratic index -> i | j << 16
+  float *pre_f0 = nullptr;         // [ks][batch][r]
+  double *pre_g = nullptr;         // [gs][batch][rs]
+  int pre_prec = 0, pre_nkba = 0, pre_nkbh = 0, pre_nrt = 0, pre_ks = 1, pre_gs = 1;
   void *d_Phi = nullptr;           // [r][nfree] column-major
   void *q[2] = {}, *qd[2] = {}, *qdd[2] = {};
   void *face_phis[2] = {};         // [rs][3 npl] Phi_S block per Schwarz face
@@ -104,6 +114,7 @@ struct Ctx {
   void choose_fe_launch(Subdomain &s, int block, int kc);
   int32_t couple();
   int32_t wire();
+  int32_t setup_pre(Subdomain &d);
   int32_t set_initial(int inst, const double *u0, const double *v0);
   int32_t init_pending();
   int32_t get_state(int sd, int inst, double *u, double *v, double *a);

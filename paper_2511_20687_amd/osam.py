@@ -27,7 +27,7 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
             "osam_get_opinf", "schwarz_step", "run", "osam_set_timing", "osam_get_timing",
             "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
-            "osam_sync"]
+            "osam_set_rom_path", "osam_get_rom_path", "osam_sync"]
 
 
 class OsamError(RuntimeError):
@@ -139,6 +139,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_set_fe_launch.restype = i32
     lib.osam_get_fe_launch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
     lib.osam_get_fe_launch.restype = i32
+    lib.osam_set_rom_path.argtypes = [vp, i32, i32]
+    lib.osam_set_rom_path.restype = i32
+    lib.osam_get_rom_path.argtypes = [vp, i32, C.POINTER(i32)]
+    lib.osam_get_rom_path.restype = i32
     lib.osam_sync.argtypes = [vp]
     lib.osam_sync.restype = i32
     _lib = lib
@@ -182,7 +186,7 @@ class Context:
         self.device = device
         self.batch = batch
         h = C.c_void_p()
-        prec = {"f64": 0, "f32": 1}[precision]
+        prec = {"f64": 0, "f32": 1, "f32_bf16h": 2}[precision]
         st = self.lib.osam_ctx_create(C.byref(h), device, prec, batch,
                                       None if stream is None else C.c_void_p(stream))
         if st != OSAM_OK:
@@ -389,6 +393,15 @@ class Context:
         b, k = C.c_int32(), C.c_int32()
         self._check(self.lib.osam_get_fe_launch(self.h, sd, C.byref(b), C.byref(k)))
         return b.value, k.value
+
+    def set_rom_path(self, sd: int, path: int):
+        """0 automatic, 1 fused, 2 batched (see osam_set_rom_path)."""
+        self._check(self.lib.osam_set_rom_path(self.h, sd, path))
+
+    def rom_path(self, sd: int) -> int:
+        p = C.c_int32()
+        self._check(self.lib.osam_get_rom_path(self.h, sd, C.byref(p)))
+        return p.value
 
     def sync(self):
         self._check(self.lib.osam_sync(self.h))
