@@ -268,8 +268,12 @@ int32_t osam_get_timing(osam_ctx *ctx, int32_t sd, double *ms, int64_t *launches
 
 /* Launch shape of FOM subdomain sd's step kernel: `block` threads per workgroup
  * (64, 128 or 256; 0 = automatic) and `kc` z-layers marched per thread
- * (>= 1; 0 = automatic).  Affects speed only, never results.  OSAM_E_INVALID
- * for other values or an OpInf subdomain. */
+ * (>= 1; 0 = automatic).  block = 1024 selects the layer-staged variant (FP32
+ * contexts, at most 4535 nodes per layer): workgroups of 1024 threads stage
+ * whole layers in LDS and take kc layers each, the boundary columns run in a
+ * second launch.  Affects speed only, never results (the FP64 convergence sums
+ * are added in another order).  OSAM_E_INVALID for other values, an OpInf
+ * subdomain, or the layer-staged variant where it does not apply. */
 int32_t osam_set_fe_launch(osam_ctx *ctx, int32_t sd, int32_t block, int32_t kc);
 /* Current launch shape of FOM subdomain sd (any pointer may be NULL). */
 int32_t osam_get_fe_launch(osam_ctx *ctx, int32_t sd, int32_t *block, int32_t *kc);
@@ -287,6 +291,20 @@ int32_t osam_get_fe_launch(osam_ctx *ctx, int32_t sd, int32_t *block, int32_t *k
 int32_t osam_set_rom_path(osam_ctx *ctx, int32_t sd, int32_t path);
 /* The path subdomain sd's step uses once wired: 1 fused, 2 batched (0 for a FOM). */
 int32_t osam_get_rom_path(osam_ctx *ctx, int32_t sd, int32_t *path);
+
+/* Graph mode of run (rounds > 0, even): run captures `rounds` Schwarz sweeps
+ * into a HIP graph and replays it.  Inside a sweep the FOM kernels run on the
+ * context stream and the OpInf kernels on a second stream: every source pushes
+ * its next-step displacement into the buffer role of the next step, which no
+ * kernel of the sweep reads, so the two streams only meet at the finisher
+ * kernel, which takes the decision of Eq. conv_criterion (Alg. 1).  Results and
+ * iteration counts are those of the sequential launch (the sweep order of the
+ * multiplicative method is unchanged; the data each subdomain reads are the
+ * same).  A replay may run up to rounds - 1 sweeps past the last step; sweeps
+ * of finished instances change nothing.  Ignored while kernel timing is on.
+ * rounds = 0 (the default) launches every sweep from the host.  OSAM_E_INVALID
+ * for odd or negative values or more than 4096. */
+int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds);
 
 /* Wait for all queued work of the context (host synchronisation). */
 int32_t osam_sync(osam_ctx *ctx);

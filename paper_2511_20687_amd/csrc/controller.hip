@@ -41,10 +41,23 @@ double *Ctx::scratch(size_t n, int32_t *st) {
 
 // Launch shape of the FE kernel: columns x z-chunks x instances.  block/kc = 0
 // selects the default (256 threads, one layer per thread).
-void Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
+bool Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
   const int nl = s.nzs - 1;
-  int bs = block > 0 ? block : 256;
   auto per_chunk = [&](int b) { return (s.n_int + b - 1) / b + (s.n_bnd + b - 1) / b; };
+  s.max_nblocks = std::max(s.max_nblocks, per_chunk(64) * nl);
+  if (block == 1024) {
+    // layer-staged interior + column kernel for the boundary (FP32, cross-section fits the LDS)
+    if (prec == OSAM_FP64 || s.npl > kFeLdsMaxNodes) return false;
+    if (kc <= 0) kc = 8;
+    kc = std::max(1, std::min(kc, nl));
+    s.fe_block = 1024;
+    s.fe_kc = kc;
+    s.fe_chunks = (nl + kc - 1) / kc;
+    s.fe_int_blocks = 0;
+    s.fe_nblocks = s.fe_chunks + (s.n_bnd / 64) * nl;
+    return true;
+  }
+  int bs = block > 0 ? block : 256;
   if (kc <= 0) kc = 1;   // one node layer per thread: a single memory round trip
   kc = std::max(1, std::min(kc, nl));
   s.fe_block = bs;
@@ -52,7 +65,7 @@ void Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
   s.fe_chunks = (nl + kc - 1) / kc;
   s.fe_int_blocks = (s.n_int + bs - 1) / bs;
   s.fe_nblocks = per_chunk(bs) * s.fe_chunks;
-  s.max_nblocks = std::max(s.max_nblocks, per_chunk(64) * nl);
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -508,14 +521,15 @@ int32_t Ctx::init_pending() {
 // ---------------------------------------------------------------------------
 // What the decider of a sweep gathers: the FOM subdomains' partial sums and
 // the OpInf subdomains (other than the last) whose sums are in the output status.
-static FinishArgs finish_args(Ctx &c) {
+// defer: every OpInf kernel leaves its sums in the output status (graph mode)
+static FinishArgs finish_args(Ctx &c, bool defer = false) {
   FinishArgs F;
   std::memset(&F, 0, sizeof(F));
   const int last = (int)c.sds.size() - 1;
   for (int i = 0; i <= last; ++i) {
     const Subdomain &d = *c.sds[i];
     if (d.rom) {
-      if (i != last) F.rom_sd[F.nrom++] = i;
+      if (i != last || defer) F.rom_sd[F.nrom++] = i;
       continue;
     }
     F.sd[F.nfom] = i;
@@ -576,6 +590,8 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.n_bnd = s.n_bnd;
   A.int_blocks = s.fe_int_blocks;
   A.nblocks = s.fe_nblocks;
+  A.part_stride = s.fe_nblocks;
+  A.part_off = 0;
   A.bnd_cols = s.bnd_cols;
   A.rec_u = (T *)s.rec.u;
   A.rec_a = (T *)s.rec.a;
@@ -587,9 +603,10 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.face_off_hi = s.face_off_hi;
 }
 
-int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0, hipEvent_t ev1) {
+int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
   Subdomain &s = *sds[sdi];
   hipError_t e;
+  hipStream_t stream = st ? st : this->stream;
   if (prec == OSAM_FP64) {
     FeArgs<double> A;
     fill_fe_args<double>(*this, s, sdi, o, A);
@@ -597,7 +614,24 @@ int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0, hipE
   } else {
     FeArgs<float> A;
     fill_fe_args<float>(*this, s, sdi, o, A);
-    e = launch_fe<float>(A, batch, s.fe_block, mode, stream, ev0, ev1);
+    if (s.fe_block == 1024) {
+      // interior: layer-staged workgroups (partials 0 .. fe_chunks-1); boundary: the
+      // column kernel over the boundary blocks only (partials after those)
+      FeArgs<float> Ab = A;
+      A.nblocks = s.fe_chunks;
+      e = launch_fe<float>(A, batch, 1024, mode, stream, ev0, nullptr);
+      if (e == hipSuccess) {
+        const int nl = s.nzs - 1;
+        Ab.kc = 1;
+        Ab.n_chunks = nl;
+        Ab.int_blocks = 0;
+        Ab.nblocks = (s.n_bnd / 64) * nl;
+        Ab.part_off = s.fe_chunks;
+        e = launch_fe<float>(Ab, batch, 64, mode, stream, nullptr, ev1);
+      }
+    } else {
+      e = launch_fe<float>(A, batch, s.fe_block, mode, stream, ev0, ev1);
+    }
   }
   if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("fe kernel: ") + hipGetErrorString(e));
   return OSAM_OK;
@@ -723,9 +757,10 @@ static void fill_pre_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomPreAr
   P.opts = o;
 }
 
-int32_t Ctx::launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0, hipEvent_t ev1) {
+int32_t Ctx::launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st, bool defer) {
   Subdomain &s = *sds[sdi];
   hipError_t e;
+  hipStream_t stream = st ? st : this->stream;
   if (s.pre) {
     RomPreArgs P;
     fill_pre_args(*this, s, sdi, o, P);
@@ -735,10 +770,12 @@ int32_t Ctx::launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0, hipEvent_t ev
   if (prec == OSAM_FP64) {
     RomArgs<double> A;
     fill_rom_args<double>(*this, s, sdi, o, A);
+    A.defer = defer;
     e = launch_rom<double>(A, batch, stream, ev0, ev1);
   } else {
     RomArgs<float> A;
     fill_rom_args<float>(*this, s, sdi, o, A);
+    A.defer = defer;
     e = launch_rom<float>(A, batch, stream, ev0, ev1);
   }
   if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("rom kernel: ") + hipGetErrorString(e));
@@ -779,6 +816,33 @@ int32_t Ctx::launch_round(const Opts &o) {
   return OSAM_OK;
 }
 
+// One Schwarz sweep with the FOM kernels on the context stream and the OpInf
+// kernels on the auxiliary stream.  Within a sweep no kernel reads what another
+// writes: every source pushes its next-step displacement into the role of the
+// next step, which no kernel of the sweep reads, so the two streams only meet
+// at the finisher, which takes the decision of Eq. conv_criterion.
+int32_t Ctx::launch_round_concurrent(const Opts &o) {
+  bool any_rom = false;
+  for (auto &d : sds) any_rom |= d->rom;
+  if (any_rom) {
+    HIPCHK(hipEventRecord(fork_ev, stream));
+    HIPCHK(hipStreamWaitEvent(aux, fork_ev, 0));
+  }
+  int32_t st;
+  for (size_t i = 0; i < sds.size(); ++i)
+    if (!sds[i]->rom && (st = launch_fe_sd((int)i, o, 0))) return st;
+  for (size_t i = 0; i < sds.size(); ++i)
+    if (sds[i]->rom && (st = launch_rom_sd((int)i, o, nullptr, nullptr, aux, true))) return st;
+  if (any_rom) {
+    HIPCHK(hipEventRecord(join_ev, aux));
+    HIPCHK(hipStreamWaitEvent(stream, join_ev, 0));
+  }
+  const hipError_t e = launch_finish(d_status, d_status_alt, finish_args(*this, true), o, batch, stream);
+  if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("finish kernel: ") + hipGetErrorString(e));
+  std::swap(d_status, d_status_alt);
+  return OSAM_OK;
+}
+
 int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_info *info) {
   if (!(op.tol_abs >= 0) || !(op.tol_rel >= 0) || op.min_iter < 1 || op.max_iter < op.min_iter ||
       op.max_iter > 1000000 || (op.guess != OSAM_GUESS_HOLD && op.guess != OSAM_GUESS_PREDICTOR))
@@ -808,8 +872,38 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
     any |= n_steps > 0;
   }
   HIPCHK(hipMemcpyAsync(d_status, h_status, sizeof(Status) * batch, hipMemcpyHostToDevice, stream));
+  // graph mode: capture graph_rounds sweeps (an even number, so the status buffers
+  // are back in their roles after each replay) and replay whole graphs; sweeps
+  // of finished instances are no-ops, so a replay may run past the last step
+  struct ExecGuard {
+    hipGraphExec_t g = nullptr;
+    ~ExecGuard() {
+      if (g) (void)hipGraphExecDestroy(g);
+    }
+  } guard;
+  hipGraphExec_t &gexec = guard.g;
+  const bool graph = graph_rounds > 0 && !timing && any;
+  if (graph) {
+    if (!aux) {
+      HIPCHK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&join_ev, hipEventDisableTiming));
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < graph_rounds && !st; ++r) st = launch_round_concurrent(o);
+    const hipError_t ec = hipStreamEndCapture(stream, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess) return fail(OSAM_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(OSAM_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+  }
   // every step ends within max_iter sweeps: bound the total work the host enqueues
-  const long long round_cap = n_steps * (long long)o.max_iter + 8;
+  const long long round_cap = n_steps * (long long)o.max_iter + 8 + (graph ? 2LL * graph_rounds : 0);
   long long rounds_done = 0;
   while (any) {
     // every step needs at least min_iter sweeps: never enqueue more than the
@@ -821,10 +915,17 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
       rounds = std::max(rounds, (S.target - S.step) * o.min_iter - S.iter);
     }
     rounds = std::max<long long>(1, rounds);
+    if (graph) rounds = (rounds + graph_rounds - 1) / graph_rounds * graph_rounds;
     if (rounds_done + rounds > round_cap)
       return fail(OSAM_E_HIP, "controller did not finish within n_steps * max_iter sweeps");
-    for (long long k = 0; k < rounds; ++k)
-      if ((st = launch_round(o))) return st;
+    for (long long k = 0; k < rounds; k += graph ? graph_rounds : 1) {
+      if (graph) {
+        const hipError_t e = hipGraphLaunch(gexec, stream);
+        if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+      } else if ((st = launch_round(o))) {
+        return st;
+      }
+    }
     rounds_done += rounds;
     if ((st = sync_status())) return st;
     any = false;

@@ -6,6 +6,9 @@
 namespace osam {
 
 constexpr int kMaxSd = 8;
+// largest cross-section (nodes per layer) of the layer-staged FE variant: three
+// layers of three FP32 components in 160 KB of LDS
+constexpr int kFeLdsMaxNodes = 160 * 1024 / (9 * 4) - 16;
 
 // Per-instance controller state, in device memory.  Only the kernels modify it
 // while a run is in flight; the host reads it back between chunks of work.
@@ -192,7 +195,8 @@ struct FeArgs {
   Status *status;
   int sd;
   Opts opts;
-  double *partials;        // [batch][nblocks][2]
+  double *partials;        // [batch][part_stride][2], this launch's workgroups from part_off
+  int part_stride, part_off;
   int kc, n_chunks, n_int, n_bnd, int_blocks, nblocks;
   const int *bnd_cols;     // boundary columns (ids in the layer)
   // records: [batch][ncols][len]
@@ -242,6 +246,7 @@ struct RomArgs {
   long long rec_every, rec_ncols;
   // batched path: f0 = A q + H (q (x) q) + c and g^ of the FOM-fed faces come
   // precomputed as partial sums (A, H, c and FOM faces are then absent above)
+  int defer;               // 1: never decide, leave the sums for the finisher kernel
   const T *f0part;         // [f0_ks][batch][r] or null
   int f0_ks;
   const double *gpart;     // [g_gs][batch][rs] or null

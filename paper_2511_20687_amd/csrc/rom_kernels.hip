@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(kRomThreads) rom_kernel(RomArgs<T> A) {
   const int r = A.r, rs = A.rs, r2 = A.r2;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const long long qo = (long long)b * r;
-  const bool last = A.sd == A.opts.nsd - 1;
+  const bool last = !A.defer && A.sd == A.opts.nsd - 1;
   const FinishArgs &F = A.finish;
 
   extern __shared__ unsigned char smem_raw[];

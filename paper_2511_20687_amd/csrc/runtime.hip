@@ -296,6 +296,12 @@ void osam_ctx_destroy(osam_ctx *c) {
   ctx->allocs.clear();
   if (ctx->h_status) hipHostFree(ctx->h_status);
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  if (ctx->aux) {
+    hipStreamSynchronize(ctx->aux);
+    hipStreamDestroy(ctx->aux);
+    hipEventDestroy(ctx->fork_ev);
+    hipEventDestroy(ctx->join_ev);
+  }
   if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -582,10 +588,11 @@ int32_t osam_set_fe_launch(osam_ctx *c, int32_t sd, int32_t block, int32_t kc) {
   if (sd < 0 || sd >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
   Subdomain &s = *ctx->sds[sd];
   if (s.rom) return ctx->fail(OSAM_E_INVALID, "not a FOM subdomain");
-  if (!(block == 0 || block == 64 || block == 128 || block == 256) || kc < 0)
-    return ctx->fail(OSAM_E_INVALID, "block must be 0, 64, 128 or 256 and kc >= 0");
+  if (!(block == 0 || block == 64 || block == 128 || block == 256 || block == 1024) || kc < 0)
+    return ctx->fail(OSAM_E_INVALID, "block must be 0, 64, 128, 256 or 1024 and kc >= 0");
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  ctx->choose_fe_launch(s, block, kc);
+  if (!ctx->choose_fe_launch(s, block, kc))
+    return ctx->fail(OSAM_E_INVALID, "the layer-staged variant needs FP32 and a cross-section that fits the LDS");
   return OSAM_OK;
 }
 
@@ -596,6 +603,15 @@ int32_t osam_get_fe_launch(osam_ctx *c, int32_t sd, int32_t *block, int32_t *kc)
   const Subdomain &s = *ctx->sds[sd];
   if (block) *block = s.fe_block;
   if (kc) *kc = s.fe_kc;
+  return OSAM_OK;
+}
+
+int32_t osam_set_graph(osam_ctx *c, int32_t rounds) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  if (rounds < 0 || rounds > 4096 || (rounds % 2) != 0)
+    return ctx->fail(OSAM_E_INVALID, "graph rounds must be 0 or an even number up to 4096");
+  ctx->graph_rounds = rounds;
   return OSAM_OK;
 }
 

@@ -42,6 +42,9 @@ struct Subdomain {
   int *bnd_cols = nullptr;
   int n_int = 0, n_bnd = 0;
   double *partials = nullptr;
+  // FE launch shape: fe_block 64/128/256 = column kernel; 1024 = layer-staged kernel for the
+  // interior (fe_chunks workgroups of fe_kc layers) plus the column kernel (64 threads, one
+  // layer per thread) for the boundary columns; fe_nblocks = workgroup partials per instance
   int fe_block = 256, fe_kc = 8, fe_chunks = 1, fe_int_blocks = 0, fe_nblocks = 0, max_nblocks = 0;
   // OpInf
   bool rom = false;
@@ -111,7 +114,7 @@ struct Ctx {
   int32_t download(double *dst, const void *src, size_t n);
   double *scratch(size_t n, int32_t *st);
 
-  void choose_fe_launch(Subdomain &s, int block, int kc);
+  bool choose_fe_launch(Subdomain &s, int block, int kc);
   int32_t couple();
   int32_t wire();
   int32_t setup_pre(Subdomain &d);
@@ -124,11 +127,19 @@ struct Ctx {
   int32_t sync_status();
   int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info);
   int32_t launch_round(const Opts &o);
+  // graph mode: rounds replayed from a captured HIP graph, the FOM and OpInf
+  // kernels of a round on two streams, the decision in the finisher kernel
+  int graph_rounds = 0;
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  int32_t launch_round_concurrent(const Opts &o);
   hipEvent_t next_event();
   int32_t rom_start(int i, int inst, const std::vector<double> &q, const std::vector<double> &qd);
   int32_t run_adjoint(int64_t n, int64_t K, const osam_misfit &m, double *J, const osam_grads &g);
-  int32_t launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-  int32_t launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+  int32_t launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                       hipStream_t st = nullptr);
+  int32_t launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                        hipStream_t st = nullptr, bool defer = false);
   int32_t learn(int sd, const osam_opinf_desc &d);
 };
 

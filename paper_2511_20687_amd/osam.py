@@ -27,7 +27,7 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
             "osam_get_opinf", "schwarz_step", "run", "osam_set_timing", "osam_get_timing",
             "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
-            "osam_set_rom_path", "osam_get_rom_path", "osam_sync"]
+            "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_sync"]
 
 
 class OsamError(RuntimeError):
@@ -92,6 +92,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with `python -m paper_2511_20687_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system one that
+    # libosam links: load torch first so both resolve to the runtime torch was built
+    # against (loaded the other way round, torch finds no GPU)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     lib.osam_version.restype = i32
@@ -139,6 +143,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_set_fe_launch.restype = i32
     lib.osam_get_fe_launch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
     lib.osam_get_fe_launch.restype = i32
+    lib.osam_set_graph.argtypes = [vp, i32]
+    lib.osam_set_graph.restype = i32
     lib.osam_set_rom_path.argtypes = [vp, i32, i32]
     lib.osam_set_rom_path.restype = i32
     lib.osam_get_rom_path.argtypes = [vp, i32, C.POINTER(i32)]
@@ -393,6 +399,10 @@ class Context:
         b, k = C.c_int32(), C.c_int32()
         self._check(self.lib.osam_get_fe_launch(self.h, sd, C.byref(b), C.byref(k)))
         return b.value, k.value
+
+    def set_graph(self, rounds: int):
+        """Replay captured graphs of `rounds` Schwarz sweeps (0: launch every sweep)."""
+        self._check(self.lib.osam_set_graph(self.h, rounds))
 
     def set_rom_path(self, sd: int, path: int):
         """0 automatic, 1 fused, 2 batched (see osam_set_rom_path)."""

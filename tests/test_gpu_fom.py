@@ -13,11 +13,16 @@ from tests._gpu import lib_free_index, lib_index_of, lib_sch_index, oracle_fom_c
 pytestmark = pytest.mark.gpu
 
 
-def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s=False, lateral_fix=()):
+def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s=False, lateral_fix=(),
+             fe_launch=None):
     import torch
     from paper_2511_20687_amd import osam
     ctx = osam.Context(0, precision, batch)
     sds = osam.add_bar_subdomains(ctx, bar, layers, dt, lateral_fix=lateral_fix)
+    if fe_launch is not None:
+        for sd in sds:
+            ctx.set_fe_launch(sd, *fe_launch)
+            assert ctx.get_fe_launch(sd)[0] == fe_launch[0]
     dev = torch.device("cuda:0")
     recs = []
     for sd in sds:
@@ -171,3 +176,36 @@ def test_state_readback_and_nonfinite_detection_f64():
     ctx2.set_initial(0, bad, v0)
     info2 = ctx2.run(5, osam.Options(), check=False)
     assert info2[0]["status"] == osam.OSAM_E_NONFINITE
+
+
+@pytest.mark.parametrize("lateral", [(0, 1), ()])
+@pytest.mark.parametrize("kc", [1, 5, 64])
+def test_layer_staged_fe_variant_f32(kc, lateral):
+    """The layer-staged FE variant (whole layers in LDS, 1024-thread workgroups of kc layers,
+    boundary columns in a second launch) against the column kernel on every record of a
+    batch of 2 (u and the Schwarz face data, three slabs, a 6 x 5 cross-section) and
+    against the oracle (FP32 bar)."""
+    bar = Bar(6, 5, 48)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 3)
+    u0 = [gaussian_pulse_u(bar, 1e-3, 0.3, 0.05), gaussian_pulse_u(bar, 2e-3, 0.6, 0.04)]
+    v0 = [np.zeros_like(u0[0]), np.zeros_like(u0[1])]
+    v0[1][0] = 2.0 * np.exp(-((bar.node_z() - 0.5) ** 2) / (2 * 0.05 ** 2))
+    n = 200
+    print(f"[layer-staged kc={kc} lateral={lateral}] gpu", flush=True)
+    _, rc, ic = _lib_run(bar, layers, dt, u0, v0, n, "f32", batch=2, record_s=True, lateral_fix=lateral)
+    _, rl, il = _lib_run(bar, layers, dt, u0, v0, n, "f32", batch=2, record_s=True, lateral_fix=lateral,
+                         fe_launch=(1024, kc))
+    for i in range(len(layers)):
+        for b in range(2):
+            du = rel_err(rl[i][0][b], rc[i][0][b])
+            ds = rel_err(rl[i][1][b], rc[i][1][b])
+            assert du <= 1e-6 and ds <= 1e-6, (i, b, du, ds)
+    assert [x["total_iters"] for x in il] == [x["total_iters"] for x in ic]
+    models, ref = oracle_fom_coupled(bar, layers, dt, u0[1], v0[1], n, record=("u", "s"), lateral_fix=lateral)
+    for i, m in enumerate(models):
+        lo, hi = layers[i]
+        e_u = rel_err(rl[i][0][1][:, lib_index_of(m)], ref["u"][i])
+        e_s = rel_err(rl[i][1][1][:, lib_sch_index(bar, lo, hi)], ref["s"][i])
+        print(f"subdomain {i}: u {e_u:.2e}, s {e_s:.2e}")
+        assert e_u <= 1e-4 and e_s <= 1e-4
