@@ -293,18 +293,43 @@ int32_t osam_set_rom_path(osam_ctx *ctx, int32_t sd, int32_t path);
 int32_t osam_get_rom_path(osam_ctx *ctx, int32_t sd, int32_t *path);
 
 /* Graph mode of run (rounds > 0, even): run captures `rounds` Schwarz sweeps
- * into a HIP graph and replays it.  Inside a sweep the FOM kernels run on the
- * context stream and the OpInf kernels on a second stream: every source pushes
- * its next-step displacement into the buffer role of the next step, which no
- * kernel of the sweep reads, so the two streams only meet at the finisher
- * kernel, which takes the decision of Eq. conv_criterion (Alg. 1).  Results and
- * iteration counts are those of the sequential launch (the sweep order of the
- * multiplicative method is unchanged; the data each subdomain reads are the
- * same).  A replay may run up to rounds - 1 sweeps past the last step; sweeps
- * of finished instances change nothing.  Ignored while kernel timing is on.
- * rounds = 0 (the default) launches every sweep from the host.  OSAM_E_INVALID
- * for odd or negative values or more than 4096. */
-int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds);
+ * (Alg. 1) into a HIP graph and replays it, which saves the host's launch work
+ * and part of the dispatch latency per kernel.  streams = 1 captures the
+ * sweeps as they are launched otherwise.  streams = 2 runs the FOM kernels of
+ * a sweep on the context stream and the OpInf kernels on a second stream:
+ * every source pushes its next-step displacement into the buffer role of the
+ * next step, which no kernel of the sweep reads, so the streams only meet at a
+ * finisher kernel, which takes the decision of Eq. conv_criterion; this pays
+ * where the kernels are long next to a cross-stream dependency.  Results and
+ * iteration counts are those of the sequential launch in both cases (the data
+ * each subdomain reads are the same).  A replay may run up to rounds - 1 sweeps
+ * past the last step; sweeps of finished instances change nothing.  Ignored
+ * while kernel timing is on.  rounds = 0 (the default) launches every sweep
+ * from the host.  OSAM_E_INVALID for odd or negative rounds, more than 4096,
+ * or streams other than 1 and 2. */
+int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds, int32_t streams);
+
+/* Launch-configuration autotuner.  Times trial runs of trial_steps controller
+ * steps (after 2 warm-up steps) from the context's current state with `opts`,
+ * and keeps, one coordinate at a time, the fastest: the FE launch shape of each
+ * FOM subdomain (osam_set_fe_launch: 256/1, 128/1, 64/1, 64/2, 256/8, 64/8 and,
+ * where it applies, the layer-staged 1024 with 4, 8, 16 layers), the OpInf
+ * path of each OpInf subdomain of an FP32 context (osam_set_rom_path 1 or 2)
+ * and the launch mode (osam_set_graph: none, 32 or 128 sweeps on one stream,
+ * 32 on two).  None of these changes results.  The choice is cached for the
+ * process per configuration (precision, batch, subdomain and reduced sizes) and
+ * applied without trials on a later call (from_cache = 1).  The trials advance
+ * the state: set the initial condition again before the production run.
+ * *out (may be NULL) receives the choice per subdomain id and the trial time of
+ * the winner.  OSAM_E_ORDER if an instance has no initial condition. */
+typedef struct {
+  int32_t fe_block[8], fe_kc[8];   /* FOM subdomains (0 for OpInf) */
+  int32_t rom_path[8];             /* OpInf subdomains (0 for FOM) */
+  int32_t graph_rounds, graph_streams;
+  double ms_per_step;              /* wall time per step of the chosen configuration's trial */
+  int32_t from_cache;
+} osam_tuning;
+int32_t osam_autotune(osam_ctx *ctx, int64_t trial_steps, const osam_schwarz_opts *opts, osam_tuning *out);
 
 /* Wait for all queued work of the context (host synchronisation). */
 int32_t osam_sync(osam_ctx *ctx);

@@ -891,7 +891,7 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
     }
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    for (int r = 0; r < graph_rounds && !st; ++r) st = launch_round_concurrent(o);
+    for (int r = 0; r < graph_rounds && !st; ++r) st = graph_streams == 2 ? launch_round_concurrent(o) : launch_round(o);
     const hipError_t ec = hipStreamEndCapture(stream, &g);
     if (st) {
       if (g) (void)hipGraphDestroy(g);

@@ -606,12 +606,13 @@ int32_t osam_get_fe_launch(osam_ctx *c, int32_t sd, int32_t *block, int32_t *kc)
   return OSAM_OK;
 }
 
-int32_t osam_set_graph(osam_ctx *c, int32_t rounds) {
+int32_t osam_set_graph(osam_ctx *c, int32_t rounds, int32_t streams) {
   if (!c) return OSAM_E_INVALID;
   Ctx *ctx = reinterpret_cast<Ctx *>(c);
-  if (rounds < 0 || rounds > 4096 || (rounds % 2) != 0)
-    return ctx->fail(OSAM_E_INVALID, "graph rounds must be 0 or an even number up to 4096");
+  if (rounds < 0 || rounds > 4096 || (rounds % 2) != 0 || streams < 1 || streams > 2)
+    return ctx->fail(OSAM_E_INVALID, "graph rounds must be 0 or an even number up to 4096, streams 1 or 2");
   ctx->graph_rounds = rounds;
+  ctx->graph_streams = streams;
   return OSAM_OK;
 }
 

@@ -129,10 +129,12 @@ struct Ctx {
   int32_t launch_round(const Opts &o);
   // graph mode: rounds replayed from a captured HIP graph, the FOM and OpInf
   // kernels of a round on two streams, the decision in the finisher kernel
-  int graph_rounds = 0;
+  int graph_rounds = 0, graph_streams = 1;
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int32_t launch_round_concurrent(const Opts &o);
+  int32_t autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out);
+  int32_t apply_tuning(const osam_tuning &t);
   hipEvent_t next_event();
   int32_t rom_start(int i, int inst, const std::vector<double> &q, const std::vector<double> &qd);
   int32_t run_adjoint(int64_t n, int64_t K, const osam_misfit &m, double *J, const osam_grads &g);

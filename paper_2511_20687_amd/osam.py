@@ -27,7 +27,7 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
             "osam_get_opinf", "schwarz_step", "run", "osam_set_timing", "osam_get_timing",
             "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
-            "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_sync"]
+            "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_autotune", "osam_sync"]
 
 
 class OsamError(RuntimeError):
@@ -69,6 +69,12 @@ class Grads(C.Structure):
                 ("dB", C.POINTER(C.c_double) * 8), ("dc", C.POINTER(C.c_double) * 8),
                 ("dq0", C.POINTER(C.c_double) * 8), ("dqd0", C.POINTER(C.c_double) * 8),
                 ("du0", C.c_void_p * 8), ("dv0", C.c_void_p * 8)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("fe_block", C.c_int32 * 8), ("fe_kc", C.c_int32 * 8), ("rom_path", C.c_int32 * 8),
+                ("graph_rounds", C.c_int32), ("graph_streams", C.c_int32), ("ms_per_step", C.c_double),
+                ("from_cache", C.c_int32)]
 
 
 class SchwarzOpts(C.Structure):
@@ -143,7 +149,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_set_fe_launch.restype = i32
     lib.osam_get_fe_launch.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32)]
     lib.osam_get_fe_launch.restype = i32
-    lib.osam_set_graph.argtypes = [vp, i32]
+    lib.osam_autotune.argtypes = [vp, i64, C.POINTER(SchwarzOpts), C.POINTER(Tuning)]
+    lib.osam_autotune.restype = i32
+    lib.osam_set_graph.argtypes = [vp, i32, i32]
     lib.osam_set_graph.restype = i32
     lib.osam_set_rom_path.argtypes = [vp, i32, i32]
     lib.osam_set_rom_path.restype = i32
@@ -400,9 +408,20 @@ class Context:
         self._check(self.lib.osam_get_fe_launch(self.h, sd, C.byref(b), C.byref(k)))
         return b.value, k.value
 
-    def set_graph(self, rounds: int):
-        """Replay captured graphs of `rounds` Schwarz sweeps (0: launch every sweep)."""
-        self._check(self.lib.osam_set_graph(self.h, rounds))
+    def autotune(self, trial_steps: int = 20, opts: "Options" = None) -> dict:
+        """Fastest launch configuration by trial runs (osam_autotune); the trials advance the
+        state, so set the initial condition again afterwards."""
+        t = Tuning()
+        o = (opts or Options()).c()
+        self._check(self.lib.osam_autotune(self.h, trial_steps, C.byref(o), C.byref(t)))
+        n = self.n_sd
+        return dict(fe=[(t.fe_block[i], t.fe_kc[i]) for i in range(n)], rom_path=list(t.rom_path[:n]),
+                    graph=(t.graph_rounds, t.graph_streams), ms_per_step=t.ms_per_step, from_cache=bool(t.from_cache))
+
+    def set_graph(self, rounds: int, streams: int = 1):
+        """Replay captured graphs of `rounds` Schwarz sweeps (0: launch every sweep);
+        streams = 2 runs the FOM and OpInf kernels of a sweep concurrently."""
+        self._check(self.lib.osam_set_graph(self.h, rounds, streams))
 
     def set_rom_path(self, sd: int, path: int):
         """0 automatic, 1 fused, 2 batched (see osam_set_rom_path)."""
