@@ -116,6 +116,13 @@ def main():
     u0 = pulse.u0(w.bar)
     v0 = np.zeros_like(u0)
 
+    # ---- launch configuration by the library's autotuner (untimed set-up) ----
+    ctx.set_initial(0, u0, v0)
+    t0 = time.perf_counter()
+    tuning = ctx.autotune(trial_steps=200, opts=opts)
+    t_tune = time.perf_counter() - t0
+    _log(f"autotune {t_tune:.2f} s: {tuning}")
+
     # ---- timed region: K complete online FOM-OpInf runs ----
     for i in range(args.warmup):
         ctx.set_initial(0, u0, v0)
@@ -183,6 +190,8 @@ def main():
     del frec, hyb
     ff2 = build_context(w, w.precision)
     ff2.set_initial(0, u0, v0)
+    ff_tuning = ff2.autotune(trial_steps=200, opts=opts)   # the best FOM-FOM launch on this GPU too
+    ff2.set_initial(0, u0, v0)
     ff2.run(n, opts)      # warm-up
     ff2.set_initial(0, u0, v0)
     torch.cuda.synchronize()
@@ -225,11 +234,14 @@ def main():
         "rom_kernel_avg_us": 1e3 * rom_ms / max(rom_launches, 1),
         "train_run_s": t_train,
         "learn_s": t_learn,
+        "launch": {"hybrid": tuning, "fom_fom": ff_tuning, "autotune_s": t_tune},
         "roofline": {"bound": "hbm", "achieved": fe_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": fe_gbs / HBM_PEAK_GBS, "traffic": traffic_bytes,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
-                     "kernel": "fe_kernel<float, step>", "bytes_per_dof": FE_BYTES_PER_DOF,
+                     "kernel": ("fe_lds_kernel<step> + boundary fe_kernel<float, step>" if tuning["fe"][0][0] == 1024
+                                else "fe_kernel<float, step>"),
+                     "launch_shape": tuning["fe"][0], "bytes_per_dof": FE_BYTES_PER_DOF,
                      "dofs_per_launch": fe_dofs, "algorithmic_bytes_per_launch": FE_BYTES_PER_DOF * fe_dofs},
         "cpu_baseline": cpu,
     }

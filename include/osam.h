@@ -159,7 +159,11 @@ int32_t osam_set_record(osam_ctx *ctx, int32_t sd, const osam_record *rec);
  * lambda on ties, non-finite = +inf) and the operators are refit with it.  On
  * success sd becomes an OpInf subdomain.  Outputs (host, may be NULL): sigma
  * (singular values of U, min(n_free, n_traj*T) entries), E_lambda [n_lambda],
- * lambda_star, r_out, rs_out. */
+ * lambda_star, r_out, rs_out.  stride: time steps between consecutive snapshots
+ * (0 or 1: every step).  The fit is pointwise in time (Udd holds the Newmark
+ * accelerations of the snapshot times); the Alg. 3 rollout takes `stride`
+ * steps between snapshots with the boundary input interpolated linearly
+ * between the two snapshots. */
 typedef struct {
   int32_t form, with_c;
   int32_t r, r_s;
@@ -171,6 +175,7 @@ typedef struct {
   const void *U, *Udd, *S, *V0;
   double *sigma_out, *E_lambda_out, *lambda_star_out;
   int32_t *r_out, *rs_out;
+  int32_t stride;
 } osam_opinf_desc;
 int32_t learn_opinf(osam_ctx *ctx, int32_t sd, const osam_opinf_desc *desc);
 

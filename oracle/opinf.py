@@ -116,16 +116,25 @@ def fit(Qs: List[np.ndarray], Qdds: List[np.ndarray], Shats: List[Optional[np.nd
 
 
 def rollout_frozen(ops: Operators, q0, qd0, qdd0, Shat: Optional[np.ndarray], n_cols: int,
-                   dt: float, beta: float = 0.0, gamma: float = 0.5) -> np.ndarray:
-    """Alg. 3 inner loop: q^{j+1} from q^j with g^ = S^[:, j+1] frozen; returns r x n_cols."""
+                   dt: float, beta: float = 0.0, gamma: float = 0.5, stride: int = 1) -> np.ndarray:
+    """Alg. 3 inner loop: from snapshot column j to j+1, `stride` time steps with the
+    training boundary input frozen; returns r x n_cols at the snapshot times.
+
+    Reading (Alg. 3 assumes a snapshot per step): with snapshots every `stride` steps the
+    boundary input of the steps in between is interpolated linearly between the two
+    snapshots (exactly S^[:, j+1] at the end of the interval; stride 1 is the plain rule)."""
     r = q0.shape[0]
     out = np.zeros((r, n_cols), dtype=np.result_type(q0, ops.A))
     q, qd, qdd = np.array(q0), np.array(qd0), np.array(qdd0)
     out[:, 0] = q
     with np.errstate(all="ignore"):
         for j in range(n_cols - 1):
-            gh = Shat[:, j + 1] if Shat is not None else np.zeros(0)
-            q, qd, qdd = newmark_reduced_step(ops, q, qd, qdd, gh, dt, beta, gamma)
+            for m in range(1, stride + 1):
+                if Shat is None:
+                    gh = np.zeros(0)
+                else:
+                    gh = Shat[:, j] + (m / stride) * (Shat[:, j + 1] - Shat[:, j])
+                q, qd, qdd = newmark_reduced_step(ops, q, qd, qdd, gh, dt, beta, gamma)
             out[:, j + 1] = q
             if not np.all(np.isfinite(q)):
                 out[:, j + 1:] = np.nan
@@ -142,8 +151,9 @@ def trajectory_error(Qrom: np.ndarray, Q: np.ndarray, blowup: float = 1e6) -> fl
 
 
 def select_lambda(trajs: List[dict], lambdas, form: str = "linear", with_c: bool = False,
-                  dt: float = 1.0, beta: float = 0.0, gamma: float = 0.5):
-    """Alg. 3.  trajs: dicts with Q (r x T), Qd0 (r), Qdd (r x T), Shat (r_S x T | None).
+                  dt: float = 1.0, beta: float = 0.0, gamma: float = 0.5, stride: int = 1):
+    """Alg. 3.  trajs: dicts with Q (r x T), Qd0 (r), Qdd (r x T), Shat (r_S x T | None);
+    snapshots every `stride` time steps of length dt.
 
     Returns (lambda_star, E (n_lambda,), operators refit at lambda_star).
     """
@@ -157,7 +167,7 @@ def select_lambda(trajs: List[dict], lambdas, form: str = "linear", with_c: bool
         errs = []
         for t in trajs:
             Qrom = rollout_frozen(ops, t["Q"][:, 0], t["Qd0"], t["Qdd"][:, 0], t.get("Shat"),
-                                  t["Q"].shape[1], dt, beta, gamma)
+                                  t["Q"].shape[1], dt, beta, gamma, stride)
             errs.append(trajectory_error(Qrom, t["Q"]))
         E[li] = np.mean(errs)
     best = int(np.argmin(E))            # first minimiser = smallest lambda on ties

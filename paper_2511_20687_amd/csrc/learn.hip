@@ -44,7 +44,7 @@ hipError_t launch_offnorm(const double *, long long, double *, int, hipStream_t)
 hipError_t launch_identity(double *, long long, hipStream_t);
 hipError_t launch_gather_cols(const double *, long long, const int *, int, double *, hipStream_t);
 hipError_t launch_rollout(const double *, int, int, int, int, int, const double *, const double *, const double *,
-                          const double *, long long, int, int, double, double *, hipStream_t);
+                          const double *, long long, int, int, double, int, double *, hipStream_t);
 
 namespace {
 
@@ -385,7 +385,8 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   if (nlam > 1) {
     double *ro = L.alloc((size_t)nlam * ntraj * 5);
     if (L.code) return ctx->fail(L.code, L.err);
-    L.ok(launch_rollout(Xall, p, r, r2, rs, with_c, Q, Qd0, Qdd, Sh, Tn, ntraj, nlam, 1.0, ro, L.s),
+    L.ok(launch_rollout(Xall, p, r, r2, rs, with_c, Q, Qd0, Qdd, Sh, Tn, ntraj, nlam, 1.0, std::max(1, d.stride), ro,
+                        L.s),
          "rollout");
     std::vector<double> h = L.down(ro, (size_t)nlam * ntraj * 5);
     if (L.code) return ctx->fail(L.code, L.err);

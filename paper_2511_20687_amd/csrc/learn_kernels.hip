@@ -677,7 +677,7 @@ hipError_t launch_data_matrix(const double *Q, int r, const double *Sh, int rs, 
 __global__ void __launch_bounds__(256) rollout_kernel(const double *X, int p, int r, int r2, int rs, int with_c,
                                                       const double *Q, const double *Qd0, const double *Qdd,
                                                       const double *Sh, long long T, int ntraj, double dt,
-                                                      double *out) {
+                                                      int stride, double *out) {
   extern __shared__ double sm[];
   double *z = sm;               // [p] regressor vector
   double *q = z + p;            // [r]
@@ -707,36 +707,43 @@ __global__ void __launch_bounds__(256) rollout_kernel(const double *X, int p, in
     qmax = rmax = sqrt(n0);
   }
   for (long long j = 0; j + 1 < T && !bad; ++j) {
-    // predictor and regressors at step j+1
-    for (int i = tid; i < r; i += bs) {
-      const double qn = q[i] + dt * qd[i] + 0.5 * dt * dt * qdd[i];
-      z[i] = qn;
-    }
-    __syncthreads();
-    if (r2 > 0)
-      for (int e = tid; e < r * r; e += bs) {
-        const int i = e / r, jj = e - i * r;
-        if (jj >= i) z[r + i * r - (i * (i - 1)) / 2 + (jj - i)] = z[i] * z[jj];
+    // `stride` steps from snapshot j to j+1; the boundary input in between is
+    // interpolated linearly between the two snapshots (the last step takes S^_{j+1})
+    for (int m = 1; m <= stride; ++m) {
+      // predictor and regressors at the next step
+      for (int i = tid; i < r; i += bs) {
+        const double qn = q[i] + dt * qd[i] + 0.5 * dt * dt * qdd[i];
+        z[i] = qn;
       }
-    for (int e = tid; e < rs; e += bs) z[r + r2 + e] = Sht[(j + 1) * rs + e];
-    if (with_c && tid == 0) z[p - 1] = 1.0;
-    __syncthreads();
-    // q'' = X^T z : one wave per output
-    for (int i = wid; i < r; i += nw) {
-      double s = 0.0;
-      const double *xc = Xl + (long long)i * p;
-      for (int m = lane; m < p; m += 64) s += xc[m] * z[m];
-      s = wsum(s);
-      if (lane == 0) {
-        const double an = s;
-        qd[i] = qd[i] + 0.5 * dt * (qdd[i] + an);
-        qdd[i] = an;
+      __syncthreads();
+      if (r2 > 0)
+        for (int e = tid; e < r * r; e += bs) {
+          const int i = e / r, jj = e - i * r;
+          if (jj >= i) z[r + i * r - (i * (i - 1)) / 2 + (jj - i)] = z[i] * z[jj];
+        }
+      const double w1 = (double)m / (double)stride;
+      for (int e = tid; e < rs; e += bs)
+        z[r + r2 + e] = Sht[j * rs + e] + w1 * (Sht[(j + 1) * rs + e] - Sht[j * rs + e]);
+      if (with_c && tid == 0) z[p - 1] = 1.0;
+      __syncthreads();
+      // q'' = X^T z : one wave per output
+      for (int i = wid; i < r; i += nw) {
+        double s = 0.0;
+        const double *xc = Xl + (long long)i * p;
+        for (int mm = lane; mm < p; mm += 64) s += xc[mm] * z[mm];
+        s = wsum(s);
+        if (lane == 0) {
+          const double an = s;
+          qd[i] = qd[i] + 0.5 * dt * (qdd[i] + an);
+          qdd[i] = an;
+        }
       }
+      __syncthreads();
+      for (int i = tid; i < r; i += bs) q[i] = z[i];
+      __syncthreads();
     }
-    __syncthreads();
     double e2 = 0.0, rr = 0.0, nn = 0.0;
     for (int i = tid; i < r; i += bs) {
-      q[i] = z[i];
       const double d = q[i] - Qt[(j + 1) * r + i];
       e2 += d * d;
       rr += Qt[(j + 1) * r + i] * Qt[(j + 1) * r + i];
@@ -762,11 +769,11 @@ __global__ void __launch_bounds__(256) rollout_kernel(const double *X, int p, in
 }
 hipError_t launch_rollout(const double *X, int p, int r, int r2, int rs, int with_c, const double *Q,
                           const double *Qd0, const double *Qdd, const double *Sh, long long T, int ntraj, int nlam,
-                          double dt, double *out, hipStream_t s) {
+                          double dt, int stride, double *out, hipStream_t s) {
   const size_t smem = sizeof(double) * (size_t)(p + 3 * r);
   if (smem > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rollout_kernel, dim3(nlam * ntraj), dim3(256), smem, s, X, p, r, r2, rs, with_c, Q, Qd0, Qdd,
-                     Sh, T, ntraj, dt, out);
+                     Sh, T, ntraj, dt, stride, out);
   return hipGetLastError();
 }
 

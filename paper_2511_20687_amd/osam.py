@@ -57,7 +57,7 @@ class OpinfDesc(C.Structure):
                 ("U", C.c_void_p), ("Udd", C.c_void_p), ("S", C.c_void_p), ("V0", C.c_void_p),
                 ("sigma_out", C.POINTER(C.c_double)), ("E_lambda_out", C.POINTER(C.c_double)),
                 ("lambda_star_out", C.POINTER(C.c_double)), ("r_out", C.POINTER(C.c_int32)),
-                ("rs_out", C.POINTER(C.c_int32))]
+                ("rs_out", C.POINTER(C.c_int32)), ("stride", C.c_int32)]
 
 
 class Misfit(C.Structure):
@@ -305,7 +305,7 @@ class Context:
 
     def learn_opinf(self, sd: int, U, Udd, S, V0, n_traj: int, T: int, form: str = "linear",
                     r: int = 0, r_s: int = 0, energy: float = 1 - 1e-6, energy_bnd: float = 1 - 1e-6,
-                    lambdas: Sequence[float] = (1e-10,), with_c: bool = False):
+                    lambdas: Sequence[float] = (1e-10,), with_c: bool = False, stride: int = 1):
         lam = _f64(list(lambdas))
         z = self.sizes(sd)
         nsig = min(z["n_free"], n_traj * T)
@@ -315,7 +315,7 @@ class Context:
         ro, rso = C.c_int32(), C.c_int32()
         d = OpinfDesc(1 if form == "quadratic" else 0, int(with_c), r, r_s, energy, energy_bnd, len(lam),
                       _dptr(lam), n_traj, T, _devptr(U), _devptr(Udd), _devptr(S), _devptr(V0),
-                      _dptr(sig), _dptr(E), C.pointer(ls), C.pointer(ro), C.pointer(rso))
+                      _dptr(sig), _dptr(E), C.pointer(ls), C.pointer(ro), C.pointer(rso), stride)
         self._check(self.lib.learn_opinf(self.h, sd, C.byref(d)))
         return dict(sigma=sig, E_lambda=E, lambda_star=ls.value, r=ro.value, r_s=rso.value)
 

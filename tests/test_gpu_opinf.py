@@ -216,3 +216,55 @@ def test_learning_pipeline_matches_oracle(form, lateral_fix):
     e1 = rel_err(rom_u, on["u"][1])
     print("online errors", e0, e1)
     assert e0 <= 1e-7 and e1 <= 1e-7
+
+
+@pytest.mark.parametrize("form", ["linear", "quadratic"])
+def test_learning_two_trajectories_strided_snapshots_matches_oracle(form):
+    """Two training trajectories (different pulses), snapshots every 3 time steps: POD
+    singular values, r_s, lambda* and E(lambda) of Alg. 3 against the oracle (its rollout
+    takes 3 steps per snapshot interval with the boundary input interpolated linearly)."""
+    import torch
+    from paper_2511_20687_amd import osam
+    from oracle.pod import energy_rank
+    bar = Bar(2, 2, 40)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    stride, T = 3, 100
+    pulses = [gaussian_pulse_u(bar, 1e-3, 0.3, 0.06), gaussian_pulse_u(bar, 1.5e-3, 0.2, 0.05)]
+    r = 8 if form == "linear" else 6
+    print(f"[learn 2 trajectories stride {stride} {form}]", flush=True)
+    models = [FomModel(bar, lo, hi, dt) for lo, hi in layers]
+    refs = [Coupled(models).run(u0, np.zeros_like(u0), stride * (T - 1), SchwarzOptions(), every=stride,
+                                record=("u", "a", "s", "v")) for u0 in pulses]
+    ctx = osam.Context(0, "f64", 2)
+    osam.add_bar_subdomains(ctx, bar, layers, dt)
+    z = ctx.sizes(1)
+    dev = "cuda:0"
+    U = torch.zeros((2, T, z["n_free"]), dtype=torch.float64, device=dev)
+    A = torch.zeros((2, T, z["n_free"]), dtype=torch.float64, device=dev)
+    S = torch.zeros((2, T, z["n_sch"]), dtype=torch.float64, device=dev)
+    ctx.set_record(1, stride, T, u=U, a=A, s=S)
+    for b, u0 in enumerate(pulses):
+        ctx.set_initial(b, u0, np.zeros_like(u0))
+    ctx.run(stride * (T - 1))
+    V0 = torch.zeros((2, z["n_free"]), dtype=torch.float64, device=dev)
+    lams = lambda_grid(11)
+    out = ctx.learn_opinf(1, U, A, S, V0, 2, T, form=form, r=r, r_s=0, energy_bnd=1 - 1e-6,
+                          lambdas=list(lams), stride=stride)
+    Uo = np.hstack([rf["u"][1].T for rf in refs])
+    Ao = np.hstack([rf["a"][1].T for rf in refs])
+    So = np.hstack([rf["s"][1].T for rf in refs])
+    Phi, sig = pod(Uo, r=r)
+    _, sS = pod(So)
+    rs = energy_rank(sS, 1 - 1e-6)
+    PhiS, _ = pod(So, r=rs)
+    trajs = [dict(Q=Phi.T @ rf["u"][1].T, Qd0=Phi.T @ rf["v"][1][0], Qdd=Phi.T @ rf["a"][1].T,
+                  Shat=PhiS.T @ rf["s"][1].T) for rf in refs]
+    lam, E, _ = select_lambda(trajs, lams, form=form, dt=dt, stride=stride)
+    print("E gpu", out["E_lambda"], "\nE ora", E)
+    assert out["r_s"] == rs
+    assert np.allclose(out["sigma"][:r], sig[:r], rtol=1e-8)
+    assert out["lambda_star"] == lam
+    fin = np.isfinite(E) & (E < 1.0)
+    assert fin.any()
+    assert np.allclose(out["E_lambda"][fin], E[fin], rtol=1e-5, atol=1e-9)

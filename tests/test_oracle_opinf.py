@@ -228,3 +228,27 @@ def test_normalised_fit_is_stationary_point_of_scaled_objective(with_c):
     # the raw fit (dt = alpha = 1) with the same lambda is a different, over-regularised model
     raw = fit([Q], [Qdd], [Sh], lam, form="quadratic", with_c=with_c)
     assert np.abs(raw.A - o.A).max() > 1e-3 * np.abs(o.A).max()
+
+
+def test_strided_rollout_equals_every_stride_th_step_of_the_full_rollout():
+    """Alg. 3 rollout with snapshots every 3 steps: with a boundary input linear in time the
+    interpolation between snapshots is exact, so the strided rollout equals every third
+    column of the step-by-step rollout (a dropped or doubled step, or an interpolation with
+    the wrong weight, breaks the equality)."""
+    from oracle.opinf import Operators, rollout_frozen
+    rng = np.random.default_rng(5)
+    r, rs, dt, stride, ncol = 4, 2, 1e-3, 3, 9
+    Vm = np.linalg.qr(rng.standard_normal((r, r)))[0]
+    A = -(Vm * (np.linspace(100.0, 900.0, r) ** 2)) @ Vm.T
+    B = rng.standard_normal((r, rs))
+    ops = Operators(A=A, H=None, B=B, c=None)
+    q0, qd0 = rng.standard_normal(r), rng.standard_normal(r)
+    a, b = rng.standard_normal(rs), rng.standard_normal(rs)
+    full_n = stride * (ncol - 1) + 1
+    S_full = a[:, None] + b[:, None] * np.arange(full_n)[None, :] * dt     # linear in time
+    qdd0 = A @ q0 + B @ S_full[:, 0]
+    full = rollout_frozen(ops, q0, qd0, qdd0, S_full, full_n, dt)
+    strided = rollout_frozen(ops, q0, qd0, qdd0, S_full[:, ::stride], ncol, dt, stride=stride)
+    assert np.allclose(strided, full[:, ::stride], rtol=1e-12, atol=1e-14)
+    # and stride 1 is the plain rule
+    assert np.array_equal(rollout_frozen(ops, q0, qd0, qdd0, S_full, full_n, dt, stride=1), full)
