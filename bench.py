@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched OpInf-OpInf comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -202,6 +204,19 @@ def main():
     fom_fom_value = n / t_ff
     _log(f"hybrid {value:.0f} steps/s, FOM-FOM {fom_fom_value:.0f} steps/s, errors {errs}")
 
+    # ---- batched OpInf-OpInf (48x48x480, 256 instances) against FOM-FOM on this GPU ----
+    batched = None
+    if not args.no_batched:
+        from paper_2511_20687_amd import batched_case
+        del ctx, ff, ff2
+        torch.cuda.empty_cache()
+        batched = batched_case.run(log=_log)
+
+    # ---- adjoint of the coupled rollout, 24x24x240 FOM + quadratic OpInf r=60 ----
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_timing(_log)
+
     # ---- CPU oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -244,8 +259,47 @@ def main():
                      "launch_shape": tuning["fe"][0], "bytes_per_dof": FE_BYTES_PER_DOF,
                      "dofs_per_launch": fe_dofs, "algorithmic_bytes_per_launch": FE_BYTES_PER_DOF * fe_dofs},
         "cpu_baseline": cpu,
+        "batched_opinf_opinf": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(line), flush=True)
+
+
+def adjoint_timing(log):
+    """run_adjoint on the 24x24x240 bar (FOM 0-144, quadratic OpInf r=60 on 96-240 with seeded
+    synthetic operators of the learned sizes), 2000 steps, checkpoints every 100 steps, misfit
+    over every step, FP32; against the forward Schwarz run of the same context."""
+    import torch
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import CFG4, draw_pulses, synthetic_rom
+    w = CFG4
+    ctx = osam.Context(0, "f32", 1)
+    osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
+    z = ctx.sizes(1)
+    R = synthetic_rom(w.seed, z["n_free"], z["n_sch"], w.r, 10, w.dt, quadratic=True, with_c=True)
+    ctx.set_opinf(1, R["Phi"], R["PhiS"], R["A"], R["H"], R["B"], R["c"])
+    u0 = draw_pulses(w.seed, 1, s=w.pulse_width)[0].u0(w.bar)
+    n, K = w.steps, w.checkpoint
+    gen = torch.Generator(device="cuda:0").manual_seed(w.seed)
+    obs = {0: 1e-5 * torch.randn((n, ctx.sizes(0)["n_free"]), generator=gen, device="cuda:0"),
+           1: 1e-5 * torch.randn((n, w.r), generator=gen, device="cuda:0")}
+    ctx.set_initial(0, u0, np.zeros_like(u0))
+    ctx.run_adjoint(50, 25, 1, {0: obs[0][:50], 1: obs[1][:50]})      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, _ = ctx.run_adjoint(n, K, 1, obs)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    ctx.set_initial(0, u0, np.zeros_like(u0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run(n)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    log(f"adjoint {n} steps: {t_adj:.3f} s, forward {t_fwd:.3f} s, J={J:.6e}")
+    return dict(workload=w.name, steps=n, checkpoint_every=K, precision="f32", adjoint_s=t_adj,
+                forward_s=t_fwd, adjoint_over_forward=t_adj / t_fwd, J=J,
+                operators="seeded synthetic, learned sizes (r=60 quadratic, r_S=10)")
 
 
 def cpu_baseline(w, pulse, n_steps, learned):

@@ -5,7 +5,7 @@ Used under rocprofv3 to produce the summaries in profiles/:
     python -m paper_2511_20687_amd.profiling workload [steps]   # coupled run, synthetic r=40 OpInf
     python -m paper_2511_20687_amd.profiling large [steps [block kc]]  # 64x64x640, OpInf-FOM-OpInf, B=16
     python -m paper_2511_20687_amd.profiling copy               # plain copy of 256 MiB (calibration)
-    python -m paper_2511_20687_amd.profiling summarize OUTDIR   # counters -> profiles/*.txt
+    python -m paper_2511_20687_amd.profiling summarize OUTDIR [bar24|bar64]   # counters -> profiles/*.txt
 
 The workload runs exactly the FE kernel work of the bench (same subdomain, launch shape and
 coupling pattern); the OpInf operators are seeded synthetic ones of the learned sizes, so no
@@ -121,20 +121,31 @@ def _mean_counter(rows, name_part, counter):
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
 
 
-def summarize(outdir: str) -> None:
-    """outdir holds the rocprofv3 results of four passes: fetch_copy, write_copy, fetch_fe, write_fe."""
+CASES = {
+    # name: (subdirectory prefix, kernel name filter, FE DOFs per launch, summary file, title)
+    "bar24": ("", "fe_kernel<float, 0", 268125, "fe_kernel_bar24x24x240_traffic.txt",
+              "24x24x240 bar, Omega_1 268125 FE DOFs, FP32, launch 256 threads x 1 layer"),
+    "bar64": ("large_", "fe_kernel<float, 0", 16 * 4322175, "fe_kernel_bar64x64x640_b16_traffic.txt",
+              "64x64x640 bar, middle FOM subdomain 4322175 FE DOFs x 16 instances, FP32, launch 64 threads x 8 layers"),
+}
+
+
+def summarize(outdir: str, case: str = "bar24") -> None:
+    """outdir holds the rocprofv3 results of the passes fetch_copy, write_copy and
+    <prefix>fetch_fe, <prefix>write_fe of the case."""
+    prefix, kname, dofs, fname, title = CASES[case]
     get = lambda sub: _counter_rows(os.path.join(outdir, sub))
     fc, nfc = _mean_counter(get("fetch_copy"), "copy", "FETCH_SIZE")
     wc, nwc = _mean_counter(get("write_copy"), "copy", "WRITE_SIZE")
-    ff, nff = _mean_counter(get("fetch_fe"), "fe_kernel<float, 0", "FETCH_SIZE")
-    wf, nwf = _mean_counter(get("write_fe"), "fe_kernel<float, 0", "WRITE_SIZE")
+    ff, nff = _mean_counter(get(prefix + "fetch_fe"), kname, "FETCH_SIZE")
+    wf, nwf = _mean_counter(get(prefix + "write_fe"), kname, "WRITE_SIZE")
     kib = COPY_BYTES / 1024.0
     sf = kib / fc if fc else None
     sw = kib / wc if wc else None
     fetch_b = ff * sf * 1024 if (ff and sf) else None
     write_b = wf * sw * 1024 if (wf and sw) else None
     lines = [
-        "# FE step kernel HBM traffic (rocprofv3 --pmc), 24x24x240 bar, Omega_1 268125 FE DOFs, FP32",
+        f"# FE step kernel HBM traffic (rocprofv3 --pmc), {title}",
         f"kernel_source_sha256_16={fe_source_hash()}",
         f"copy_bytes={COPY_BYTES}",
         f"copy_fetch_kib_per_dispatch={fc} (n={nfc})",
@@ -146,10 +157,10 @@ def summarize(outdir: str) -> None:
         f"fe_fetch_bytes_per_launch={fetch_b}",
         f"fe_write_bytes_per_launch={write_b}",
         f"fe_traffic_bytes_per_launch={None if fetch_b is None or write_b is None else fetch_b + write_b}",
-        "algorithmic_bytes_per_launch=" + str(28 * 268125),
+        "algorithmic_bytes_per_launch=" + str(28 * dofs),
     ]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    path = os.path.join(ROOT, "profiles", "fe_kernel_bar24x24x240_traffic.txt")
+    path = os.path.join(ROOT, "profiles", fname)
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -184,6 +195,6 @@ if __name__ == "__main__":
     elif cmd == "copy":
         copy()
     elif cmd == "summarize":
-        summarize(sys.argv[2])
+        summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "bar24")
     else:
         raise SystemExit(f"unknown command {cmd}")
