@@ -314,14 +314,34 @@ int32_t osam_get_rom_path(osam_ctx *ctx, int32_t sd, int32_t *path);
  * or streams other than 1 and 2. */
 int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds, int32_t streams);
 
+/* Fused sweeps (enable = 1): each Schwarz sweep of Alg. 1 runs as one kernel
+ * launch in which every subdomain's step (FOM explicit step, or OpInf step of
+ * Eq. opinf_model_schwarz) takes its own range of workgroups, followed by the
+ * finisher kernel that takes the decision of Eq. conv_criterion (the batched
+ * OpInf parts of osam_set_rom_path 2 are launched before).  Within a sweep no
+ * step reads what another writes: sources push the displacement of the next
+ * step into buffers the sweep does not read, and an OpInf face fed by another
+ * OpInf subdomain forms the source's displacement at t_k (its explicit
+ * predictor) from the source's accepted state.  Results and iteration counts
+ * equal those of the sequential launches.  FOM steps run the column kernel
+ * with 512 threads per workgroup and kc (>= 1; 0 means 1) node layers per
+ * thread, whatever osam_set_fe_launch chose (that choice still serves the
+ * initial acceleration).  Combines with osam_set_graph (its streams setting is
+ * then unused).  At most 4 subdomains, 3 FOM and 2 OpInf: OSAM_E_INVALID here
+ * when the context already has more, and from run when a sweep does not fit
+ * (also when an OpInf step needs more than 64 KB of LDS).  enable = 0 (the
+ * default) returns to one launch per subdomain. */
+int32_t osam_set_fusion(osam_ctx *ctx, int32_t enable, int32_t kc);
+
 /* Launch-configuration autotuner.  Times trial runs of trial_steps controller
  * steps (after 2 warm-up steps) from the context's current state with `opts`,
  * and keeps, one coordinate at a time, the fastest: the FE launch shape of each
  * FOM subdomain (osam_set_fe_launch: 256/1, 128/1, 64/1, 64/2, 256/8, 64/8 and,
  * where it applies, the layer-staged 1024 with 4, 8, 16 layers), the OpInf
  * path of each OpInf subdomain of an FP32 context (osam_set_rom_path 1 or 2)
- * and the launch mode (osam_set_graph: none, 32 or 128 sweeps on one stream,
- * 32 on two).  None of these changes results.  The choice is cached for the
+ * the launch mode (osam_set_graph: none, 32 or 128 sweeps on one stream,
+ * 32 on two) and sweep fusion (osam_set_fusion with 1 or 4 layers per thread,
+ * host launches or graphs of 32 or 128 sweeps).  None of these changes results.  The choice is cached for the
  * process per configuration (precision, batch, subdomain and reduced sizes) and
  * applied without trials on a later call (from_cache = 1).  The trials advance
  * the state: set the initial condition again before the production run.
@@ -333,6 +353,7 @@ typedef struct {
   int32_t graph_rounds, graph_streams;
   double ms_per_step;              /* wall time per step of the chosen configuration's trial */
   int32_t from_cache;
+  int32_t fusion_kc;               /* fused sweeps with this many layers per FE thread, 0: off */
 } osam_tuning;
 int32_t osam_autotune(osam_ctx *ctx, int64_t trial_steps, const osam_schwarz_opts *opts, osam_tuning *out);
 

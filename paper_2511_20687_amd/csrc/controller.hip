@@ -18,6 +18,10 @@ template <typename T>
 hipError_t launch_rom(const RomArgs<T> &, int, hipStream_t, hipEvent_t = nullptr, hipEvent_t = nullptr);
 hipError_t launch_finish(const Status *, Status *, const FinishArgs &, const Opts &, int, hipStream_t);
 template <typename T>
+size_t rom_smem_bytes(int, int, int);
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T> &, int, bool, size_t, hipStream_t, hipEvent_t, hipEvent_t);
+template <typename T>
 hipError_t launch_project(const T *, long long, long long, const T *, long long, long long, double *, int,
                           int, hipStream_t);
 template <typename T>
@@ -522,7 +526,8 @@ int32_t Ctx::init_pending() {
 // What the decider of a sweep gathers: the FOM subdomains' partial sums and
 // the OpInf subdomains (other than the last) whose sums are in the output status.
 // defer: every OpInf kernel leaves its sums in the output status (graph mode)
-static FinishArgs finish_args(Ctx &c, bool defer = false) {
+// fused: the FOM partials come from the FE part of a fused sweep
+static FinishArgs finish_args(Ctx &c, bool defer = false, bool fused = false) {
   FinishArgs F;
   std::memset(&F, 0, sizeof(F));
   const int last = (int)c.sds.size() - 1;
@@ -533,7 +538,7 @@ static FinishArgs finish_args(Ctx &c, bool defer = false) {
       continue;
     }
     F.sd[F.nfom] = i;
-    F.nblocks[F.nfom] = d.fe_nblocks;
+    F.nblocks[F.nfom] = fused ? d.fz_nblocks : d.fe_nblocks;
     F.part[F.nfom] = d.partials;
     ++F.nfom;
   }
@@ -681,8 +686,13 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
       F.type = 3;
       F.src_r = src.r;
       F.tm = (const T *)s.face_tm[f];
-      F.src_q[0] = (T *)src.q[0];
-      F.src_q[1] = (T *)src.q[1];
+      for (int k = 0; k < 2; ++k) {
+        F.src_q[k] = (T *)src.q[k];
+        F.src_qd[k] = (const T *)src.qd[k];
+        F.src_qdd[k] = (const T *)src.qdd[k];
+      }
+      F.src_dt = (T)src.desc.dt;
+      F.src_half_dt2 = (T)(0.5 * src.desc.dt * src.desc.dt);
     } else {
       F.type = kFaceFom;
       for (int k = 0; k < 3; ++k) F.sface[k] = (const T *)s.sface[f][k];
@@ -843,6 +853,115 @@ int32_t Ctx::launch_round_concurrent(const Opts &o) {
   return OSAM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fused sweeps.  Every FOM step runs as the column kernel with 512-thread
+// workgroups (the OpInf step's workgroup size), fuse_kc layers per thread.
+void Ctx::fuse_layout(Subdomain &s) {
+  const int nl = s.nzs - 1, bs = 512;
+  s.fz_kc = std::max(1, std::min(fuse_kc, nl));
+  s.fz_chunks = (nl + s.fz_kc - 1) / s.fz_kc;
+  s.fz_int_blocks = (s.n_int + bs - 1) / bs;
+  s.fz_nblocks = (s.fz_int_blocks + (s.n_bnd + bs - 1) / bs) * s.fz_chunks;   // <= max_nblocks
+}
+
+std::string Ctx::fusion_unsupported() const {
+  int nfe = 0, nrom = 0;
+  for (const auto &d : sds) {
+    if (d->rom) {
+      ++nrom;
+      const size_t smem = prec == OSAM_FP64
+                              ? rom_smem_bytes<double>(d->r, d->rs, d->oh.quadratic ? d->r * (d->r + 1) / 2 : 0)
+                              : rom_smem_bytes<float>(d->r, d->rs,
+                                                      d->oh.quadratic && !d->pre ? d->r * (d->r + 1) / 2 : 0);
+      if (smem > 65536) return "an OpInf subdomain's step needs more than 64 KB of LDS";
+    } else {
+      ++nfe;
+    }
+  }
+  if ((int)sds.size() > kSweepMax || nfe > kSweepFe || nrom > kSweepRom)
+    return "a fused sweep takes at most 4 subdomains, 3 of them FOM and 2 OpInf";
+  return "";
+}
+
+template <typename T>
+static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1) {
+  SweepArgs<T> S;
+  std::memset(&S, 0, sizeof(S));
+  S.n = (int)c.sds.size();
+  int nfe = 0, nrom = 0;
+  bool one = true;
+  size_t smem = 0;
+  for (int i = 0; i < S.n; ++i) {
+    Subdomain &d = *c.sds[i];
+    if (!d.rom) {
+      FeArgs<T> &A = S.fe[nfe];
+      fill_fe_args<T>(c, d, i, o, A);
+      A.kc = d.fz_kc;
+      A.n_chunks = d.fz_chunks;
+      A.int_blocks = d.fz_int_blocks;
+      A.nblocks = d.fz_nblocks;
+      A.part_stride = d.fz_nblocks;
+      A.part_off = 0;
+      one = one && d.fz_kc == 1;
+      S.nblk[i] = d.fz_nblocks;
+      S.fe_idx[i] = nfe++;
+      S.rom_idx[i] = -1;
+    } else {
+      RomArgs<T> &A = S.rom[nrom];
+      fill_rom_args<T>(c, d, i, o, A);
+      A.defer = 1;
+      // an OpInf source runs side by side with this step: take its predictor
+      // from its accepted state (the value it writes in this sweep)
+      for (int f = 0; f < A.nfaces; ++f)
+        if (A.fin[f].type == 3) A.fin[f].pred = 1;
+      int rows = 0;
+      for (int e = 0; e < A.nexp; ++e) rows = std::max(rows, 3 * A.ex[e].npl);
+      S.nblk[i] = rows > 0 ? (rows + 511) / 512 : 1;
+      S.fe_idx[i] = -1;
+      S.rom_idx[i] = nrom++;
+      smem = std::max(smem, rom_smem_bytes<T>(A.r, A.rs, A.r2));
+    }
+  }
+  const hipError_t e = launch_sweep<T>(S, c.batch, one, smem, c.stream, ev0, ev1);
+  if (e != hipSuccess) return c.fail(OSAM_E_HIP, std::string("sweep kernel: ") + hipGetErrorString(e));
+  return OSAM_OK;
+}
+
+// One Schwarz sweep as one launch (after the batched OpInf parts), then the
+// finisher.  Sources push into the next step's roles and write their sums to
+// their own slots, so the subdomains' steps are independent within the sweep
+// (an OpInf source's displacement is formed from its accepted state).
+int32_t Ctx::launch_round_fused(const Opts &o) {
+  const std::string why = fusion_unsupported();
+  if (!why.empty()) return fail(OSAM_E_INVALID, why);
+  for (size_t i = 0; i < sds.size(); ++i) {
+    Subdomain &d = *sds[i];
+    if (!d.rom) {
+      fuse_layout(d);
+    } else if (d.pre) {
+      RomPreArgs P;
+      fill_pre_args(*this, d, (int)i, o, P);
+      const hipError_t e = launch_rom_pre(P, stream);
+      if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("batched OpInf kernels: ") + hipGetErrorString(e));
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timing) {   // every subdomain reports the fused launch
+    const int a = (int)ev_next;
+    e0 = next_event();
+    const int b = (int)ev_next;
+    e1 = next_event();
+    if (!e0 || !e1) return fail(OSAM_E_HIP, "event create");
+    for (size_t i = 0; i < sds.size(); ++i) ev_used.push_back({(int)i, {a, b}});
+  }
+  int32_t st = prec == OSAM_FP64 ? fused_sweep<double>(*this, o, e0, e1) : fused_sweep<float>(*this, o, e0, e1);
+  if (st) return st;
+  const hipError_t e = launch_finish(d_status, d_status_alt, finish_args(*this, true, true), o, batch, stream);
+  if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("finish kernel: ") + hipGetErrorString(e));
+  std::swap(d_status, d_status_alt);
+  return OSAM_OK;
+}
+
 int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_info *info) {
   if (!(op.tol_abs >= 0) || !(op.tol_rel >= 0) || op.min_iter < 1 || op.max_iter < op.min_iter ||
       op.max_iter > 1000000 || (op.guess != OSAM_GUESS_HOLD && op.guess != OSAM_GUESS_PREDICTOR))
@@ -891,7 +1010,8 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
     }
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    for (int r = 0; r < graph_rounds && !st; ++r) st = graph_streams == 2 ? launch_round_concurrent(o) : launch_round(o);
+    for (int r = 0; r < graph_rounds && !st; ++r)
+      st = fuse ? launch_round_fused(o) : (graph_streams == 2 ? launch_round_concurrent(o) : launch_round(o));
     const hipError_t ec = hipStreamEndCapture(stream, &g);
     if (st) {
       if (g) (void)hipGraphDestroy(g);
@@ -922,7 +1042,7 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
       if (graph) {
         const hipError_t e = hipGraphLaunch(gexec, stream);
         if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("graph launch: ") + hipGetErrorString(e));
-      } else if ((st = launch_round(o))) {
+      } else if ((st = fuse ? launch_round_fused(o) : launch_round(o))) {
         return st;
       }
     }

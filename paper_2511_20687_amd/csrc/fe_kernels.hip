@@ -36,286 +36,13 @@
 //    instance advances at its own pace and the host never waits per step.
 #include <hip/hip_ext.h>
 
-#include "osam_device.hpp"
-#include "stencil.hpp"
+#include "fe_body.hpp"
 
 namespace osam {
 
-constexpr int kModeStep = 0;
-constexpr int kModeInit = 1;
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
-// Per-thread view of one instance's buffers in the roles of its current step.
-template <typename T>
-struct Roles {
-  T *U0, *P, *P2, *V0, *V1, *A0, *A1;
-  const T *Pin, *Flo, *Fhi;
-  int rP, rP2;
-};
-
-template <typename T, int MODE>
-__device__ __forceinline__ Roles<T> roles(const FeArgs<T> &A, int b, long long step, int n_iter) {
-  Roles<T> R;
-  const long long boff = (long long)b * A.is;
-  const int s3 = (int)(step % 3), s2 = (int)(step % 2);
-  // U0 = u[s%3], P = u[(s+1)%3], P2 = u[(s+2)%3]; V0 = v[s%2], V1 = v[(s+1)%2]
-  R.rP = (s3 + 1) % 3;
-  R.rP2 = (s3 + 2) % 3;
-  R.U0 = A.u[s3] + boff;
-  R.P = A.u[R.rP] + boff;
-  R.P2 = A.u[R.rP2] + boff;
-  R.V0 = A.v[s2] + boff;
-  R.V1 = A.v[1 - s2] + boff;
-  R.A0 = A.a[s2] + boff;
-  R.A1 = A.a[1 - s2] + boff;
-  // Face layers: HOLD at iteration 1 when the source comes later in the sweep
-  // reads the neighbour's value at t_{k-1} (role U0), otherwise at t_k (role P).
-  R.Pin = (MODE == kModeInit) ? R.U0 : R.P;
-  R.Flo = R.Pin;
-  R.Fhi = R.Pin;
-  if (MODE == kModeStep && n_iter == 1 && A.opts.guess == 0) {
-    if (A.face_src[0] > A.sd) R.Flo = R.U0;
-    if (A.face_src[1] > A.sd) R.Fhi = R.U0;
-  }
-  return R;
-}
-
-template <typename T>
-__device__ __forceinline__ Strides strides(const FeArgs<T> &A) {
-  return Strides{(unsigned)(A.cs * (long long)sizeof(T)), (unsigned)A.npl * (unsigned)sizeof(T),
-                 (unsigned)(A.nx + 1) * (unsigned)sizeof(T)};
-}
-
-// Newmark update of node (layer k, column nid0) from its acceleration, with
-// the convergence sums, records and pushes.
-template <typename T, int MODE>
-__device__ __forceinline__ void update_node(const FeArgs<T> &A, const Roles<T> &R, int b, int k, int nid0,
-                                            const T (&ctr)[3], const T (&acc)[3], const T (&v0)[3],
-                                            const T (&a0)[3], const T (&old)[3], int n_iter, bool rec,
-                                            long long rbase, double &acc_abs, double &acc_den) {
-  const Strides B = strides(A);
-  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T);
-  T out[3];   // value pushed to neighbours: the displacement at the next step
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const T a1 = acc[c];
-    const unsigned so = (unsigned)k * B.npl + c * B.cs;   // wave-uniform part of the offset
-    if (MODE == kModeInit) {
-      Field<T>(R.A0).st(a1, vo, so);
-      out[c] = ctr[c] + A.dt * v0[c] + A.half_dt2 * a1;
-      Field<T>(R.P).st(out[c], vo, so);
-    } else {
-      const T p = ctr[c];
-      const T v1 = v0[c] + A.half_dt * (a0[c] + a1);
-      double dlt;
-      if (n_iter >= 2)
-        dlt = (double)A.dt * ((double)v1 - (double)old[c]);   // old = previous iterate's V1
-      else   // iterate 0 = state at t_{k-1} (only tested when min_iter = 1); old = U0
-        dlt = ((double)p - (double)old[c]) + (double)A.dt * ((double)v1 - (double)v0[c]);
-      acc_abs += dlt * dlt;
-      const double den = (double)p + (double)A.dt * (double)v1;
-      acc_den += den * den;
-      Field<T>(R.V1).st(v1, vo, so);
-      Field<T>(R.A1).st(a1, vo, so);
-      out[c] = p + A.dt * v1 + A.half_dt2 * a1;
-      Field<T>(R.P2).st(out[c], vo, so);
-    }
-    if (rec) {
-      const long long ro = rbase + (long long)c * A.nfree_nodes + (long long)(k - 1) * A.npl + nid0;
-      if (A.rec_u) A.rec_u[ro] = ctr[c];
-      if (A.rec_a) A.rec_a[ro] = a1;
-    }
-  }
-  // push to the faces fed by this layer (next-step role: P2, or P when initialising)
-  for (int e = 0; e < A.npush; ++e) {
-    const PushDev<T> &Pd = A.push[e];
-    if (Pd.layer != k) continue;
-    T *dst = Pd.role[MODE == kModeInit ? R.rP : R.rP2] + (long long)b * Pd.is + nid0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) dst[c * Pd.cs] = out[c];
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void record_face(const FeArgs<T> &A, int b, int f, int nid0, const T (&w)[9][3],
-                                            long long rcol) {
-  const long long so = ((long long)b * A.rec_ncols + rcol) * 3 * A.nsch_nodes + (f ? A.face_off_hi : 0);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) A.rec_s[so + (long long)c * A.nsch_nodes + nid0] = w[4][c];
-}
-
-// v0, a0 and the previous iterate (V1, or U0 at the first iteration) of one node.
-template <typename T, int MODE>
-__device__ __forceinline__ void state_loads(const Roles<T> &R, const Strides &B, int k, int nid0, int n_iter,
-                                            T (&v0)[3], T (&a0)[3], T (&old)[3]) {
-  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T);
-  const Field<T> FV(R.V0), FA(R.A0), FO(n_iter >= 2 ? R.V1 : R.U0);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const unsigned so = (unsigned)k * B.npl + c * B.cs;
-    v0[c] = FV.ld(vo, so);
-    a0[c] = MODE == kModeInit ? T(0) : FA.ld(vo, so);
-    old[c] = MODE == kModeInit ? T(0) : FO.ld(vo, so);
-  }
-}
-
-// One layer's 3x3 neighbourhood: interior columns through wave-uniform row bases,
-// boundary columns (clamped indices) through per-lane addresses.
-template <typename T, bool INTERIOR>
-__device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B, long long cs, int L, int npl,
-                                      int nxp, int ix, int iy, int nx, int ny, int nid0) {
-  if (INTERIOR) load_layer_uniform<T>(w, P, B, L, (unsigned)(nid0 - nxp - 1) * (unsigned)sizeof(T));
-  else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
-}
-
-// Column (ix, iy), layers k0 .. k1-1 (ONE: the single layer k0, every load issued at once).
-template <typename T, int MODE, bool INTERIOR, bool ONE>
-__device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int chunk, long long step,
-                                           int iter, double &acc_abs, double &acc_den) {
-  const int nx = A.nx, ny = A.ny, nxp = nx + 1, npl = A.npl, nzs = A.nzs;
-  const long long cs = A.cs;
-  const int n_iter = iter + 1;
-  int ix, iy, cse;
-  if (INTERIOR) {
-    if (t >= A.n_int) return;
-    ix = 1 + t % (nx - 1);
-    iy = 1 + t / (nx - 1);
-    cse = 4;
-  } else {
-    if (t >= A.n_bnd) return;
-    const int col = A.bnd_cols[t];
-    if (col < 0) return;   // padding of a case group
-    ix = col % nxp;
-    iy = col / nxp;
-    // every wave holds one case group: make the case (and the coefficient block) wave-uniform
-    cse = __builtin_amdgcn_readfirstlane((ix == 0 ? 0 : (ix == nx ? 2 : 1)) + 3 * (iy == 0 ? 0 : (iy == ny ? 2 : 1)));
-  }
-  const T *C = A.coef + cse * 234;
-  const Roles<T> R = roles<T, MODE>(A, b, step, n_iter);
-  const int k0 = 1 + chunk * A.kc;
-  const int k1 = ONE ? k0 + 1 : min(k0 + A.kc, nzs);
-  const int nid0 = ix + nxp * iy;
-  const Strides B = strides(A);
-
-  // records (the division only when recording is on)
-  long long rcol = 0, rbase = 0;
-  bool rec = false;
-  if (A.rec_every > 0) {
-    rcol = (MODE == kModeInit) ? 0 : (step + 1) / A.rec_every;
-    rec = rcol < A.rec_ncols && (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
-    rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
-  }
-
-  if (ONE) {
-    const int k = k0;
-    T w0[9][3], w1[9][3], w2[9][3], v0[3], a0[3], old[3], acc[3], ctr[3];
-    layer<T, INTERIOR>(w0, k == 1 ? R.Flo : R.Pin, B, cs, k - 1, npl, nxp, ix, iy, nx, ny, nid0);
-    layer<T, INTERIOR>(w1, R.Pin, B, cs, k, npl, nxp, ix, iy, nx, ny, nid0);
-    layer<T, INTERIOR>(w2, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
-    state_loads<T, MODE>(R, B, k, nid0, n_iter, v0, a0, old);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      ctr[c] = w1[4][c];
-      acc[c] = T(0);
-    }
-    slab<T, INTERIOR, -1>(A.cb, C, w0, ctr, acc);
-    slab<T, INTERIOR, 0>(A.cb, C, w1, ctr, acc);
-    slab<T, INTERIOR, 1>(A.cb, C, w2, ctr, acc);
-    update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
-    if (rec && A.rec_s) {
-      if (k == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, w0, rcol);
-      if (k == nzs - 1 && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, w2, rcol);
-    }
-    return;
-  }
-
-  // rolling window: cur = layer k, nxt = layer k+1; acc holds the partial force
-  // of layer k from layers k-1 and k until layer k+1 arrives.
-  T cur[9][3], nxt[9][3], acc[3], ctr[3];
-  layer<T, INTERIOR>(nxt, k0 == 1 ? R.Flo : R.Pin, B, cs, k0 - 1, npl, nxp, ix, iy, nx, ny, nid0);
-  layer<T, INTERIOR>(cur, R.Pin, B, cs, k0, npl, nxp, ix, iy, nx, ny, nid0);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    ctr[c] = cur[4][c];
-    acc[c] = T(0);
-  }
-  slab<T, INTERIOR, -1>(A.cb, C, nxt, ctr, acc);
-  slab<T, INTERIOR, 0>(A.cb, C, cur, ctr, acc);
-  if (rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, nxt, rcol);
-
-  for (int k = k0; k < k1; ++k) {
-    T v0[3], a0[3], old[3];
-    state_loads<T, MODE>(R, B, k, nid0, n_iter, v0, a0, old);
-    layer<T, INTERIOR>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
-    slab<T, INTERIOR, 1>(A.cb, C, nxt, ctr, acc);
-    update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
-    if (k + 1 < k1) {
-      // start layer k+1: contributions of layers k (dz = -1) and k+1 (dz = 0)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        ctr[c] = nxt[4][c];
-        acc[c] = T(0);
-      }
-      slab<T, INTERIOR, -1>(A.cb, C, cur, ctr, acc);
-      slab<T, INTERIOR, 0>(A.cb, C, nxt, ctr, acc);
-#pragma unroll
-      for (int n = 0; n < 9; ++n)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) cur[n][c] = nxt[n][c];
-    }
-  }
-  if (rec && A.rec_s && k1 == nzs && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, nxt, rcol);
-}
-
 template <typename T, int MODE, bool ONE>
 __global__ void __launch_bounds__(256) fe_kernel(FeArgs<T> A) {
-  const int b = blockIdx.y;
-  const Status *stp = A.status + b;
-  const int flags = stp->flags;
-  if (MODE == kModeStep && (flags & kFinished)) return;
-  if (MODE == kModeInit && !(flags & kNeedInit)) return;
-  const long long step = stp->step;
-  const int iter = stp->iter;
-
-  double acc_abs = 0.0, acc_den = 0.0;
-  const int bx = xcd_block(blockIdx.x, A.nblocks);
-  if (bx < A.int_blocks * A.n_chunks) {
-    const int t = (bx % A.int_blocks) * blockDim.x + threadIdx.x;
-    fe_columns<T, MODE, true, ONE>(A, b, t, bx / A.int_blocks, step, iter, acc_abs, acc_den);
-  } else {
-    const int bb = bx - A.int_blocks * A.n_chunks;
-    const int nbb = A.nblocks / A.n_chunks - A.int_blocks;
-    const int t = (bb % nbb) * blockDim.x + threadIdx.x;
-    fe_columns<T, MODE, false, ONE>(A, b, t, bb / nbb, step, iter, acc_abs, acc_den);
-  }
-  if (MODE == kModeInit) return;
-
-  // fixed-order workgroup reduction of the two FP64 sums; the sweep's finisher
-  // adds the workgroups' partials (no fences or atomics here)
-  __shared__ double red[2][16];
-  acc_abs = wave_sum(acc_abs);
-  acc_den = wave_sum(acc_den);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) {
-    red[0][wid] = acc_abs;
-    red[1][wid] = acc_den;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sa = 0.0, sd = 0.0;
-    for (int i = 0; i < nw; ++i) {
-      sa += red[0][i];
-      sd += red[1][i];
-    }
-    double *pp = A.partials + ((long long)b * A.part_stride + A.part_off + bx) * 2;
-    pp[0] = sa;
-    pp[1] = sd;
-  }
+  fe_body<T, MODE, ONE>(A, blockIdx.x);
 }
 
 // Layer-staged variant for the interior columns (FP32, cross-sections up to

@@ -215,7 +215,20 @@ struct RomFaceIn {
   const T *phis;           // [rs][n] column-major block of Phi_S for this face
   const T *tm;             // [rs][src_r] row-major: Phi_S,face^T Pi Phi_src (ROM source)
   T *src_q[2];             // source reduced displacement buffers [batch][src_r]
+  // ROM source: its displacement at t_k is its explicit predictor, formed from
+  // its accepted state at t_{k-1} (src_qd, src_qdd) where it is not read back
+  // from what the source wrote in this sweep; pred = 1 always (fused sweeps)
+  int pred;
+  T src_dt, src_half_dt2;
+  const T *src_qd[2], *src_qdd[2];
 };
+
+// Explicit Newmark predictor q + dt q' + dt^2/2 q'' in one fixed rounding order,
+// shared by an OpInf step and the faces that read its displacement.
+template <typename T>
+__device__ __forceinline__ T newmark_pred(T q, T qd, T qdd, T dt, T half_dt2) {
+  return fma(half_dt2, qdd, fma(dt, qd, q));
+}
 
 template <typename T>
 struct RomExport {
@@ -279,5 +292,18 @@ struct RomPreArgs {
 };
 
 hipError_t launch_rom_pre(const RomPreArgs &P, hipStream_t s);
+
+// One Schwarz sweep in a single launch: subdomain i of the sweep owns the next
+// nblk[i] workgroups of the grid (x), instances along y; fe_idx / rom_idx pick
+// its arguments (rom_idx < 0: a FOM step).  Kernel arguments stay below 4 KB.
+constexpr int kSweepMax = 4, kSweepFe = 3, kSweepRom = 2;
+template <typename T>
+struct SweepArgs {
+  int n;
+  int nblk[kSweepMax], fe_idx[kSweepMax], rom_idx[kSweepMax];
+  FeArgs<T> fe[kSweepFe];
+  RomArgs<T> rom[kSweepRom];
+};
+static_assert(sizeof(SweepArgs<double>) <= 4096, "sweep kernel arguments exceed 4 KB");
 
 }  // namespace osam

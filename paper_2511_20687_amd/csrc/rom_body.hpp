@@ -1,0 +1,340 @@
+// Device code of the OpInf step kernel (see rom_kernels.hip), shared by the step
+// kernel and the fused sweep kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "osam_device.hpp"
+
+namespace osam {
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+constexpr int kRomThreads = 512;
+constexpr int kRomWaves = kRomThreads / 64;   // 8
+constexpr int kRowsPerWave = 16;              // rows i = wave + 8 j: r <= 128
+constexpr int kFaceDofs = 4;                  // face DOFs per thread on the fast g^ path
+constexpr int kPushK = 64;                    // modes of the push row held in registers
+
+// Sum of NV per-thread values over the workgroup in a fixed order; the totals
+// land in out[0..NV) (LDS) for every thread after the call.
+template <int NV, typename T>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double (*red)[kRomWaves], T *out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_d(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wid] = v[k];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    double t = 0.0;
+    for (int w = 0; w < kRomWaves; ++w) t += red[threadIdx.x][w];
+    out[threadIdx.x] = (T)t;
+  }
+  __syncthreads();
+}
+
+// Grid (G, batch): the G workgroups of an instance each take one slice of the
+// push rows and recompute the (small) reduced step redundantly, so the push
+// streams through G CUs instead of one; workgroup 0 alone stores the state and
+// the sums and, when this subdomain ends the sweep, decides.  Every load that
+// does not depend on this step's results is issued first, in one straight-line
+// batch (indices clamped into range, values zeroed afterwards), speculatively
+// for both state parities and all three face roles.
+template <typename T>
+__device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
+  const int b = blockIdx.y;
+  const Status *stp = A.status + b;
+  const int r = A.r, rs = A.rs, r2 = A.r2;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const long long qo = (long long)b * r;
+  const bool last = !A.defer && A.sd == A.opts.nsd - 1;
+  const FinishArgs &F = A.finish;
+
+  extern __shared__ unsigned char smem_raw[];
+  T *q1s = reinterpret_cast<T *>(smem_raw);   // q(t_k): Newmark predictor of the accepted state
+  T *qps = q1s + r;                            // q(t_k+1) predictor, input of the pushes
+  T *qdd1s = qps + r;                          // row sums of q''(t_k)
+  T *sh = qdd1s + r;                           // g^ (max(rs, 1))
+  T *k2 = sh + (rs > 0 ? rs : 1);              // q (x) q, compressed (r2)
+  __shared__ double red[12][kRomWaves];
+  __shared__ double tot[12];
+  __shared__ double nsum[2];
+
+  // ---- 1. loads independent of this step's results
+  const int flags = stp->flags;
+  const long long step = stp->step;
+  const int iter = stp->iter;
+  const int tq = min(tid, r - 1);
+  T xq[2], xqd[2], xqdd[2], x_c = T(0);
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    xq[p] = A.q[p][qo + tq];
+    xqd[p] = A.qd[p][qo + tq];
+    xqdd[p] = A.qdd[p][qo + tq];
+  }
+  if (A.c) x_c = A.c[tq];
+  // batched path: this row's f0 and this thread's mode of g^ (partial sums, fixed order)
+  T x_f0 = T(0);
+  double x_g = 0.0;
+  if (A.f0part)
+    for (int k = 0; k < A.f0_ks; ++k) x_f0 += A.f0part[k * A.f0_stride + qo + tq];
+  if (A.gpart && rs > 0) {
+    const int tg = min(tid, rs - 1);
+    for (int k = 0; k < A.g_gs; ++k) x_g += A.gpart[k * A.g_stride + (long long)b * rs + tg];
+  }
+  T arow[kRowsPerWave][2], brow[kRowsPerWave];
+  const int l0 = min(lane, r - 1), l1 = min(lane + 64, r - 1), lb = min(lane, rs > 0 ? rs - 1 : 0);
+#pragma unroll
+  for (int j = 0; j < kRowsPerWave; ++j) {
+    const int i = wid + kRomWaves * j;
+    arow[j][0] = arow[j][1] = brow[j] = T(0);
+    if (i < r) {   // wave-uniform
+      if (A.A) {
+        arow[j][0] = A.A[(long long)i * r + l0];
+        if (r > 64) arow[j][1] = A.A[(long long)i * r + l1];
+      }
+      if (A.B) brow[j] = A.B[(long long)i * rs + lb];
+    }
+  }
+  // first face when fed by a FOM: values of all three roles and up to 8 modes
+  const bool small_face = A.nfaces > 0 && A.fin[0].type == kFaceFom &&
+                          A.fin[0].n <= kFaceDofs * kRomThreads && rs <= 8;
+  T fv[3][kFaceDofs], fph[kFaceDofs][8];
+  if (small_face) {
+    const RomFaceIn<T> &f = A.fin[0];
+#pragma unroll
+    for (int d = 0; d < kFaceDofs; ++d) {
+      const long long m = min(tid + kRomThreads * d, f.n - 1);
+#pragma unroll
+      for (int ro = 0; ro < 3; ++ro) fv[ro][d] = f.sface[ro][(long long)b * f.n + m];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) fph[d][kk] = kk < rs ? f.phis[(long long)kk * f.n + m] : T(0);
+    }
+  }
+  // this thread's push row (export 0): (Pi Phi)[m, 0..r)
+  const bool reg_push = A.nexp > 0;
+  T pv[kPushK];
+  if (reg_push) {
+    const RomExport<T> &ex = A.ex[0];
+    const int n = 3 * ex.npl;
+    const long long m = min(g * kRomThreads + tid, n - 1);
+#pragma unroll
+    for (int k = 0; k < kPushK; ++k) pv[k] = k < r ? ex.piphi[(long long)k * n + m] : T(0);
+  }
+  // the FOM workgroups' partial sums, when this workgroup decides
+  bool small_part = last && g == 0 && F.nfom <= 2;
+  for (int k = 0; k < F.nfom; ++k) small_part = small_part && F.nblocks[k] <= kFaceDofs * kRomThreads;
+  double2 pa[2][kFaceDofs];
+  if (small_part && F.nfom > 0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int kk = min(k, F.nfom - 1);
+      const double2 *pp = reinterpret_cast<const double2 *>(F.part[kk]) + (long long)b * F.nblocks[kk];
+#pragma unroll
+      for (int d = 0; d < kFaceDofs; ++d) pa[k][d] = pp[min(tid + kRomThreads * d, F.nblocks[kk] - 1)];
+    }
+  }
+  if (flags & kFinished) {
+    if (last && g == 0 && wid == 0) finish_sweep(A.status, A.status_out, F, A.opts, b);   // carries the status over
+    return;
+  }
+  const int n_iter = iter + 1;
+  const int s2 = (int)(step % 2);
+  const T x_q0 = xq[s2], x_qd0 = xqd[s2], x_qdd0 = xqdd[s2];
+  const T x_old_q = n_iter >= 2 ? xq[1 - s2] : x_q0;
+  const T x_old_v = n_iter >= 2 ? xqd[1 - s2] : x_qd0;
+#pragma unroll
+  for (int j = 0; j < kRowsPerWave; ++j) {
+    if (lane >= r) arow[j][0] = T(0);
+    if (lane + 64 >= r) arow[j][1] = T(0);
+    if (lane >= rs) brow[j] = T(0);
+  }
+
+  // ---- 2. predictor q(t_k) = q + dt q' + dt^2/2 q''
+  if (tid < r) {
+    q1s[tid] = newmark_pred<T>(x_q0, x_qd0, x_qdd0, A.dt, A.half_dt2);
+    qdd1s[tid] = x_f0;   // rows add A q + H (q (x) q) + B g^ below
+  }
+  for (int k = tid; k < rs; k += kRomThreads) sh[k] = k == tid ? (T)x_g : T(0);
+
+  // ---- 3. reduced boundary input g^ (and the FOM partial sums, same reduction)
+  {
+    double part[12];
+#pragma unroll
+    for (int kk = 0; kk < 12; ++kk) part[kk] = 0.0;
+    if (small_face) {
+      const RomFaceIn<T> &f = A.fin[0];
+      const bool hold = n_iter == 1 && f.src_sd > A.sd && A.opts.guess == 0;
+      const int ro = hold ? (int)(step % 3) : (int)((step + 1) % 3);
+#pragma unroll
+      for (int d = 0; d < kFaceDofs; ++d) {
+        const bool ok = tid + kRomThreads * d < f.n;
+        const T sv = ok ? (ro == 0 ? fv[0][d] : (ro == 1 ? fv[1][d] : fv[2][d])) : T(0);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+          if (kk < rs) part[kk] += (double)(fph[d][kk] * sv);
+      }
+    }
+    if (small_part) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int d = 0; d < kFaceDofs; ++d)
+          if (k < F.nfom && tid + kRomThreads * d < F.nblocks[k]) {
+            part[8 + 2 * k] += pa[k][d].x;
+            part[9 + 2 * k] += pa[k][d].y;
+          }
+    }
+    block_reduce<12>(part, red, tot);
+    if (small_face && tid < rs) sh[tid] = (T)tot[tid];
+  }
+  for (int fi = small_face ? 1 : 0; fi < A.nfaces; ++fi) {
+    const RomFaceIn<T> &f = A.fin[fi];
+    const bool hold = n_iter == 1 && f.src_sd > A.sd && A.opts.guess == 0;
+    if (f.type == kFaceFom) {
+      // g^_k += sum_m Phi_S[m, k] s_m : threads over the face DOFs, 8 modes per pass
+      const T *src = f.sface[hold ? (int)(step % 3) : (int)((step + 1) % 3)] + (long long)b * f.n;
+      for (int k0 = 0; k0 < rs; k0 += 8) {
+        double part[8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) part[kk] = 0.0;
+        for (int m0 = 0; m0 < f.n; m0 += 2 * kRomThreads) {
+          T sv[2], ph[2][8];
+#pragma unroll
+          for (int d = 0; d < 2; ++d) {
+            const long long m = min(m0 + tid + kRomThreads * d, f.n - 1);
+            sv[d] = m0 + tid + kRomThreads * d < f.n ? src[m] : T(0);
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) ph[d][kk] = f.phis[(long long)min(k0 + kk, rs - 1) * f.n + m];
+          }
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+              if (k0 + kk < rs) part[kk] += (double)(ph[d][kk] * sv[d]);
+        }
+        block_reduce<8>(part, red, tot + 0);
+        if (tid < 8 && k0 + tid < rs) sh[k0 + tid] += (T)tot[tid];
+        __syncthreads();
+      }
+    } else {
+      // ROM source: g^ += (Phi_S,face^T Pi Phi_src) q_src, one wave per mode
+      const long long so = (long long)b * f.src_r;
+      // the source's predictor at t_k when it is not read back from this sweep:
+      // fused sweeps, and the first sweep of a step before the source has run
+      // (PREDICTOR guess with the source later in the sweep)
+      const bool pred = !hold && (f.pred || (n_iter == 1 && f.src_sd > A.sd));
+      const T *qs = f.src_q[hold || pred ? s2 : 1 - s2] + so;
+      for (int k = wid; k < rs; k += kRomWaves) {
+        double v = 0.0;
+        for (int j = lane; j < f.src_r; j += 64) {
+          const T x = pred ? newmark_pred<T>(qs[j], f.src_qd[s2][so + j], f.src_qdd[s2][so + j], f.src_dt,
+                                             f.src_half_dt2)
+                           : qs[j];
+          v += (double)(f.tm[(long long)k * f.src_r + j] * x);
+        }
+        v = wave_sum_d(v);
+        if (lane == 0) sh[k] += (T)v;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+
+  // ---- 4. compressed quadratic vector q_i q_j (i <= j), row by row
+  if (r2 > 0) {
+    for (int idx = tid; idx < r * r; idx += kRomThreads) {
+      const int i = idx / r, j = idx - i * r;
+      if (j >= i) k2[i * r - (i * (i - 1)) / 2 + (j - i)] = q1s[i] * q1s[j];
+    }
+    __syncthreads();
+  }
+
+  // ---- 5. q''(t_k) rows: A q + H k2 + B g^ (+ c below), one wave per row
+#pragma unroll
+  for (int j = 0; j < kRowsPerWave; ++j) {
+    const int i = wid + kRomWaves * j;
+    if (i >= r) break;
+    T s = arow[j][0] * (lane < r ? q1s[lane] : T(0)) + arow[j][1] * (lane + 64 < r ? q1s[lane + 64] : T(0));
+    if (r2 > 0) {
+      const T *Hr = A.H + (long long)i * r2;
+#pragma unroll 4
+      for (int m = lane; m < r2; m += 64) s += Hr[m] * k2[m];
+    }
+    if (lane < rs) s += brow[j] * sh[lane];
+    for (int l = 64 + lane; l < rs; l += 64) s += A.B[(long long)i * rs + l] * sh[l];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) qdd1s[i] += s;
+  }
+  __syncthreads();
+
+  // ---- 6. velocity, convergence sums, next predictor; workgroup 0 stores the state
+  double nrm[2] = {0.0, 0.0};
+  if (tid < r) {
+    const T qn = q1s[tid], an = qdd1s[tid] + x_c;
+    const T vn = x_qd0 + A.half_dt * (x_qdd0 + an);
+    qps[tid] = qn + A.dt * vn + A.half_dt2 * an;
+    if (g == 0) {
+      const double d = ((double)qn - (double)x_old_q) + (double)A.dt * ((double)vn - (double)x_old_v);
+      nrm[0] = d * d;
+      const double e = (double)qn + (double)A.dt * (double)vn;
+      nrm[1] = e * e;
+      A.q[1 - s2][qo + tid] = qn;
+      A.qd[1 - s2][qo + tid] = vn;
+      A.qdd[1 - s2][qo + tid] = an;
+      if (A.rec_q && A.rec_every > 0 && ((step + 1) % A.rec_every) == 0) {
+        const long long col = (step + 1) / A.rec_every;
+        if (col < A.rec_ncols) A.rec_q[((long long)b * A.rec_ncols + col) * r + tid] = qn;
+      }
+    }
+  }
+  block_reduce<2>(nrm, red, nsum);   // also publishes qps to every thread
+
+  // ---- 7. push (Pi Phi) q(t_k+1) into the FOM neighbours' faces (role of step k+1)
+  const int role = (int)((step + 2) % 3);
+  for (int e = 0; e < A.nexp; ++e) {
+    const RomExport<T> &ex = A.ex[e];
+    const int n = 3 * ex.npl;
+    const int m = g * kRomThreads + tid;
+    T acc0 = T(0), acc1 = T(0);
+    if (e == 0) {
+#pragma unroll
+      for (int k = 0; k < kPushK; k += 2) {
+        if (k < r) acc0 += pv[k] * qps[k];
+        if (k + 1 < r) acc1 += pv[k + 1] * qps[k + 1];
+      }
+    }
+    for (int k0 = e == 0 ? kPushK : 0; k0 < r; k0 += 16) {
+      T pw[16];
+      const long long mm = min(m, n - 1);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) pw[u] = ex.piphi[(long long)min(k0 + u, r - 1) * n + mm];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (k0 + u < r) acc0 += pw[u] * qps[k0 + u];
+    }
+    if (m < n) {
+      const int c = m / ex.npl, nid = m - c * ex.npl;
+      ex.role[role][(long long)b * ex.is + c * ex.cs + nid] = acc0 + acc1;
+    }
+  }
+
+  // ---- 8. sums of this subdomain; the last subdomain of the sweep decides
+  if (g != 0) return;
+  if (last) {
+    if (wid == 0)
+      finish_sweep(A.status, A.status_out, F, A.opts, b, A.sd, nsum[0], nsum[1], small_part ? tot + 8 : nullptr);
+  } else if (tid == 0) {
+    A.status_out[b].sd_abs2[A.sd] = nsum[0];
+    A.status_out[b].sd_den2[A.sd] = nsum[1];
+  }
+}
+
+}  // namespace osam

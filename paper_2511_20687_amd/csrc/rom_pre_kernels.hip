@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kPreThreads) rom_f0_kernel(RomPreArgs P) {
     const int b = min(it * 16 + bl, P.batch - 1);
     const int s2 = (int)(P.status[b].step % 2);
     const long long o = (long long)b * r + k;
-    q1s[e] = P.q[s2][o] + P.dt * P.qd[s2][o] + P.half_dt2 * P.qdd[s2][o];
+    q1s[e] = newmark_pred<float>(P.q[s2][o], P.qd[s2][o], P.qdd[s2][o], P.dt, P.half_dt2);
   }
   __syncthreads();
 

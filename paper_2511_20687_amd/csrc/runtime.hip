@@ -616,6 +616,23 @@ int32_t osam_set_graph(osam_ctx *c, int32_t rounds, int32_t streams) {
   return OSAM_OK;
 }
 
+int32_t osam_set_fusion(osam_ctx *c, int32_t enable, int32_t kc) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  ctx->err.clear();
+  if (kc < 0 || kc > 4096) return ctx->fail(OSAM_E_INVALID, "kc must be in 0 .. 4096");
+  if (enable) {
+    int nfe = 0, nrom = 0;
+    for (const auto &d : ctx->sds) (d->rom ? nrom : nfe)++;
+    if ((int)ctx->sds.size() > kSweepMax || nfe > kSweepFe || nrom > kSweepRom)
+      return ctx->fail(OSAM_E_INVALID, "a fused sweep takes at most 4 subdomains, 3 of them FOM and 2 OpInf");
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->fuse = enable != 0;
+  ctx->fuse_kc = kc > 0 ? kc : 1;
+  return OSAM_OK;
+}
+
 int32_t osam_set_rom_path(osam_ctx *c, int32_t sd, int32_t path) {
   if (!c) return OSAM_E_INVALID;
   Ctx *ctx = reinterpret_cast<Ctx *>(c);

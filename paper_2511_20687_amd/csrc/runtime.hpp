@@ -46,6 +46,8 @@ struct Subdomain {
   // interior (fe_chunks workgroups of fe_kc layers) plus the column kernel (64 threads, one
   // layer per thread) for the boundary columns; fe_nblocks = workgroup partials per instance
   int fe_block = 256, fe_kc = 8, fe_chunks = 1, fe_int_blocks = 0, fe_nblocks = 0, max_nblocks = 0;
+  // FE part of a fused sweep: 512-thread workgroups of the column kernel, fz_kc layers per thread
+  int fz_kc = 1, fz_chunks = 1, fz_int_blocks = 0, fz_nblocks = 0;
   // OpInf
   bool rom = false;
   int r = 0, rs = 0;
@@ -133,6 +135,12 @@ struct Ctx {
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int32_t launch_round_concurrent(const Opts &o);
+  // fused sweeps: every subdomain's step in one launch (sweep_kernels.hip)
+  bool fuse = false;
+  int fuse_kc = 1;
+  std::string fusion_unsupported() const;
+  void fuse_layout(Subdomain &s);
+  int32_t launch_round_fused(const Opts &o);
   int32_t autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out);
   int32_t apply_tuning(const osam_tuning &t);
   hipEvent_t next_event();

@@ -1,0 +1,44 @@
+// One Schwarz sweep (Alg. 1 inner loop) of every subdomain in a single launch.
+//
+// Within a sweep no step kernel reads what another writes: every source pushes
+// its next-step displacement into the buffer role of the next step, which no
+// kernel of the sweep reads, and the convergence sums go to separate partial
+// buffers.  So the FOM step (fe_body) and the OpInf step (rom_body) of all
+// subdomains can run side by side: subdomain i owns the workgroups
+// [off_i, off_i + nblk_i) of one grid, and a finisher kernel afterwards reduces
+// the sums and takes the decision of Eq. conv_criterion.  Results equal those of
+// separate launches; the sweep costs one dispatch and the longest subdomain
+// instead of the sum of them.
+#include <hip/hip_ext.h>
+
+#include "fe_body.hpp"
+#include "rom_body.hpp"
+
+namespace osam {
+
+template <typename T, bool ONE>
+__global__ void __launch_bounds__(kRomThreads) sweep_kernel(SweepArgs<T> S) {
+  int x = blockIdx.x, i = 0;
+  while (i + 1 < S.n && x >= S.nblk[i]) x -= S.nblk[i++];
+  if (S.rom_idx[i] >= 0) rom_body<T>(S.rom[S.rom_idx[i]], x);
+  else fe_body<T, kModeStep, ONE>(S.fe[S.fe_idx[i]], x);
+}
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T> &S, int batch, bool one, size_t smem, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1) {
+  int total = 0;
+  for (int i = 0; i < S.n; ++i) total += S.nblk[i];
+  if (total <= 0 || smem > 65536) return hipErrorInvalidValue;
+  const dim3 grid(total, batch);
+  if (one) hipExtLaunchKernelGGL((sweep_kernel<T, true>), grid, dim3(kRomThreads), (uint32_t)smem, s, ev0, ev1, 0, S);
+  else hipExtLaunchKernelGGL((sweep_kernel<T, false>), grid, dim3(kRomThreads), (uint32_t)smem, s, ev0, ev1, 0, S);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, bool, size_t, hipStream_t, hipEvent_t,
+                                        hipEvent_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, bool, size_t, hipStream_t, hipEvent_t,
+                                         hipEvent_t);
+
+}  // namespace osam

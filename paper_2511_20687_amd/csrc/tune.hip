@@ -3,9 +3,10 @@
 // (column kernel: threads per workgroup and layers per thread; layer-staged
 // kernel: layers per workgroup), the OpInf evaluation path (fused or batched)
 // and the launch mode (host launches, or replays of a captured graph on one or
-// two streams).  None of these changes the results.  The tuner times short
-// trial runs from the context's current state and descends one coordinate at a
-// time: FE shape per FOM subdomain, OpInf path per OpInf subdomain, launch mode.
+// two streams, or fused sweeps of one launch each).  None of these changes the
+// results.  The tuner times short trial runs from the context's current state
+// and descends one coordinate at a time: FE shape per FOM subdomain, OpInf path
+// per OpInf subdomain, launch mode, sweep fusion.
 // The choice is cached per configuration (precision, batch, subdomain sizes,
 // reduced sizes) for the lifetime of the process.
 #include <hip/hip_runtime.h>
@@ -53,6 +54,8 @@ int32_t Ctx::apply_tuning(const osam_tuning &t) {
   }
   graph_rounds = t.graph_rounds;
   graph_streams = t.graph_streams;
+  fuse = t.fusion_kc > 0;
+  fuse_kc = fuse ? t.fusion_kc : 1;
   return OSAM_OK;
 }
 
@@ -92,6 +95,7 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
   };
   graph_rounds = 0;
   graph_streams = 1;
+  fuse = false;
   double best = 0.0;
   if ((st = trial(&best))) return st;
   // 1. FE launch shape, one FOM subdomain at a time
@@ -148,6 +152,29 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
   }
   graph_rounds = gr;
   graph_streams = gs;
+  // 4. fused sweeps (layers per thread of the FE part) with host launches or graphs
+  int fkc = 0;
+  if (fusion_unsupported().empty()) {
+    const int fmodes[][2] = {{1, 0}, {1, 32}, {1, 128}, {4, 0}, {4, 32}};
+    for (const auto &m : fmodes) {
+      fuse = true;
+      fuse_kc = m[0];
+      graph_rounds = m[1];
+      graph_streams = 1;
+      double ms;
+      if ((st = trial(&ms))) return st;
+      if (ms < best) {
+        best = ms;
+        fkc = m[0];
+        gr = m[1];
+        gs = 1;
+      }
+    }
+  }
+  fuse = fkc > 0;
+  fuse_kc = fuse ? fkc : 1;
+  graph_rounds = gr;
+  graph_streams = gs;
   for (size_t i = 0; i < sds.size() && i < 8; ++i) {
     t.fe_block[i] = sds[i]->rom ? 0 : sds[i]->fe_block;
     t.fe_kc[i] = sds[i]->rom ? 0 : sds[i]->fe_kc;
@@ -155,6 +182,7 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
   }
   t.graph_rounds = gr;
   t.graph_streams = gs;
+  t.fusion_kc = fkc;
   t.ms_per_step = best;
   t.from_cache = 0;
   {

@@ -56,16 +56,18 @@ def _roms_for(bar, layers, kinds, dt, r, rs, quadratic, with_c, seed):
     return roms
 
 
-@pytest.mark.parametrize("kinds,quadratic,with_c,precision,tol", [
-    (("fom", "opinf"), False, False, "f64", 1e-10),
-    (("fom", "opinf"), True, True, "f64", 1e-10),
-    (("opinf", "fom"), True, False, "f64", 1e-10),
-    (("opinf", "opinf"), True, False, "f64", 1e-10),
-    (("opinf", "fom", "opinf"), True, False, "f64", 1e-10),
-    (("fom", "opinf"), True, False, "f32", 1e-4),
-    (("opinf", "fom", "opinf"), True, False, "f32", 1e-4),
+@pytest.mark.parametrize("kinds,quadratic,with_c,precision,tol,guess", [
+    (("fom", "opinf"), False, False, "f64", 1e-10, "hold"),
+    (("fom", "opinf"), True, True, "f64", 1e-10, "hold"),
+    (("opinf", "fom"), True, False, "f64", 1e-10, "hold"),
+    (("opinf", "opinf"), True, False, "f64", 1e-10, "hold"),
+    (("opinf", "opinf"), True, False, "f64", 1e-10, "predictor"),
+    (("opinf", "fom", "opinf"), True, False, "f64", 1e-10, "hold"),
+    (("opinf", "fom", "opinf"), True, True, "f64", 1e-10, "predictor"),
+    (("fom", "opinf"), True, False, "f32", 1e-4, "hold"),
+    (("opinf", "fom", "opinf"), True, False, "f32", 1e-4, "hold"),
 ])
-def test_synthetic_opinf_couplings_match_oracle(kinds, quadratic, with_c, precision, tol):
+def test_synthetic_opinf_couplings_match_oracle(kinds, quadratic, with_c, precision, tol, guess):
     import torch
     bar = Bar(3, 3, 36)
     dt = bar.explicit_dt()
@@ -75,8 +77,8 @@ def test_synthetic_opinf_couplings_match_oracle(kinds, quadratic, with_c, precis
     u0 = gaussian_pulse_u(bar, 1e-3, 0.45, 0.06)
     v0 = np.zeros_like(u0)
     n = 150
-    print(f"[{kinds} quad={quadratic} c={with_c} {precision}] oracle", flush=True)
-    ref = Coupled(models).run(u0, v0, n, SchwarzOptions(), record=("u", "q"))
+    print(f"[{kinds} quad={quadratic} c={with_c} {precision} {guess}] oracle", flush=True)
+    ref = Coupled(models).run(u0, v0, n, SchwarzOptions(guess=guess), record=("u", "q"))
     recs = []
     for i, sd in enumerate(sds):
         z = ctx.sizes(sd)
@@ -86,7 +88,8 @@ def test_synthetic_opinf_couplings_match_oracle(kinds, quadratic, with_c, precis
         recs.append(t)
     ctx.set_initial(0, u0, v0)
     print("gpu", flush=True)
-    info = ctx.run(n)
+    from paper_2511_20687_amd import osam
+    info = ctx.run(n, osam.Options(guess=1 if guess == "predictor" else 0))
     for i, (lo, hi) in enumerate(layers):
         got = recs[i][0].cpu().numpy()
         if kinds[i] == "opinf":
