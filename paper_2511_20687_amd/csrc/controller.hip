@@ -164,11 +164,11 @@ static uint16_t bf16_rne(float x) {
 
 int32_t Ctx::setup_pre(Subdomain &d) {
   HIPCHK(hipStreamSynchronize(stream));
-  void *old[] = {d.pre_fa, d.pre_fh, d.pre_pairs, d.pre_f0, d.pre_g};
+  void *old[] = {d.pre_fa, d.pre_fh, d.pre_blocks, d.pre_f0, d.pre_g};
   for (void *p : old) dfree(p);
   d.pre_fa = nullptr;
   d.pre_fh = nullptr;
-  d.pre_pairs = nullptr;
+  d.pre_blocks = nullptr;
   d.pre_f0 = nullptr;
   d.pre_g = nullptr;
   d.pre = false;
@@ -181,11 +181,25 @@ int32_t Ctx::setup_pre(Subdomain &d) {
   d.pre_prec = bf16 ? 1 : 0;
   d.pre_nrt = (r + 15) / 16;
   d.pre_nkba = (r + 3) / 4;
-  d.pre_nkbh = r2 > 0 ? (bf16 ? (r2 + 15) / 16 : (r2 + 3) / 4) : 0;
+  // H's K blocks: row i of the compressed triangle (columns j = i .. r-1) cut
+  // into blocks of kw columns, the last one zero-padded
+  const int kw = bf16 ? 16 : 4;
+  std::vector<int> blk;
+  for (int i = 0; i < r && r2 > 0; ++i)
+    for (int j0 = i; j0 < r; j0 += kw) blk.push_back(i | (j0 << 16));
+  d.pre_nkbh = (int)blk.size();
   const int nit = (batch + 15) / 16, nkb = d.pre_nkba + d.pre_nkbh;
-  d.pre_ks = std::max(1, std::min((512 + d.pre_nrt * nit - 1) / (d.pre_nrt * nit), std::max(1, nkb / 8)));
+  d.pre_ni = nit >= 4 ? 4 : (nit >= 2 ? 2 : 1);
+  const int ngrp = (nit + d.pre_ni - 1) / d.pre_ni;
+  // K splits: about 512 workgroups, at most 16 partial sums for the step kernel to add
+  d.pre_ks = std::max(1, std::min({16, (512 + d.pre_nrt * ngrp - 1) / (d.pre_nrt * ngrp), std::max(1, nkb / 16)}));
   auto Aij = [&](int i, int k) -> double { return i < r && k < r ? d.oh.A[(size_t)k * r + i] : 0.0; };
-  auto Him = [&](int i, int m) -> double { return i < r && m < r2 ? d.oh.H[(size_t)m * r + i] : 0.0; };
+  // H[i][m(a, b)], m(a, b) = a r - a (a - 1) / 2 + (b - a): compressed index of q_a q_b (a <= b)
+  auto Hab = [&](int i, int a, int b) -> double {
+    if (i >= r || b >= r) return 0.0;
+    const size_t m = (size_t)a * r - (size_t)a * (a - 1) / 2 + (b - a);
+    return d.oh.H[m * r + i];
+  };
   int32_t st = OSAM_OK;
   // lane l of the 16x16x4 block (rt, kb) holds M[16 rt + l % 16][4 kb + l / 16]
   {
@@ -199,31 +213,34 @@ int32_t Ctx::setup_pre(Subdomain &d) {
     HIPCHK(hipMemcpy(d.pre_fa, fa.data(), fa.size() * 4, hipMemcpyHostToDevice));
   }
   if (r2 > 0 && !bf16) {
+    // lane l of H block (rt, kb) = (i, j0): H[16 rt + l % 16][m(i, j0 + l / 16)]
     std::vector<float> fh((size_t)d.pre_nrt * d.pre_nkbh * 64);
     for (int rt = 0; rt < d.pre_nrt; ++rt)
-      for (int kb = 0; kb < d.pre_nkbh; ++kb)
+      for (int kb = 0; kb < d.pre_nkbh; ++kb) {
+        const int i = blk[kb] & 0xffff, j0 = blk[kb] >> 16;
         for (int l = 0; l < 64; ++l)
-          fh[((size_t)rt * d.pre_nkbh + kb) * 64 + l] = (float)Him(rt * 16 + l % 16, kb * 4 + l / 16);
+          fh[((size_t)rt * d.pre_nkbh + kb) * 64 + l] = (float)Hab(rt * 16 + l % 16, i, j0 + l / 16);
+      }
     d.pre_fh = arena_alloc(fh.size() * 4, &st);
     if (st) return fail(st, "out of device memory");
     HIPCHK(hipMemcpy(d.pre_fh, fh.data(), fh.size() * 4, hipMemcpyHostToDevice));
   } else if (r2 > 0) {
-    // lane l of the 16x16x16 block (rt, kb) holds H[16 rt + l % 16][16 kb + 4 (l / 16) + j], j < 4
+    // lane l of the 16x16x16 block (rt, kb) = (i, j0): H[16 rt + l % 16][m(i, j0 + 4 (l / 16) + j)], j < 4
     std::vector<uint16_t> fh((size_t)d.pre_nrt * d.pre_nkbh * 64 * 4);
     for (int rt = 0; rt < d.pre_nrt; ++rt)
-      for (int kb = 0; kb < d.pre_nkbh; ++kb)
+      for (int kb = 0; kb < d.pre_nkbh; ++kb) {
+        const int i = blk[kb] & 0xffff, j0 = blk[kb] >> 16;
         for (int l = 0; l < 64; ++l)
           for (int j = 0; j < 4; ++j)
             fh[(((size_t)rt * d.pre_nkbh + kb) * 64 + l) * 4 + j] =
-                bf16_rne((float)Him(rt * 16 + l % 16, kb * 16 + 4 * (l / 16) + j));
+                bf16_rne((float)Hab(rt * 16 + l % 16, i, j0 + 4 * (l / 16) + j));
+      }
     d.pre_fh = arena_alloc(fh.size() * 2, &st);
     if (st) return fail(st, "out of device memory");
     HIPCHK(hipMemcpy(d.pre_fh, fh.data(), fh.size() * 2, hipMemcpyHostToDevice));
   }
-  std::vector<int> pr(std::max(r2, 1), 0);
-  for (int i = 0, m = 0; i < r && r2 > 0; ++i)
-    for (int j = i; j < r; ++j) pr[m++] = i | (j << 16);
-  d.pre_pairs = static_cast<int *>(arena_alloc(pr.size() * sizeof(int), &st));
+  if (blk.empty()) blk.push_back(0);
+  d.pre_blocks = static_cast<int *>(arena_alloc(blk.size() * sizeof(int), &st));
   d.pre_f0 = static_cast<float *>(arena_alloc((size_t)d.pre_ks * batch * r * sizeof(float), &st));
   long long nfd = 0;
   for (int f = 0; f < 2; ++f)
@@ -231,7 +248,7 @@ int32_t Ctx::setup_pre(Subdomain &d) {
   d.pre_gs = nfd > 0 && rs > 0 ? (int)std::max(1LL, std::min(64LL, (nfd + 2047) / 2048)) : 0;
   if (d.pre_gs > 0) d.pre_g = static_cast<double *>(arena_alloc((size_t)d.pre_gs * batch * rs * sizeof(double), &st));
   if (st) return fail(st, "out of device memory");
-  HIPCHK(hipMemcpy(d.pre_pairs, pr.data(), pr.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d.pre_blocks, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice));
   d.pre = true;
   return OSAM_OK;
 }
@@ -383,6 +400,19 @@ int32_t Ctx::rom_start(int i, int inst, const std::vector<double> &q, const std:
   }
   std::vector<double> q1(d.r);
   for (int k = 0; k < d.r; ++k) q1[k] = q[k] + d.desc.dt * qd[k] + 0.5 * d.desc.dt * d.desc.dt * qdd[k];
+  // the predictor as the step kernel forms it: in the context precision, fma(h, q'', fma(dt, q', q))
+  {
+    std::vector<double> qp(d.r);
+    for (int k = 0; k < d.r; ++k) {
+      if (prec == OSAM_FP64) {
+        qp[k] = std::fma(0.5 * d.desc.dt * d.desc.dt, qdd[k], std::fma(d.desc.dt, qd[k], q[k]));
+      } else {
+        const float h = (float)(0.5 * d.desc.dt * d.desc.dt), dt = (float)d.desc.dt;
+        qp[k] = (double)std::fma(h, (float)qdd[k], std::fma(dt, (float)qd[k], (float)q[k]));
+      }
+    }
+    if ((st = upload((char *)d.qpred + off, qp.data(), d.r))) return st;
+  }
   int e = 0;
   for (size_t i2 = 0; i2 < sds.size(); ++i2) {
     Subdomain &fd = *sds[i2];
@@ -664,6 +694,7 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
     A.g_gs = s.pre_gs;
     A.g_stride = (long long)c.batch * s.rs;
   }
+  A.qpred = (T *)s.qpred;
   for (int k = 0; k < 2; ++k) {
     A.q[k] = (T *)s.q[k];
     A.qd[k] = (T *)s.qd[k];
@@ -738,17 +769,12 @@ static void fill_pre_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomPreAr
   P.nrt = s.pre_nrt;
   P.ks = s.pre_ks;
   P.nit = (c.batch + 15) / 16;
+  P.ni = s.pre_ni;
   P.frag_a = s.pre_fa;
   P.frag_h = s.pre_fh;
-  P.pairs = s.pre_pairs;
+  P.blocks = s.pre_blocks;
   P.c = (const float *)s.d_c;
-  for (int k = 0; k < 2; ++k) {
-    P.q[k] = (const float *)s.q[k];
-    P.qd[k] = (const float *)s.qd[k];
-    P.qdd[k] = (const float *)s.qdd[k];
-  }
-  P.dt = (float)s.desc.dt;
-  P.half_dt2 = (float)(0.5 * s.desc.dt * s.desc.dt);
+  P.qpred = (const float *)s.qpred;
   P.f0part = s.pre_f0;
   int nf = 0;
   for (int f = 0; f < 2 && s.pre_g; ++f) {
@@ -891,7 +917,14 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
   int nfe = 0, nrom = 0;
   bool one = true;
   size_t smem = 0;
-  for (int i = 0; i < S.n; ++i) {
+  // grid order: the OpInf steps (few workgroups, the longest chain of dependent
+  // steps) first, so they are dispatched before the FE workgroups fill the chip
+  std::vector<int> order;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = 0; i < S.n; ++i)
+      if (c.sds[i]->rom == (pass == 0)) order.push_back(i);
+  for (int slot = 0; slot < S.n; ++slot) {
+    const int i = order[slot];
     Subdomain &d = *c.sds[i];
     if (!d.rom) {
       FeArgs<T> &A = S.fe[nfe];
@@ -903,9 +936,9 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
       A.part_stride = d.fz_nblocks;
       A.part_off = 0;
       one = one && d.fz_kc == 1;
-      S.nblk[i] = d.fz_nblocks;
-      S.fe_idx[i] = nfe++;
-      S.rom_idx[i] = -1;
+      S.nblk[slot] = d.fz_nblocks;
+      S.fe_idx[slot] = nfe++;
+      S.rom_idx[slot] = -1;
     } else {
       RomArgs<T> &A = S.rom[nrom];
       fill_rom_args<T>(c, d, i, o, A);
@@ -916,9 +949,9 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
         if (A.fin[f].type == 3) A.fin[f].pred = 1;
       int rows = 0;
       for (int e = 0; e < A.nexp; ++e) rows = std::max(rows, 3 * A.ex[e].npl);
-      S.nblk[i] = rows > 0 ? (rows + 511) / 512 : 1;
-      S.fe_idx[i] = -1;
-      S.rom_idx[i] = nrom++;
+      S.nblk[slot] = rows > 0 ? (rows + 511) / 512 : 1;
+      S.fe_idx[slot] = -1;
+      S.rom_idx[slot] = nrom++;
       smem = std::max(smem, rom_smem_bytes<T>(A.r, A.rs, A.r2));
     }
   }
@@ -1171,19 +1204,20 @@ int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
   const int r = oh.r, rs = oh.rs, r2 = r * (r + 1) / 2;
   const long long nf = 3 * d.nfree_nodes;
   // free any previous OpInf data and the FOM state buffers
-  void *old[] = {d.d_A, d.d_H, d.d_B, d.d_c, d.d_Phi, d.q[0], d.q[1], d.qd[0], d.qd[1], d.qdd[0], d.qdd[1],
+  void *old[] = {d.d_A, d.d_H, d.d_B, d.d_c, d.d_Phi, d.q[0], d.q[1], d.qd[0], d.qd[1], d.qdd[0], d.qdd[1], d.qpred,
                  d.u[0], d.u[1], d.u[2], d.v[0], d.v[1], d.a[0], d.a[1], d.face_phis[0], d.face_phis[1],
-                 d.face_tm[0], d.face_tm[1], d.pre_fa, d.pre_fh, d.pre_pairs, d.pre_f0, d.pre_g};
+                 d.face_tm[0], d.face_tm[1], d.pre_fa, d.pre_fh, d.pre_blocks, d.pre_f0, d.pre_g};
   HIPCHK(hipStreamSynchronize(stream));
   for (void *p : old) dfree(p);
   d.d_A = d.d_H = d.d_B = d.d_c = d.d_Phi = nullptr;
   for (int k = 0; k < 2; ++k) d.q[k] = d.qd[k] = d.qdd[k] = nullptr;
+  d.qpred = nullptr;
   for (int k = 0; k < 3; ++k) d.u[k] = nullptr;
   for (int k = 0; k < 2; ++k) d.v[k] = d.a[k] = nullptr;
   for (int k = 0; k < 2; ++k) d.face_phis[k] = d.face_tm[k] = nullptr;
   d.pre_fa = nullptr;
   d.pre_fh = nullptr;
-  d.pre_pairs = nullptr;
+  d.pre_blocks = nullptr;
   d.pre_f0 = nullptr;
   d.pre_g = nullptr;
   d.pre = false;
@@ -1211,7 +1245,11 @@ int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
     d.qd[k] = alloc_t((size_t)batch * r, &st);
     d.qdd[k] = alloc_t((size_t)batch * r, &st);
   }
+  // rounded up to whole groups of 64 instances (the batched f0 kernel reads groups)
+  const size_t npred = (size_t)(batch + 63) / 64 * 64 * r;
+  d.qpred = alloc_t(npred, &st);
   if (st) return fail(st, "out of device memory for OpInf data");
+  HIPCHK(hipMemsetAsync(d.qpred, 0, npred * esize(), stream));
   if ((st = upload(d.d_A, Ar.data(), Ar.size()))) return st;
   if (oh.quadratic && (st = upload(d.d_H, Hr.data(), Hr.size()))) return st;
   if (rs > 0 && (st = upload(d.d_B, Br.data(), Br.size()))) return st;

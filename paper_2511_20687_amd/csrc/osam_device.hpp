@@ -97,9 +97,9 @@ __device__ __forceinline__ double wave_sum64(double x) {
 }
 
 // Sums of FOM subdomain k's partials, computed by one wave (lane 0 holds them).
-// Loads are issued in batches of 16 per lane before any is consumed.
+// Loads are issued in batches of U per lane before any is consumed.
+template <int U>
 __device__ inline double2 fom_sums(const FinishArgs &F, int k, int b, int lane) {
-  constexpr int U = 16;
   const int nb = F.nblocks[k];
   const double2 *pp = reinterpret_cast<const double2 *>(F.part[k]) + (long long)b * nb;
   double sa = 0.0, sd = 0.0;
@@ -120,6 +120,8 @@ __device__ inline double2 fom_sums(const FinishArgs &F, int k, int b, int lane) 
 // The decider: called by one whole wave (lane 0 writes `out`).  own_sd >= 0
 // with own_abs2/own_den2: the calling OpInf kernel's own sums.
 // pre (optional): the FOM sums already reduced by the caller, [abs2, den2] per FOM subdomain.
+// U: partial-sum loads in flight per lane (registers: 4 U).
+template <int U = 16>
 __device__ inline void finish_sweep(const Status *in, Status *out, const FinishArgs &F, const Opts &o, int b,
                                     int own_sd = -1, double own_abs2 = 0.0, double own_den2 = 0.0,
                                     const double *pre = nullptr) {
@@ -128,7 +130,7 @@ __device__ inline void finish_sweep(const Status *in, Status *out, const FinishA
   if (!(s.flags & kFinished)) {
     // per-subdomain sums, written with compile-time indices only (no private-memory indexing)
     for (int k = 0; k < F.nfom; ++k) {
-      const double2 t = pre ? make_double2(pre[2 * k], pre[2 * k + 1]) : fom_sums(F, k, b, lane);
+      const double2 t = pre ? make_double2(pre[2 * k], pre[2 * k + 1]) : fom_sums<U>(F, k, b, lane);
       const int j = F.sd[k];
 #pragma unroll
       for (int i = 0; i < kMaxSd; ++i)
@@ -246,6 +248,7 @@ struct RomArgs {
   const T *B;              // [r][rs] row-major or null
   const T *c;              // [r] or null
   T *q[2], *qd[2], *qdd[2];  // [batch][r] by step parity
+  T *qpred;                // [batch][r]: Newmark predictor of the latest state
   T dt, half_dt, half_dt2;
   int nfaces, nexp;
   RomFaceIn<T> fin[2];
@@ -272,13 +275,12 @@ struct RomPreArgs {
   int r, rs, r2, batch;
   int prec;                // 0: FP32 operands, 1: BF16 operands (FP32 accumulation)
   int nkba, nkbh;          // K blocks of A (FP32, 4 wide) and of H (4 wide FP32 / 16 wide BF16)
-  int nrt, ks, nit;        // row tiles of 16, K splits, instance tiles of 16
+  int nrt, ks, nit, ni;    // row tiles of 16, K splits, instance tiles of 16, tiles per workgroup
   const float *frag_a;     // A in MFMA fragment order (FP32)
   const void *frag_h;      // H in MFMA fragment order (FP32 or BF16), null when linear
-  const int *pairs;        // compressed quadratic index m -> i | j << 16
+  const int *blocks;       // H K block -> row i of the triangle | first column j0 << 16
   const float *c;
-  const float *q[2], *qd[2], *qdd[2];
-  float dt, half_dt2;
+  const float *qpred;      // [batch][r]: the predictor q(t_k) of each instance starting a step
   float *f0part;           // [ks][batch][r]
   int nface, gs;           // FOM-fed faces, DOF splits
   long long fn[2];
@@ -293,7 +295,7 @@ struct RomPreArgs {
 
 hipError_t launch_rom_pre(const RomPreArgs &P, hipStream_t s);
 
-// One Schwarz sweep in a single launch: subdomain i of the sweep owns the next
+// One Schwarz sweep in a single launch: the subdomain in slot i owns the next
 // nblk[i] workgroups of the grid (x), instances along y; fe_idx / rom_idx pick
 // its arguments (rom_idx < 0: a FOM step).  Kernel arguments stay below 4 KB.
 constexpr int kSweepMax = 4, kSweepFe = 3, kSweepRom = 2;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "osam_device.hpp"
+#include "stencil.hpp"
 
 namespace osam {
 
@@ -46,8 +47,19 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double (*red)[kRom
 // does not depend on this step's results is issued first, in one straight-line
 // batch (indices clamped into range, values zeroed afterwards), speculatively
 // for both state parities and all three face roles.
+// Variants (register budget): kRomPre = f0 and the FOM-fed g^ arrive as
+// partial sums (no A rows, no quadratic term, no FOM face here);
+// kRomNoPushRegs = no push row held in registers (no FOM neighbour).
+constexpr int kRomPre = 1, kRomNoPushRegs = 2;
+
 template <typename T>
+__host__ __device__ inline int rom_variant(const RomArgs<T> &A) {
+  return (A.f0part ? kRomPre : 0) | (A.nexp == 0 ? kRomNoPushRegs : 0);
+}
+
+template <typename T, int V>
 __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
+  constexpr bool PRE = (V & kRomPre) != 0, PUSHREG = (V & kRomNoPushRegs) == 0;
   const int b = blockIdx.y;
   const Status *stp = A.status + b;
   const int r = A.r, rs = A.rs, r2 = A.r2;
@@ -82,11 +94,16 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   // batched path: this row's f0 and this thread's mode of g^ (partial sums, fixed order)
   T x_f0 = T(0);
   double x_g = 0.0;
-  if (A.f0part)
-    for (int k = 0; k < A.f0_ks; ++k) x_f0 += A.f0part[k * A.f0_stride + qo + tq];
+  // (buffer loads: one per-lane offset, the split in the uniform offset)
+  if (A.f0part) {
+    const Field<T> F0(A.f0part);
+    const unsigned vo = (unsigned)((qo + tq) * (long long)sizeof(T));
+    for (int k = 0; k < A.f0_ks; ++k) x_f0 += F0.ld(vo, (unsigned)(k * A.f0_stride * (long long)sizeof(T)));
+  }
   if (A.gpart && rs > 0) {
-    const int tg = min(tid, rs - 1);
-    for (int k = 0; k < A.g_gs; ++k) x_g += A.gpart[k * A.g_stride + (long long)b * rs + tg];
+    const Field<double> G(A.gpart);
+    const unsigned vo = (unsigned)(((long long)b * rs + min(tid, rs - 1)) * 8);
+    for (int k = 0; k < A.g_gs; ++k) x_g += G.ld(vo, (unsigned)(k * A.g_stride * 8));
   }
   T arow[kRowsPerWave][2], brow[kRowsPerWave];
   const int l0 = min(lane, r - 1), l1 = min(lane + 64, r - 1), lb = min(lane, rs > 0 ? rs - 1 : 0);
@@ -95,7 +112,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     const int i = wid + kRomWaves * j;
     arow[j][0] = arow[j][1] = brow[j] = T(0);
     if (i < r) {   // wave-uniform
-      if (A.A) {
+      if (!PRE && A.A) {
         arow[j][0] = A.A[(long long)i * r + l0];
         if (r > 64) arow[j][1] = A.A[(long long)i * r + l1];
       }
@@ -103,7 +120,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     }
   }
   // first face when fed by a FOM: values of all three roles and up to 8 modes
-  const bool small_face = A.nfaces > 0 && A.fin[0].type == kFaceFom &&
+  const bool small_face = !PRE && A.nfaces > 0 && A.fin[0].type == kFaceFom &&
                           A.fin[0].n <= kFaceDofs * kRomThreads && rs <= 8;
   T fv[3][kFaceDofs], fph[kFaceDofs][8];
   if (small_face) {
@@ -118,7 +135,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     }
   }
   // this thread's push row (export 0): (Pi Phi)[m, 0..r)
-  const bool reg_push = A.nexp > 0;
+  const bool reg_push = PUSHREG && A.nexp > 0;
   T pv[kPushK];
   if (reg_push) {
     const RomExport<T> &ex = A.ex[0];
@@ -128,7 +145,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     for (int k = 0; k < kPushK; ++k) pv[k] = k < r ? ex.piphi[(long long)k * n + m] : T(0);
   }
   // the FOM workgroups' partial sums, when this workgroup decides
-  bool small_part = last && g == 0 && F.nfom <= 2;
+  bool small_part = !PRE && last && g == 0 && F.nfom <= 2;
   for (int k = 0; k < F.nfom; ++k) small_part = small_part && F.nblocks[k] <= kFaceDofs * kRomThreads;
   double2 pa[2][kFaceDofs];
   if (small_part && F.nfom > 0) {
@@ -141,7 +158,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     }
   }
   if (flags & kFinished) {
-    if (last && g == 0 && wid == 0) finish_sweep(A.status, A.status_out, F, A.opts, b);   // carries the status over
+    if (last && g == 0 && wid == 0) finish_sweep<4>(A.status, A.status_out, F, A.opts, b);   // carries the status over
     return;
   }
   const int n_iter = iter + 1;
@@ -164,7 +181,9 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   for (int k = tid; k < rs; k += kRomThreads) sh[k] = k == tid ? (T)x_g : T(0);
 
   // ---- 3. reduced boundary input g^ (and the FOM partial sums, same reduction)
-  {
+  if (PRE) {
+    __syncthreads();   // sh is complete
+  } else {
     double part[12];
 #pragma unroll
     for (int kk = 0; kk < 12; ++kk) part[kk] = 0.0;
@@ -248,7 +267,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   __syncthreads();
 
   // ---- 4. compressed quadratic vector q_i q_j (i <= j), row by row
-  if (r2 > 0) {
+  if (!PRE && r2 > 0) {
     for (int idx = tid; idx < r * r; idx += kRomThreads) {
       const int i = idx / r, j = idx - i * r;
       if (j >= i) k2[i * r - (i * (i - 1)) / 2 + (j - i)] = q1s[i] * q1s[j];
@@ -261,8 +280,8 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   for (int j = 0; j < kRowsPerWave; ++j) {
     const int i = wid + kRomWaves * j;
     if (i >= r) break;
-    T s = arow[j][0] * (lane < r ? q1s[lane] : T(0)) + arow[j][1] * (lane + 64 < r ? q1s[lane + 64] : T(0));
-    if (r2 > 0) {
+    T s = PRE ? T(0) : arow[j][0] * (lane < r ? q1s[lane] : T(0)) + arow[j][1] * (lane + 64 < r ? q1s[lane + 64] : T(0));
+    if (!PRE && r2 > 0) {
       const T *Hr = A.H + (long long)i * r2;
 #pragma unroll 4
       for (int m = lane; m < r2; m += 64) s += Hr[m] * k2[m];
@@ -280,7 +299,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   if (tid < r) {
     const T qn = q1s[tid], an = qdd1s[tid] + x_c;
     const T vn = x_qd0 + A.half_dt * (x_qdd0 + an);
-    qps[tid] = qn + A.dt * vn + A.half_dt2 * an;
+    qps[tid] = newmark_pred<T>(qn, vn, an, A.dt, A.half_dt2);
     if (g == 0) {
       const double d = ((double)qn - (double)x_old_q) + (double)A.dt * ((double)vn - (double)x_old_v);
       nrm[0] = d * d;
@@ -289,6 +308,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
       A.q[1 - s2][qo + tid] = qn;
       A.qd[1 - s2][qo + tid] = vn;
       A.qdd[1 - s2][qo + tid] = an;
+      A.qpred[qo + tid] = qps[tid];   // the next step's q(t_k) if this iterate is accepted
       if (A.rec_q && A.rec_every > 0 && ((step + 1) % A.rec_every) == 0) {
         const long long col = (step + 1) / A.rec_every;
         if (col < A.rec_ncols) A.rec_q[((long long)b * A.rec_ncols + col) * r + tid] = qn;
@@ -304,14 +324,14 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     const int n = 3 * ex.npl;
     const int m = g * kRomThreads + tid;
     T acc0 = T(0), acc1 = T(0);
-    if (e == 0) {
+    if (PUSHREG && e == 0) {
 #pragma unroll
       for (int k = 0; k < kPushK; k += 2) {
         if (k < r) acc0 += pv[k] * qps[k];
         if (k + 1 < r) acc1 += pv[k + 1] * qps[k + 1];
       }
     }
-    for (int k0 = e == 0 ? kPushK : 0; k0 < r; k0 += 16) {
+    for (int k0 = PUSHREG && e == 0 ? kPushK : 0; k0 < r; k0 += 16) {
       T pw[16];
       const long long mm = min(m, n - 1);
 #pragma unroll
@@ -330,7 +350,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   if (g != 0) return;
   if (last) {
     if (wid == 0)
-      finish_sweep(A.status, A.status_out, F, A.opts, b, A.sd, nsum[0], nsum[1], small_part ? tot + 8 : nullptr);
+      finish_sweep<4>(A.status, A.status_out, F, A.opts, b, A.sd, nsum[0], nsum[1], small_part ? tot + 8 : nullptr);
   } else if (tid == 0) {
     A.status_out[b].sd_abs2[A.sd] = nsum[0];
     A.status_out[b].sd_den2[A.sd] = nsum[1];

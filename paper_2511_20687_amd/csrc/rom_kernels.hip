@@ -21,9 +21,9 @@
 
 namespace osam {
 
-template <typename T>
+template <typename T, int V>
 __global__ void __launch_bounds__(kRomThreads) rom_kernel(RomArgs<T> A) {
-  rom_body<T>(A, blockIdx.x);
+  rom_body<T, V>(A, blockIdx.x);
 }
 
 template <typename T>
@@ -38,7 +38,18 @@ hipError_t launch_rom(const RomArgs<T> &A, int batch, hipStream_t s, hipEvent_t 
   int rows = 0;
   for (int e = 0; e < A.nexp; ++e) rows = rows > 3 * A.ex[e].npl ? rows : 3 * A.ex[e].npl;
   const int G = rows > 0 ? (rows + kRomThreads - 1) / kRomThreads : 1;
-  hipExtLaunchKernelGGL(rom_kernel<T>, dim3(G, batch), dim3(kRomThreads), (uint32_t)smem, s, ev0, ev1, 0, A);
+  const dim3 grid(G, batch), block(kRomThreads);
+  const int v = rom_variant(A);
+  if constexpr (sizeof(T) == 8) {   // the batched parts are FP32 only
+    if (v & kRomPre) return hipErrorInvalidValue;
+    if (v == kRomNoPushRegs) hipExtLaunchKernelGGL((rom_kernel<T, kRomNoPushRegs>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
+    else hipExtLaunchKernelGGL((rom_kernel<T, 0>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
+  } else {
+    if (v == 3) hipExtLaunchKernelGGL((rom_kernel<T, 3>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
+    else if (v == 2) hipExtLaunchKernelGGL((rom_kernel<T, 2>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
+    else if (v == 1) hipExtLaunchKernelGGL((rom_kernel<T, 1>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
+    else hipExtLaunchKernelGGL((rom_kernel<T, 0>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_rom<float>(const RomArgs<float> &, int, hipStream_t, hipEvent_t, hipEvent_t);

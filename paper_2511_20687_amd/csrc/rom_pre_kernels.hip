@@ -10,12 +10,12 @@
 //    The linear part always takes FP32 operands (v_mfma_f32_16x16x4_f32); the
 //    quadratic part FP32 operands too, or BF16 operands with FP32 accumulation
 //    (v_mfma_f32_16x16x16_bf16) in the BF16-H precision.  M is stored in MFMA
-//    fragment order, so every wave reads one contiguous block per instruction;
-//    z is formed on the fly
-//    from the predictor staged in LDS and a table of the (i, j) pairs of the
-//    compressed quadratic vector.  K is split over workgroups; each split
-//    writes its own partial tile (no atomics), reduced in a fixed order by the
-//    step kernel.
+//    fragment order, so every wave reads one contiguous block per instruction
+//    and applies it to up to 4 tiles of 16 instances; H's K blocks are padded
+//    per row i of the compressed triangle, so z = q_i q_j is formed on the fly
+//    from the predictor staged in LDS with a wave-uniform (i, j0) per block.
+//    K is split over workgroups; each split writes its own partial tile (no
+//    atomics), reduced in a fixed order by the step kernel.
 //  * rom_ghat_kernel: g^ = Phi_S^T s over the faces fed by FOM neighbours, split
 //    over the face DOFs, FP64 partial sums per split.
 #include <hip/hip_ext.h>
@@ -35,78 +35,139 @@ __device__ __forceinline__ short to_bf16(float x) {
 }
 
 constexpr int kPreThreads = 256;
+constexpr int kPreUnroll = 8;   // K blocks per wave and round; the next round's fragments are in flight
 
-template <int PREC>
-__global__ void __launch_bounds__(kPreThreads) rom_f0_kernel(RomPreArgs P) {
-  const int it = blockIdx.y;
-  const int rt = blockIdx.x % P.nrt, ksi = blockIdx.x / P.nrt;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  extern __shared__ float q1s[];   // [16][r]: the predictor of the tile's instances
-  __shared__ f4_t red[4][64];
+// Fragments of the K blocks kb = base, base + 4, ... (wave-strided) of one
+// round, A blocks (HP = false) or H blocks (HP = true); indices past the range
+// are clamped into it (their products are never accumulated), so every load is
+// issued without a branch and stays in flight while the previous round computes.
+template <int PREC, bool HP>
+struct Frags {
+  float a[kPreUnroll];    // FP32 operand (A blocks; H blocks when PREC == 0)
+  s4_t h[kPreUnroll];     // BF16 operand (H blocks when PREC == 1)
+  int ij[kPreUnroll];     // H block: row i of the triangle | first column j0 << 16
+};
 
-  // only when some instance of the tile starts a step
-  bool need = false;
-  if (tid < 16) {
-    const int b = it * 16 + tid;
-    if (b < P.batch) {
-      const Status &S = P.status[b];
-      need = !(S.flags & kFinished) && S.iter == 0;
+template <int PREC, bool HP>
+__device__ __forceinline__ void load_frags(const RomPreArgs &P, int rt, int base, int hi, int lane,
+                                           Frags<PREC, HP> &F) {
+#pragma unroll
+  for (int u = 0; u < kPreUnroll; ++u) {
+    const int kb = min(base + 4 * u, hi - 1);   // wave-uniform
+    if (!HP) {
+      F.a[u] = P.frag_a[((long long)rt * P.nkba + kb) * 64 + lane];
+    } else {
+      const int kh = kb - P.nkba;
+      F.ij[u] = P.blocks[kh];
+      if (PREC == 0) F.a[u] = reinterpret_cast<const float *>(P.frag_h)[((long long)rt * P.nkbh + kh) * 64 + lane];
+      else F.h[u] = reinterpret_cast<const s4_t *>(P.frag_h)[((long long)rt * P.nkbh + kh) * 64 + lane];
     }
   }
+}
+
+// acc[n] += M[rows of tile rt][K blocks lo .. hi-1 of this wave] z[.., tile n]
+template <int PREC, int NI, bool HP>
+__device__ __forceinline__ void mfma_range(const RomPreArgs &P, const float *q1s, int rt, int lo, int hi, int wid,
+                                           int lane, f4_t (&acc)[NI]) {
+  const int r = P.r, col = lane & 15, g4 = lane >> 4;
+  if (lo + wid >= hi) return;
+  Frags<PREC, HP> cur, nxt;
+  load_frags<PREC, HP>(P, rt, lo + wid, hi, lane, nxt);
+  for (int base = lo + wid; base < hi; base += 4 * kPreUnroll) {
+    cur = nxt;
+    if (base + 4 * kPreUnroll < hi) load_frags<PREC, HP>(P, rt, base + 4 * kPreUnroll, hi, lane, nxt);
+#pragma unroll
+    for (int u = 0; u < kPreUnroll; ++u) {
+      const int kb = base + 4 * u;
+      if (kb >= hi) break;
+      if (!HP) {   // linear part, FP32 operands
+        const int k = kb * 4 + g4;
+#pragma unroll
+        for (int n = 0; n < NI; ++n) {
+          const float z = k < r ? q1s[(n * 16 + col) * r + min(k, r - 1)] : 0.f;
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.a[u], z, acc[n], 0, 0, 0);
+        }
+      } else {
+        const int i = cur.ij[u] & 0xffff, j0 = cur.ij[u] >> 16;
+#pragma unroll
+        for (int n = 0; n < NI; ++n) {
+          const float *qc = q1s + (n * 16 + col) * r;
+          const float qi = qc[i];
+          if (PREC == 0) {
+            const int j = j0 + g4;
+            const float z = j < r ? qi * qc[min(j, r - 1)] : 0.f;
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.a[u], z, acc[n], 0, 0, 0);
+          } else {
+            s4_t z;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              const int j = j0 + 4 * g4 + jj;
+              z[jj] = to_bf16(j < r ? qi * qc[min(j, r - 1)] : 0.f);
+            }
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(cur.h[u], z, acc[n], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Grid (row tiles x K splits, instance groups of NI tiles of 16).  Every wave
+// takes every fourth K block of its split and applies each fragment of M to
+// the NI instance tiles; K block kb of H covers columns j0 .. j0 + 3 (FP32) or
+// j0 .. j0 + 15 (BF16) of row i of the triangle (rows padded to whole blocks),
+// so z = q_i q_j needs no per-lane index table.
+template <int PREC, int NI>
+__global__ void __launch_bounds__(kPreThreads) rom_f0_kernel(RomPreArgs P) {
+  const int b0 = blockIdx.y * NI * 16;
+  const int rt = blockIdx.x % P.nrt, ksi = blockIdx.x / P.nrt;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  extern __shared__ float q1s[];   // [NI * 16][r]: the predictor of the group's instances
+  __shared__ int start[NI * 16];   // instance starts a step: its f0 partials are written
+
+  // this group's status (loads in flight during the staging below)
+  int flags = kFinished, iter = 1;
+  if (tid < NI * 16 && b0 + tid < P.batch) {
+    const Status &S = P.status[b0 + tid];
+    flags = S.flags;
+    iter = S.iter;
+  }
+  // the group's predictors are contiguous ([batch rounded up to 64][r], 16-byte aligned)
+  const int r = P.r, n4 = NI * 4 * r;
+  const float4 *qp = reinterpret_cast<const float4 *>(P.qpred + (long long)b0 * r);
+#pragma unroll 8
+  for (int i4 = tid; i4 < n4; i4 += kPreThreads) reinterpret_cast<float4 *>(q1s)[i4] = qp[i4];
+  // only when some instance of the group starts a step
+  const bool need = tid < NI * 16 && !(flags & kFinished) && iter == 0;
+  if (tid < NI * 16) start[tid] = need;
   if (!__syncthreads_or(need)) return;
 
-  const int r = P.r;
-  for (int e = tid; e < 16 * r; e += kPreThreads) {
-    const int bl = e / r, k = e - bl * r;
-    const int b = min(it * 16 + bl, P.batch - 1);
-    const int s2 = (int)(P.status[b].step % 2);
-    const long long o = (long long)b * r + k;
-    q1s[e] = newmark_pred<float>(P.q[s2][o], P.qd[s2][o], P.qdd[s2][o], P.dt, P.half_dt2);
-  }
-  __syncthreads();
-
-  // this split's K blocks (A blocks first, then H blocks), round robin over the waves
   const int nkb = P.nkba + P.nkbh;
   const int per = (nkb + P.ks - 1) / P.ks;
   const int kb0 = ksi * per, kb1 = min(nkb, kb0 + per);
-  const int col = lane & 15, grp = lane >> 4;
-  const float *qc = q1s + col * r;
-  f4_t acc = {0.f, 0.f, 0.f, 0.f};
-  auto quad = [&](int m) -> float {   // (q (x) q)[m] of instance col
-    if (m >= P.r2) return 0.f;
-    const int pr = P.pairs[m];
-    return qc[pr & 0xffff] * qc[pr >> 16];
-  };
-  for (int kb = kb0 + wid; kb < kb1; kb += 4) {
-    if (kb < P.nkba) {   // linear part, FP32 operands
-      const float a = P.frag_a[((long long)rt * P.nkba + kb) * 64 + lane];
-      const int k = kb * 4 + grp;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, k < r ? qc[k] : 0.f, acc, 0, 0, 0);
-    } else if (PREC == 0) {
-      const int kh = kb - P.nkba;
-      const float a = reinterpret_cast<const float *>(P.frag_h)[((long long)rt * P.nkbh + kh) * 64 + lane];
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, quad(kh * 4 + grp), acc, 0, 0, 0);
-    } else {
-      const int kh = kb - P.nkba;
-      const s4_t a = reinterpret_cast<const s4_t *>(P.frag_h)[((long long)rt * P.nkbh + kh) * 64 + lane];
-      s4_t z;
+  const int col = lane & 15, g4 = lane >> 4;
+  f4_t acc[NI];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) z[j] = to_bf16(quad(kh * 16 + 4 * grp + j));
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, z, acc, 0, 0, 0);
-    }
-  }
-  red[wid][lane] = acc;
+  for (int n = 0; n < NI; ++n) acc[n] = f4_t{0.f, 0.f, 0.f, 0.f};
+  mfma_range<PREC, NI, false>(P, q1s, rt, kb0, min(kb1, P.nkba), wid, lane, acc);   // A blocks
+  mfma_range<PREC, NI, true>(P, q1s, rt, max(kb0, P.nkba), kb1, wid, lane, acc);    // H blocks
+  __syncthreads();   // the predictor is no longer read: its LDS takes the wave sums
+  f4_t *red = reinterpret_cast<f4_t *>(q1s);   // [4 waves][NI][64]
+#pragma unroll
+  for (int n = 0; n < NI; ++n) red[(wid * NI + n) * 64 + lane] = acc[n];
   __syncthreads();
-  if (wid == 0) {
-    f4_t t = red[0][lane];
+  if (wid < NI) {
+    const int n = wid;
+    f4_t t = red[n * 64 + lane];
 #pragma unroll
-    for (int w = 1; w < 4; ++w) t += red[w][lane];
+    for (int w = 1; w < 4; ++w) t += red[(w * NI + n) * 64 + lane];
     // result register i of lane l: row 4 (l / 16) + i, column (instance) l % 16
-    const int b = it * 16 + col;
-    if (b < P.batch) {
+    const int b = b0 + n * 16 + col;
+    if (b < P.batch && start[n * 16 + col]) {   // instances within a step keep their f0
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = rt * 16 + 4 * grp + i;
+        const int row = rt * 16 + 4 * g4 + i;
         if (row < r) {
           float v = t[i];
           if (ksi == 0 && P.c) v += P.c[row];
@@ -115,6 +176,11 @@ __global__ void __launch_bounds__(kPreThreads) rom_f0_kernel(RomPreArgs P) {
       }
     }
   }
+}
+
+size_t rom_f0_smem_bytes(int r, int ni) {
+  const size_t q = sizeof(float) * 16 * (size_t)ni * r, red = sizeof(f4_t) * 4 * (size_t)ni * 64;
+  return q > red ? q : red;
 }
 
 // grid (gs, batch): workgroup (split, instance) sums its slice of the FOM-fed
@@ -159,12 +225,21 @@ __global__ void __launch_bounds__(kPreThreads) rom_ghat_kernel(RomPreArgs P) {
   }
 }
 
+template <int PREC>
+static void launch_f0(const RomPreArgs &P, dim3 grid, size_t smem, hipStream_t s) {
+  if (P.ni == 4) hipLaunchKernelGGL((rom_f0_kernel<PREC, 4>), grid, dim3(kPreThreads), smem, s, P);
+  else if (P.ni == 2) hipLaunchKernelGGL((rom_f0_kernel<PREC, 2>), grid, dim3(kPreThreads), smem, s, P);
+  else hipLaunchKernelGGL((rom_f0_kernel<PREC, 1>), grid, dim3(kPreThreads), smem, s, P);
+}
+
 hipError_t launch_rom_pre(const RomPreArgs &P, hipStream_t s) {
   if (P.nkba + P.nkbh > 0) {
-    const dim3 grid(P.nrt * P.ks, P.nit);
-    const size_t smem = sizeof(float) * 16 * (size_t)P.r;
-    if (P.prec == 0) hipLaunchKernelGGL(rom_f0_kernel<0>, grid, dim3(kPreThreads), smem, s, P);
-    else hipLaunchKernelGGL(rom_f0_kernel<1>, grid, dim3(kPreThreads), smem, s, P);
+    if (!(P.ni == 1 || P.ni == 2 || P.ni == 4) || P.ni * 4 * P.r > 16 * kPreThreads) return hipErrorInvalidValue;
+    const size_t smem = rom_f0_smem_bytes(P.r, P.ni);
+    if (smem > 65536) return hipErrorInvalidValue;
+    const dim3 grid(P.nrt * P.ks, (P.nit + P.ni - 1) / P.ni);
+    if (P.prec == 0) launch_f0<0>(P, grid, smem, s);
+    else launch_f0<1>(P, grid, smem, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -59,12 +59,13 @@ struct Subdomain {
   bool pre = false;                // batched path wired
   float *pre_fa = nullptr;         // A in MFMA fragment order (FP32)
   void *pre_fh = nullptr;          // H in MFMA fragment order (FP32 or BF16)
-  int *pre_pairs = nullptr;        // compressed quadratic index -> i | j << 16
+  int *pre_blocks = nullptr;       // H K block -> row i of the triangle | first column j0 << 16
   float *pre_f0 = nullptr;         // [ks][batch][r]
   double *pre_g = nullptr;         // [gs][batch][rs]
-  int pre_prec = 0, pre_nkba = 0, pre_nkbh = 0, pre_nrt = 0, pre_ks = 1, pre_gs = 1;
+  int pre_prec = 0, pre_nkba = 0, pre_nkbh = 0, pre_nrt = 0, pre_ks = 1, pre_gs = 1, pre_ni = 1;
   void *d_Phi = nullptr;           // [r][nfree] column-major
   void *q[2] = {}, *qd[2] = {}, *qdd[2] = {};
+  void *qpred = nullptr;           // [batch][r]: Newmark predictor of the latest state (next step's q(t_k))
   void *face_phis[2] = {};         // [rs][3 npl] Phi_S block per Schwarz face
   void *face_tm[2] = {};           // [rs][r_src] for ROM sources
   void *sface[2][3] = {};          // OpInf: pushed face values by role, [batch][3 npl] (FOM source)
