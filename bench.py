@@ -11,7 +11,9 @@ the multiplicative Schwarz loop).  value = controller steps per second.
 Learning and the training run are set-up (timed separately, reported).
 Also reported: the FOM-FOM run of the same bar on the same GPU, the accuracy of
 the hybrid against it (Eq. mse), FE DOF-updates/s, the FE kernel's achieved
-bandwidth vs the HBM peak, and the FP64 CPU oracle timed on a bounded sample.
+bandwidth vs the HBM peak (of the fused sweep kernel when the autotuner picks fused
+sweeps: FE step and OpInf step in one launch), and the FP64 CPU oracle timed on a
+bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -148,17 +150,37 @@ def main():
     fe_dofs = z0["n_free"]
     dof_updates_per_s = fe_dofs * iters / times[-1]
 
-    # ---- FE kernel timing with HIP events (same workload, extra pass) ----
+    # ---- dominant kernel timing with HIP events (same workload and launch configuration,
+    # extra pass): the fused sweep kernel when the tuner chose fused sweeps, else the FE kernel
+    from paper_2511_20687_amd.profiling import read_traffic, rom_bytes_per_launch
+    fused = tuning.get("fusion_kc", 0) > 0
     ctx.set_initial(0, u0, v0)
     ctx.set_timing(True)
     ctx.run(n, opts)
-    fe_ms, fe_launches = ctx.get_timing(0)
+    k_ms, k_launches = ctx.get_timing(0)      # fused: the sweep kernel, reported for every subdomain
     rom_ms, rom_launches = ctx.get_timing(1)
     ctx.set_timing(False)
-    fe_avg_us = 1e3 * fe_ms / max(fe_launches, 1)
-    fe_gbs = FE_BYTES_PER_DOF * fe_dofs / (fe_avg_us * 1e-6) / 1e9
-    from paper_2511_20687_amd.profiling import read_traffic
-    traffic_bytes, traffic_src = read_traffic()
+    k_avg_us = 1e3 * k_ms / max(k_launches, 1)
+    face = 3 * (w.bar.nx + 1) * (w.bar.ny + 1)      # DOFs of one Schwarz face (each way)
+    rom_alg = rom_bytes_per_launch(learned["r"], learned["r_s"], face, face)
+    fe_alg = FE_BYTES_PER_DOF * fe_dofs
+    alg_bytes = fe_alg + rom_alg if fused else fe_alg
+    k_gbs = alg_bytes / (k_avg_us * 1e-6) / 1e9
+    traffic_bytes, traffic_src = read_traffic("bar24_sweep" if fused else "bar24")
+    # the FE kernel alone (one launch per subdomain), for reference
+    fe_avg_us = None
+    if fused:
+        ctx.set_fusion(False)
+        ctx.set_initial(0, u0, v0)
+        ctx.set_timing(True)
+        ctx.run(n, opts)
+        fe_ms, fe_launches = ctx.get_timing(0)
+        rom_ms, rom_launches = ctx.get_timing(1)
+        ctx.set_timing(False)
+        ctx.set_fusion(True, tuning["fusion_kc"])
+        fe_avg_us = 1e3 * fe_ms / max(fe_launches, 1)
+    else:
+        fe_avg_us = k_avg_us
 
     # ---- accuracy vs FOM-FOM and FOM-FOM throughput on the same GPU ----
     every = 10
@@ -247,17 +269,22 @@ def main():
         "fe_dof_updates_per_s": dof_updates_per_s,
         "fe_kernel_avg_us": fe_avg_us,
         "rom_kernel_avg_us": 1e3 * rom_ms / max(rom_launches, 1),
+        "sweep_kernel_avg_us": k_avg_us if fused else None,
         "train_run_s": t_train,
         "learn_s": t_learn,
         "launch": {"hybrid": tuning, "fom_fom": ff_tuning, "autotune_s": t_tune},
-        "roofline": {"bound": "hbm", "achieved": fe_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fe_gbs / HBM_PEAK_GBS, "traffic": traffic_bytes,
+        "roofline": {"bound": "hbm", "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": k_gbs / HBM_PEAK_GBS, "traffic": traffic_bytes,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
-                     "kernel": ("fe_lds_kernel<step> + boundary fe_kernel<float, step>" if tuning["fe"][0][0] == 1024
-                                else "fe_kernel<float, step>"),
-                     "launch_shape": tuning["fe"][0], "bytes_per_dof": FE_BYTES_PER_DOF,
-                     "dofs_per_launch": fe_dofs, "algorithmic_bytes_per_launch": FE_BYTES_PER_DOF * fe_dofs},
+                     "kernel": ("sweep_kernel<float, 1, 0> (FE step + OpInf step in one launch)" if fused
+                                else "fe_lds_kernel<step> + boundary fe_kernel<float, step>"
+                                if tuning["fe"][0][0] == 1024 else "fe_kernel<float, step>"),
+                     "kernel_avg_us": k_avg_us,
+                     "launch_shape": ([512, tuning["fusion_kc"]] if fused else tuning["fe"][0]),
+                     "bytes_per_dof": FE_BYTES_PER_DOF, "dofs_per_launch": fe_dofs,
+                     "algorithmic_bytes_per_launch": alg_bytes, "fe_bytes_per_launch": fe_alg,
+                     "rom_bytes_per_launch": rom_alg if fused else None},
         "cpu_baseline": cpu,
         "batched_opinf_opinf": batched,
         "adjoint": adjoint,

@@ -1,11 +1,12 @@
-"""Profiling helpers for the FE step kernel on the 24x24x240 bar (FOM-OpInf coupling).
+"""Profiling helpers for the FE step kernel and the fused sweep kernel on the 24x24x240 bar
+(FOM-OpInf coupling).
 
 Used under rocprofv3 to produce the summaries in profiles/:
 
-    python -m paper_2511_20687_amd.profiling workload [steps]   # coupled run, synthetic r=40 OpInf
+    python -m paper_2511_20687_amd.profiling workload [steps [fused]]  # coupled run, synthetic r=40 OpInf
     python -m paper_2511_20687_amd.profiling large [steps [block kc]]  # 64x64x640, OpInf-FOM-OpInf, B=16
     python -m paper_2511_20687_amd.profiling copy               # plain copy of 256 MiB (calibration)
-    python -m paper_2511_20687_amd.profiling summarize OUTDIR [bar24|bar64]   # counters -> profiles/*.txt
+    python -m paper_2511_20687_amd.profiling summarize OUTDIR [bar24|bar64|bar24_sweep]   # counters -> profiles/*.txt
 
 The workload runs exactly the FE kernel work of the bench (same subdomain, launch shape and
 coupling pattern); the OpInf operators are seeded synthetic ones of the learned sizes, so no
@@ -24,18 +25,30 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 256 << 20
-FE_SOURCES = ("paper_2511_20687_amd/csrc/fe_kernels.hip", "paper_2511_20687_amd/csrc/osam_device.hpp")
+_CSRC = "paper_2511_20687_amd/csrc/"
+SOURCES = {   # the sources each profiled kernel is built from
+    "fe": tuple(_CSRC + f for f in ("fe_kernels.hip", "fe_body.hpp", "stencil.hpp", "osam_device.hpp")),
+    "sweep": tuple(_CSRC + f for f in ("sweep_kernels.hip", "fe_body.hpp", "rom_body.hpp", "stencil.hpp",
+                                       "osam_device.hpp")),
+}
 
 
-def fe_source_hash() -> str:
+def source_hash(kernel: str = "fe") -> str:
     h = hashlib.sha256()
-    for rel in FE_SOURCES:
+    for rel in SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def workload(steps: int = 200) -> None:
+def rom_bytes_per_launch(r: int, rs: int, n_in: int, n_exp: int) -> float:
+    """FP32 algorithmic bytes of one OpInf step launch (fused path, one instance): A, B,
+    the Phi_S block and values of the FOM-fed face, the Pi Phi rows and values of the push,
+    and the reduced state (3 r read, 3 r written)."""
+    return 4.0 * (r * r + r * rs + rs * n_in + n_in + r * n_exp + n_exp + 6 * r)
+
+
+def workload(steps: int = 200, fused: bool = False) -> None:
     import torch
     from paper_2511_20687_amd import osam
     from paper_2511_20687_amd.inputs import CFG2, draw_pulses, synthetic_rom
@@ -47,10 +60,12 @@ def workload(steps: int = 200) -> None:
     ctx.set_opinf(1, R["Phi"], R["PhiS"], R["A"], None, R["B"])
     u0 = draw_pulses(w.seed, 1, s=w.pulse_width)[0].u0(w.bar)
     ctx.set_initial(0, u0, np.zeros_like(u0))
+    if fused:
+        ctx.set_fusion(True, 1)
     info = ctx.run(steps, osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel))
     torch.cuda.synchronize()
-    print(f"workload done: {steps} steps, {info[0]['total_iters']} Schwarz iterations, "
-          f"{z['n_free']} FE DOFs", flush=True)
+    print(f"workload done: {steps} steps{' (fused sweeps)' if fused else ''}, {info[0]['total_iters']} "
+          f"Schwarz iterations, {z['n_free']} FE DOFs", flush=True)
 
 
 def large_context(steps: int = 0):
@@ -121,19 +136,28 @@ def _mean_counter(rows, name_part, counter):
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
 
 
+# the fused sweep of the 24x24x240 workload: FE step of Omega_1 plus the OpInf step
+# (r = 40, r_S = 1, one FOM-fed face and one push face of 3 x 625 DOFs)
+_SWEEP24_BYTES = 28 * 268125 + rom_bytes_per_launch(40, 1, 1875, 1875)
+
 CASES = {
-    # name: (subdirectory prefix, kernel name filter, FE DOFs per launch, summary file, title)
-    "bar24": ("", "fe_kernel<float, 0", 268125, "fe_kernel_bar24x24x240_traffic.txt",
-              "24x24x240 bar, Omega_1 268125 FE DOFs, FP32, launch 256 threads x 1 layer"),
-    "bar64": ("large_", "fe_kernel<float, 0", 16 * 4322175, "fe_kernel_bar64x64x640_b16_traffic.txt",
-              "64x64x640 bar, middle FOM subdomain 4322175 FE DOFs x 16 instances, FP32, launch 64 threads x 8 layers"),
+    # name: (subdirectory prefix, kernel name filter, algorithmic bytes per launch, summary file,
+    #        source set, title)
+    "bar24": ("", "fe_kernel<float, 0", 28 * 268125, "fe_kernel_bar24x24x240_traffic.txt", "fe",
+              "FE step kernel, 24x24x240 bar, Omega_1 268125 FE DOFs, FP32, launch 256 threads x 1 layer"),
+    "bar64": ("large_", "fe_kernel<float, 0", 28 * 16 * 4322175, "fe_kernel_bar64x64x640_b16_traffic.txt", "fe",
+              "FE step kernel, 64x64x640 bar, middle FOM subdomain 4322175 FE DOFs x 16 instances, FP32, "
+              "launch 64 threads x 8 layers"),
+    "bar24_sweep": ("sweep_", "sweep_kernel<float, 1", _SWEEP24_BYTES, "sweep_kernel_bar24x24x240_traffic.txt",
+                    "sweep", "fused sweep kernel (FE step of Omega_1, 268125 FE DOFs, + OpInf step r=40), "
+                    "24x24x240 bar, FP32, 512 threads x 1 layer"),
 }
 
 
 def summarize(outdir: str, case: str = "bar24") -> None:
     """outdir holds the rocprofv3 results of the passes fetch_copy, write_copy and
     <prefix>fetch_fe, <prefix>write_fe of the case."""
-    prefix, kname, dofs, fname, title = CASES[case]
+    prefix, kname, alg_bytes, fname, kernel, title = CASES[case]
     get = lambda sub: _counter_rows(os.path.join(outdir, sub))
     fc, nfc = _mean_counter(get("fetch_copy"), "copy", "FETCH_SIZE")
     wc, nwc = _mean_counter(get("write_copy"), "copy", "WRITE_SIZE")
@@ -144,20 +168,32 @@ def summarize(outdir: str, case: str = "bar24") -> None:
     sw = kib / wc if wc else None
     fetch_b = ff * sf * 1024 if (ff and sf) else None
     write_b = wf * sw * 1024 if (wf and sw) else None
+    args = {"bar24": "workload 100", "bar24_sweep": "workload 100 fused", "bar64": "large 4 64 8"}[case]
     lines = [
-        f"# FE step kernel HBM traffic (rocprofv3 --pmc), {title}",
-        f"kernel_source_sha256_16={fe_source_hash()}",
+        f"# HBM traffic (rocprofv3 --pmc), {title}",
+        "# commands, from the repository root after `cd /tmp && export TMPDIR=/tmp` (OUT: an output folder):",
+        "#   timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch_copy -o run -- "
+        "python3 -m paper_2511_20687_amd.profiling copy",
+        "#   timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write_copy -o run -- "
+        "python3 -m paper_2511_20687_amd.profiling copy",
+        f"#   timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/{prefix}fetch_fe -o run -- "
+        f"python3 -m paper_2511_20687_amd.profiling {args}",
+        f"#   timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/{prefix}write_fe -o run -- "
+        f"python3 -m paper_2511_20687_amd.profiling {args}",
+        f"#   python3 -m paper_2511_20687_amd.profiling summarize OUT {case}",
+        "# scale = known bytes of the copy / its counted KiB; traffic = counted KiB x scale, per launch",
+        f"kernel_source_sha256_16={source_hash(kernel)}",
         f"copy_bytes={COPY_BYTES}",
         f"copy_fetch_kib_per_dispatch={fc} (n={nfc})",
         f"copy_write_kib_per_dispatch={wc} (n={nwc})",
         f"fetch_scale={sf}",
         f"write_scale={sw}",
-        f"fe_fetch_kib_per_dispatch={ff} (n={nff})",
-        f"fe_write_kib_per_dispatch={wf} (n={nwf})",
-        f"fe_fetch_bytes_per_launch={fetch_b}",
-        f"fe_write_bytes_per_launch={write_b}",
-        f"fe_traffic_bytes_per_launch={None if fetch_b is None or write_b is None else fetch_b + write_b}",
-        "algorithmic_bytes_per_launch=" + str(28 * dofs),
+        f"kernel_fetch_kib_per_dispatch={ff} (n={nff})",
+        f"kernel_write_kib_per_dispatch={wf} (n={nwf})",
+        f"kernel_fetch_bytes_per_launch={fetch_b}",
+        f"kernel_write_bytes_per_launch={write_b}",
+        f"kernel_traffic_bytes_per_launch={None if fetch_b is None or write_b is None else fetch_b + write_b}",
+        f"algorithmic_bytes_per_launch={alg_bytes:.0f}",
     ]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     path = os.path.join(ROOT, "profiles", fname)
@@ -166,10 +202,11 @@ def summarize(outdir: str, case: str = "bar24") -> None:
     print("\n".join(lines))
 
 
-def read_traffic():
-    """(traffic bytes per FE launch, details) from the committed summary, or (None, reason)
-    when it is missing or was taken for another version of the FE kernel source."""
-    path = os.path.join(ROOT, "profiles", "fe_kernel_bar24x24x240_traffic.txt")
+def read_traffic(case: str = "bar24"):
+    """(traffic bytes per launch, details) from the committed summary of a case, or (None,
+    reason) when it is missing or was taken for another version of the kernel's sources."""
+    _, _, _, fname, kernel, _ = CASES[case]
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None, "no PMC summary"
     kv = {}
@@ -177,10 +214,10 @@ def read_traffic():
         if "=" in line and not line.startswith("#"):
             k, v = line.strip().split("=", 1)
             kv[k] = v.split(" ")[0]
-    if kv.get("kernel_source_sha256_16") != fe_source_hash():
-        return None, "FE kernel changed since the counters were taken"
+    if kv.get("kernel_source_sha256_16") != source_hash(kernel):
+        return None, "kernel sources changed since the counters were taken"
     try:
-        return float(kv["fe_traffic_bytes_per_launch"]), path
+        return float(kv["kernel_traffic_bytes_per_launch"]), path
     except (KeyError, ValueError):
         return None, "incomplete PMC summary"
 
@@ -188,7 +225,7 @@ def read_traffic():
 if __name__ == "__main__":
     cmd = sys.argv[1] if len(sys.argv) > 1 else "workload"
     if cmd == "workload":
-        workload(int(sys.argv[2]) if len(sys.argv) > 2 else 200)
+        workload(int(sys.argv[2]) if len(sys.argv) > 2 else 200, len(sys.argv) > 3 and sys.argv[3] == "fused")
     elif cmd == "large":
         a = [int(x) for x in sys.argv[2:5]]
         large(*a)
