@@ -340,7 +340,7 @@ int32_t osam_set_fusion(osam_ctx *ctx, int32_t enable, int32_t kc);
  * where it applies, the layer-staged 1024 with 4, 8, 16 layers), the OpInf
  * path of each OpInf subdomain of an FP32 context (osam_set_rom_path 1 or 2)
  * the launch mode (osam_set_graph: none, 32 or 128 sweeps on one stream,
- * 32 on two) and sweep fusion (osam_set_fusion with 1 or 4 layers per thread,
+ * 32 on two) and sweep fusion (osam_set_fusion with 1, 2 or 4 layers per thread,
  * host launches or graphs of 32 or 128 sweeps).  None of these changes results.  The choice is cached for the
  * process per configuration (precision, batch, subdomain and reduced sizes) and
  * applied without trials on a later call (from_cache = 1).  The trials advance

@@ -43,12 +43,18 @@ double *Ctx::scratch(size_t n, int32_t *st) {
   return d_scratch;
 }
 
-// Launch shape of the FE kernel: columns x z-chunks x instances.  block/kc = 0
-// selects the default (256 threads, one layer per thread).
+// Launch shape of the FE kernel: column groups x z-chunks x instances.  block/kc
+// = 0 selects the default (256 threads, one layer per thread).  The column
+// kernel packs waves: a chunk of layers is ceil(n_int / 64) interior and
+// ceil(n_bnd / 64) boundary groups of 64 columns, one wave each.
+static int fe_waves(const Subdomain &s, int kc) {
+  const int nl = s.nzs - 1;
+  return ((s.n_int + 63) / 64 + (s.n_bnd + 63) / 64) * ((nl + kc - 1) / kc);
+}
+
 bool Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
   const int nl = s.nzs - 1;
-  auto per_chunk = [&](int b) { return (s.n_int + b - 1) / b + (s.n_bnd + b - 1) / b; };
-  s.max_nblocks = std::max(s.max_nblocks, per_chunk(64) * nl);
+  s.max_nblocks = std::max(s.max_nblocks, fe_waves(s, 1) + nl);   // bound on the workgroups of any shape
   if (block == 1024) {
     // layer-staged interior + column kernel for the boundary (FP32, cross-section fits the LDS)
     if (prec == OSAM_FP64 || s.npl > kFeLdsMaxNodes) return false;
@@ -57,8 +63,7 @@ bool Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
     s.fe_block = 1024;
     s.fe_kc = kc;
     s.fe_chunks = (nl + kc - 1) / kc;
-    s.fe_int_blocks = 0;
-    s.fe_nblocks = s.fe_chunks + (s.n_bnd / 64) * nl;
+    s.fe_nblocks = s.fe_chunks + (s.n_bnd + 63) / 64 * nl;
     return true;
   }
   int bs = block > 0 ? block : 256;
@@ -67,8 +72,7 @@ bool Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
   s.fe_block = bs;
   s.fe_kc = kc;
   s.fe_chunks = (nl + kc - 1) / kc;
-  s.fe_int_blocks = (s.n_int + bs - 1) / bs;
-  s.fe_nblocks = per_chunk(bs) * s.fe_chunks;
+  s.fe_nblocks = (fe_waves(s, kc) + bs / 64 - 1) / (bs / 64);
   return true;
 }
 
@@ -326,11 +330,22 @@ int32_t Ctx::wire() {
     Subdomain &s = *sds[j];
     if (!s.rom) continue;
     s.piphi_d.clear();
+    s.piphi_rm.clear();
+    const int r4 = (s.r + 3) / 4 * 4;
     for (auto &pp : s.piphi_h) {
       void *p = alloc_t(pp.size(), &st);
       if (st) return fail(st, "oom");
       if ((st = upload(p, pp.data(), pp.size()))) return st;
       s.piphi_d.push_back(p);
+      // row-major copy [n][r4] (zero-padded): one thread's row in 16-byte loads
+      const size_t n = pp.size() / (size_t)s.r;
+      std::vector<double> rm(n * r4, 0.0);
+      for (size_t m = 0; m < n; ++m)
+        for (int k = 0; k < s.r; ++k) rm[m * r4 + k] = pp[(size_t)k * n + m];
+      void *q = alloc_t(rm.size(), &st);
+      if (st) return fail(st, "oom");
+      if ((st = upload(q, rm.data(), rm.size()))) return st;
+      s.piphi_rm.push_back(q);
     }
   }
   // FOM state buffers only for FOM subdomains
@@ -623,7 +638,6 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.n_chunks = s.fe_chunks;
   A.n_int = s.n_int;
   A.n_bnd = s.n_bnd;
-  A.int_blocks = s.fe_int_blocks;
   A.nblocks = s.fe_nblocks;
   A.part_stride = s.fe_nblocks;
   A.part_off = 0;
@@ -659,8 +673,8 @@ int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0, hipE
         const int nl = s.nzs - 1;
         Ab.kc = 1;
         Ab.n_chunks = nl;
-        Ab.int_blocks = 0;
-        Ab.nblocks = (s.n_bnd / 64) * nl;
+        Ab.n_int = 0;   // boundary groups only
+        Ab.nblocks = (s.n_bnd + 63) / 64 * nl;
         Ab.part_off = s.fe_chunks;
         e = launch_fe<float>(Ab, batch, 64, mode, stream, nullptr, ev1);
       }
@@ -742,7 +756,8 @@ static void fill_rom_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, RomArgs<
       E.cs = fd.cs;
       E.is = fd.is;
       E.npl = fd.npl;
-      E.piphi = (const T *)s.piphi_d[ne];
+      E.prow = (const T *)s.piphi_rm[ne];
+      E.r4 = (s.r + 3) / 4 * 4;
       ++ne;
     }
   }
@@ -883,11 +898,10 @@ int32_t Ctx::launch_round_concurrent(const Opts &o) {
 // Fused sweeps.  Every FOM step runs as the column kernel with 512-thread
 // workgroups (the OpInf step's workgroup size), fuse_kc layers per thread.
 void Ctx::fuse_layout(Subdomain &s) {
-  const int nl = s.nzs - 1, bs = 512;
+  const int nl = s.nzs - 1;
   s.fz_kc = std::max(1, std::min(fuse_kc, nl));
   s.fz_chunks = (nl + s.fz_kc - 1) / s.fz_kc;
-  s.fz_int_blocks = (s.n_int + bs - 1) / bs;
-  s.fz_nblocks = (s.fz_int_blocks + (s.n_bnd + bs - 1) / bs) * s.fz_chunks;   // <= max_nblocks
+  s.fz_nblocks = (fe_waves(s, s.fz_kc) + 7) / 8;   // 8 waves per workgroup; <= max_nblocks
 }
 
 std::string Ctx::fusion_unsupported() const {
@@ -931,7 +945,6 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
       fill_fe_args<T>(c, d, i, o, A);
       A.kc = d.fz_kc;
       A.n_chunks = d.fz_chunks;
-      A.int_blocks = d.fz_int_blocks;
       A.nblocks = d.fz_nblocks;
       A.part_stride = d.fz_nblocks;
       A.part_off = 0;

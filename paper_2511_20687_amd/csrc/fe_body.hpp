@@ -12,11 +12,7 @@ namespace osam {
 constexpr int kModeStep = 0;
 constexpr int kModeInit = 1;
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
+__device__ __forceinline__ double wave_sum(double x) { return wave_total(x); }
 
 // Per-thread view of one instance's buffers in the roles of its current step.
 template <typename T>
@@ -252,14 +248,16 @@ __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
 
   double acc_abs = 0.0, acc_den = 0.0;
   const int bx = xcd_block(xblk, A.nblocks);
-  if (bx < A.int_blocks * A.n_chunks) {
-    const int t = (bx % A.int_blocks) * blockDim.x + threadIdx.x;
-    fe_columns<T, MODE, true, ONE>(A, b, t, bx / A.int_blocks, step, iter, acc_abs, acc_den);
-  } else {
-    const int bb = bx - A.int_blocks * A.n_chunks;
-    const int nbb = A.nblocks / A.n_chunks - A.int_blocks;
-    const int t = (bb % nbb) * blockDim.x + threadIdx.x;
-    fe_columns<T, MODE, false, ONE>(A, b, t, bb / nbb, step, iter, acc_abs, acc_den);
+  // work by wave: a layer chunk is wi groups of 64 interior columns then wb groups
+  // of 64 boundary columns (one case per group); wave w of the grid takes group
+  // w % (wi + wb) of chunk w / (wi + wb), so workgroups pack whole groups
+  const int wi = (A.n_int + 63) >> 6, wb = (A.n_bnd + 63) >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(bx * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6));
+  const int chunk = wave / (wi + wb), wc = wave - chunk * (wi + wb);
+  const int lane = threadIdx.x & 63;
+  if (chunk < A.n_chunks) {
+    if (wc < wi) fe_columns<T, MODE, true, ONE>(A, b, wc * 64 + lane, chunk, step, iter, acc_abs, acc_den);
+    else fe_columns<T, MODE, false, ONE>(A, b, (wc - wi) * 64 + lane, chunk, step, iter, acc_abs, acc_den);
   }
   if (MODE == kModeInit) return;
 
@@ -268,7 +266,7 @@ __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
   __shared__ double red[2][16];
   acc_abs = wave_sum(acc_abs);
   acc_den = wave_sum(acc_den);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if (lane == 0) {
     red[0][wid] = acc_abs;
     red[1][wid] = acc_den;

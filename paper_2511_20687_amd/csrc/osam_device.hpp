@@ -90,11 +90,42 @@ struct FinishArgs {
   int rom_sd[kMaxSd];           // OpInf subdomains whose sums are in `out` already
 };
 
-__device__ __forceinline__ double wave_sum64(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+// Sum over the 64 lanes of a wave (every lane active), returned to every lane.
+// An inclusive scan with DPP row shifts (1, 2, 4, 8 within rows of 16) and the
+// row broadcasts of lanes 15 and 31 leaves the total in lane 63; the additions
+// stay in the vector ALU (no LDS permutes), six dependent steps in all.
+template <int CTRL, int ROW, int BANK>
+__device__ __forceinline__ float dpp_src(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW, BANK, true));
 }
+template <int CTRL, int ROW, int BANK>
+__device__ __forceinline__ double dpp_src(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROW, BANK, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROW, BANK, true);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane63(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+}
+__device__ __forceinline__ double lane63(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T wave_total(T x) {
+  x += dpp_src<0x111, 0xf, 0xf>(x);   // row_shr:1
+  x += dpp_src<0x112, 0xf, 0xf>(x);   // row_shr:2
+  x += dpp_src<0x114, 0xf, 0xe>(x);   // row_shr:4, lanes 4..15 of each row
+  x += dpp_src<0x118, 0xf, 0xc>(x);   // row_shr:8, lanes 8..15 of each row
+  x += dpp_src<0x142, 0xa, 0xf>(x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_src<0x143, 0xc, 0xf>(x);   // row_bcast:31 into rows 2 and 3
+  return lane63(x);
+}
+
+__device__ __forceinline__ double wave_sum64(double x) { return wave_total(x); }
 
 // Sums of FOM subdomain k's partials, computed by one wave (lane 0 holds them).
 // Loads are issued in batches of U per lane before any is consumed.
@@ -199,7 +230,7 @@ struct FeArgs {
   Opts opts;
   double *partials;        // [batch][part_stride][2], this launch's workgroups from part_off
   int part_stride, part_off;
-  int kc, n_chunks, n_int, n_bnd, int_blocks, nblocks;
+  int kc, n_chunks, n_int, n_bnd, nblocks;   // nblocks: workgroups of the launch (waves packed, see fe_body)
   const int *bnd_cols;     // boundary columns (ids in the layer)
   // records: [batch][ncols][len]
   T *rec_u, *rec_a, *rec_s;
@@ -237,7 +268,8 @@ struct RomExport {
   T *role[3];              // destination face values by role, at the face start
   long long cs, is;        // destination component / instance strides
   int npl;
-  const T *piphi;          // [r][3 npl] column-major rows of Pi Phi for the face
+  const T *prow;           // [3 npl][r4] row-major rows of Pi Phi for the face, zero-padded
+  int r4;                  // row stride: r rounded up to a multiple of 4 (16-byte rows)
 };
 
 template <typename T>

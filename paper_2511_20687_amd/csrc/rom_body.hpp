@@ -8,17 +8,19 @@
 
 namespace osam {
 
-__device__ __forceinline__ double wave_sum_d(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
+__device__ __forceinline__ double wave_sum_d(double x) { return wave_total(x); }
 
 constexpr int kRomThreads = 512;
 constexpr int kRomWaves = kRomThreads / 64;   // 8
 constexpr int kRowsPerWave = 16;              // rows i = wave + 8 j: r <= 128
 constexpr int kFaceDofs = 4;                  // face DOFs per thread on the fast g^ path
 constexpr int kPushK = 64;                    // modes of the push row held in registers
+
+// 16-byte vectors (push rows are read a row per thread, 16 bytes per load)
+template <typename T>
+constexpr int kVec16 = 16 / (int)sizeof(T);
+template <typename T>
+using Vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
 
 // Sum of NV per-thread values over the workgroup in a fixed order; the totals
 // land in out[0..NV) (LDS) for every thread after the call.
@@ -141,8 +143,13 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     const RomExport<T> &ex = A.ex[0];
     const int n = 3 * ex.npl;
     const long long m = min(g * kRomThreads + tid, n - 1);
+    const Vec16<T> *row = reinterpret_cast<const Vec16<T> *>(ex.prow + m * ex.r4);
 #pragma unroll
-    for (int k = 0; k < kPushK; ++k) pv[k] = k < r ? ex.piphi[(long long)k * n + m] : T(0);
+    for (int j = 0; j < kPushK / kVec16<T>; ++j) {
+      const Vec16<T> v = j * kVec16<T> < r ? row[j] : Vec16<T>(T(0));
+#pragma unroll
+      for (int e = 0; e < kVec16<T>; ++e) pv[j * kVec16<T> + e] = v[e];
+    }
   }
   // the FOM workgroups' partial sums, when this workgroup decides
   bool small_part = !PRE && last && g == 0 && F.nfom <= 2;
@@ -288,8 +295,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     }
     if (lane < rs) s += brow[j] * sh[lane];
     for (int l = 64 + lane; l < rs; l += 64) s += A.B[(long long)i * rs + l] * sh[l];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    s = wave_total(s);
     if (lane == 0) qdd1s[i] += s;
   }
   __syncthreads();
@@ -331,11 +337,16 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
         if (k + 1 < r) acc1 += pv[k + 1] * qps[k + 1];
       }
     }
+    const Vec16<T> *row = reinterpret_cast<const Vec16<T> *>(ex.prow + (long long)min(m, n - 1) * ex.r4);
     for (int k0 = PUSHREG && e == 0 ? kPushK : 0; k0 < r; k0 += 16) {
       T pw[16];
-      const long long mm = min(m, n - 1);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) pw[u] = ex.piphi[(long long)min(k0 + u, r - 1) * n + mm];
+      for (int j = 0; j < 16 / kVec16<T>; ++j) {
+        const int k = k0 + j * kVec16<T>;
+        const Vec16<T> v = k < ex.r4 ? row[k / kVec16<T>] : Vec16<T>(T(0));
+#pragma unroll
+        for (int q = 0; q < kVec16<T>; ++q) pw[j * kVec16<T> + q] = v[q];
+      }
 #pragma unroll
       for (int u = 0; u < 16; ++u)
         if (k0 + u < r) acc0 += pw[u] * qps[k0 + u];

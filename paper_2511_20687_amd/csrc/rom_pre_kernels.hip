@@ -211,9 +211,7 @@ __global__ void __launch_bounds__(kPreThreads) rom_ghat_kernel(RomPreArgs P) {
       }
     }
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) part[kk] += __shfl_xor(part[kk], o, 64);
+    for (int kk = 0; kk < 8; ++kk) part[kk] = wave_total(part[kk]);
     if (lane == 0)
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) red[wid][kk] = part[kk];

@@ -45,9 +45,9 @@ struct Subdomain {
   // FE launch shape: fe_block 64/128/256 = column kernel; 1024 = layer-staged kernel for the
   // interior (fe_chunks workgroups of fe_kc layers) plus the column kernel (64 threads, one
   // layer per thread) for the boundary columns; fe_nblocks = workgroup partials per instance
-  int fe_block = 256, fe_kc = 8, fe_chunks = 1, fe_int_blocks = 0, fe_nblocks = 0, max_nblocks = 0;
+  int fe_block = 256, fe_kc = 8, fe_chunks = 1, fe_nblocks = 0, max_nblocks = 0;
   // FE part of a fused sweep: 512-thread workgroups of the column kernel, fz_kc layers per thread
-  int fz_kc = 1, fz_chunks = 1, fz_int_blocks = 0, fz_nblocks = 0;
+  int fz_kc = 1, fz_chunks = 1, fz_nblocks = 0;
   // OpInf
   bool rom = false;
   int r = 0, rs = 0;
@@ -70,7 +70,8 @@ struct Subdomain {
   void *face_tm[2] = {};           // [rs][r_src] for ROM sources
   void *sface[2][3] = {};          // OpInf: pushed face values by role, [batch][3 npl] (FOM source)
   std::vector<std::vector<double>> piphi_h;  // host copy per export
-  std::vector<void *> piphi_d;               // device copy per export
+  std::vector<void *> piphi_d;               // device copy per export ([r][3 npl], column-major)
+  std::vector<void *> piphi_rm;              // row-major device copy per export ([3 npl][r rounded up to 4])
   // records
   osam_record rec{};
 };

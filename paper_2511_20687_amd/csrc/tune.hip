@@ -155,7 +155,7 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
   // 4. fused sweeps (layers per thread of the FE part) with host launches or graphs
   int fkc = 0;
   if (fusion_unsupported().empty()) {
-    const int fmodes[][2] = {{1, 0}, {1, 32}, {1, 128}, {4, 0}, {4, 32}};
+    const int fmodes[][2] = {{1, 0}, {1, 32}, {1, 128}, {2, 32}, {4, 32}};
     for (const auto &m : fmodes) {
       fuse = true;
       fuse_kc = m[0];
