@@ -43,13 +43,28 @@ double *Ctx::scratch(size_t n, int32_t *st) {
   return d_scratch;
 }
 
-// Launch shape of the FE kernel: column groups x z-chunks x instances.  block/kc
-// = 0 selects the default (256 threads, one layer per thread).  The column
-// kernel packs waves: a chunk of layers is ceil(n_int / 64) interior and
-// ceil(n_bnd / 64) boundary groups of 64 columns, one wave each.
-static int fe_waves(const Subdomain &s, int kc) {
-  const int nl = s.nzs - 1;
-  return ((s.n_int + 63) / 64 + (s.n_bnd + 63) / 64) * ((nl + kc - 1) / kc);
+// Launch shape of the FE kernel: waves x instances.  block/kc = 0 selects the
+// default (256 threads, one layer per thread).  The column kernel packs waves
+// in super-chunks of bl chunks of kc layers: per chunk ceil(n_int / 64)
+// interior waves, and per boundary case group of n columns either ceil(n / 64)
+// waves per chunk (n >= 64) or one wave per min(64 / n, bl) chunks.  FE launches
+// use bl = 1; fused sweeps bl = 2 (fewer workgroups, so that they fit in one
+// round next to the OpInf workgroups).
+constexpr int kFusedBndChunks = 2;
+static int fe_bnd_waves(const Subdomain &s, int chunks, int bl) {
+  int w = 0;
+  for (int g = 0; g < s.nbg; ++g) {
+    const int n = s.bg_n[g], L = std::min(64 / std::max(n, 1), bl);
+    w += n >= 64 ? (n + 63) / 64 * chunks : (chunks + L - 1) / L;
+  }
+  return w;
+}
+static int fe_waves_in(const Subdomain &s, int chunks, int wi, int bl) {
+  const int nsc = (chunks + bl - 1) / bl, last = chunks - (nsc - 1) * bl;
+  return (nsc - 1) * (wi * bl + fe_bnd_waves(s, bl, bl)) + wi * last + fe_bnd_waves(s, last, bl);
+}
+static int fe_waves(const Subdomain &s, int kc, int bl = 1) {
+  return fe_waves_in(s, (s.nzs - 1 + kc - 1) / kc, (s.n_int + 63) / 64, bl);
 }
 
 bool Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
@@ -63,7 +78,7 @@ bool Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
     s.fe_block = 1024;
     s.fe_kc = kc;
     s.fe_chunks = (nl + kc - 1) / kc;
-    s.fe_nblocks = s.fe_chunks + (s.n_bnd + 63) / 64 * nl;
+    s.fe_nblocks = s.fe_chunks + fe_waves_in(s, nl, 0, 1);   // + the boundary launch
     return true;
   }
   int bs = block > 0 ? block : 256;
@@ -642,6 +657,12 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.part_stride = s.fe_nblocks;
   A.part_off = 0;
   A.bnd_cols = s.bnd_cols;
+  A.nbg = s.nbg;
+  A.bnd_l = 1;
+  for (int g = 0; g < 8; ++g) {
+    A.bg_start[g] = s.bg_start[g];
+    A.bg_n[g] = s.bg_n[g];
+  }
   A.rec_u = (T *)s.rec.u;
   A.rec_a = (T *)s.rec.a;
   A.rec_s = (T *)s.rec.s;
@@ -674,7 +695,7 @@ int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0, hipE
         Ab.kc = 1;
         Ab.n_chunks = nl;
         Ab.n_int = 0;   // boundary groups only
-        Ab.nblocks = (s.n_bnd + 63) / 64 * nl;
+        Ab.nblocks = fe_waves_in(s, nl, 0, 1);
         Ab.part_off = s.fe_chunks;
         e = launch_fe<float>(Ab, batch, 64, mode, stream, nullptr, ev1);
       }
@@ -901,7 +922,7 @@ void Ctx::fuse_layout(Subdomain &s) {
   const int nl = s.nzs - 1;
   s.fz_kc = std::max(1, std::min(fuse_kc, nl));
   s.fz_chunks = (nl + s.fz_kc - 1) / s.fz_kc;
-  s.fz_nblocks = (fe_waves(s, s.fz_kc) + 7) / 8;   // 8 waves per workgroup; <= max_nblocks
+  s.fz_nblocks = (fe_waves(s, s.fz_kc, kFusedBndChunks) + 7) / 8;   // 8 waves per workgroup; <= max_nblocks
 }
 
 std::string Ctx::fusion_unsupported() const {
@@ -945,6 +966,7 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
       fill_fe_args<T>(c, d, i, o, A);
       A.kc = d.fz_kc;
       A.n_chunks = d.fz_chunks;
+      A.bnd_l = kFusedBndChunks;
       A.nblocks = d.fz_nblocks;
       A.part_stride = d.fz_nblocks;
       A.part_off = 0;

@@ -57,18 +57,21 @@ __device__ __forceinline__ Strides strides(const FeArgs<T> &A) {
 
 // Newmark update of node (layer k, column nid0) from its acceleration, with
 // the convergence sums, records and pushes.
-template <typename T, int MODE>
+// UK: the layer k is wave-uniform (its offset goes into the scalar offset of the
+// buffer accesses); otherwise every lane has its own layer (boundary waves that
+// hold several layers) and the layer offset goes into the per-lane offset.
+template <typename T, int MODE, bool UK>
 __device__ __forceinline__ void update_node(const FeArgs<T> &A, const Roles<T> &R, int b, int k, int nid0,
                                             const T (&ctr)[3], const T (&acc)[3], const T (&v0)[3],
                                             const T (&a0)[3], const T (&old)[3], int n_iter, bool rec,
                                             long long rbase, double &acc_abs, double &acc_den) {
   const Strides B = strides(A);
-  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T);
+  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T) + (UK ? 0u : (unsigned)k * B.npl);
   T out[3];   // value pushed to neighbours: the displacement at the next step
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const T a1 = acc[c];
-    const unsigned so = (unsigned)k * B.npl + c * B.cs;   // wave-uniform part of the offset
+    const unsigned so = (UK ? (unsigned)k * B.npl : 0u) + c * B.cs;   // wave-uniform part of the offset
     if (MODE == kModeInit) {
       Field<T>(R.A0).st(a1, vo, so);
       out[c] = ctr[c] + A.dt * v0[c] + A.half_dt2 * a1;
@@ -114,14 +117,14 @@ __device__ __forceinline__ void record_face(const FeArgs<T> &A, int b, int f, in
 }
 
 // v0, a0 and the previous iterate (V1, or U0 at the first iteration) of one node.
-template <typename T, int MODE>
+template <typename T, int MODE, bool UK>
 __device__ __forceinline__ void state_loads(const Roles<T> &R, const Strides &B, int k, int nid0, int n_iter,
                                             T (&v0)[3], T (&a0)[3], T (&old)[3]) {
-  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T);
+  const unsigned vo = (unsigned)nid0 * (unsigned)sizeof(T) + (UK ? 0u : (unsigned)k * B.npl);
   const Field<T> FV(R.V0), FA(R.A0), FO(n_iter >= 2 ? R.V1 : R.U0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const unsigned so = (unsigned)k * B.npl + c * B.cs;
+    const unsigned so = (UK ? (unsigned)k * B.npl : 0u) + c * B.cs;
     v0[c] = FV.ld(vo, so);
     a0[c] = MODE == kModeInit ? T(0) : FA.ld(vo, so);
     old[c] = MODE == kModeInit ? T(0) : FO.ld(vo, so);
@@ -137,9 +140,11 @@ __device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B
   else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
 }
 
-// Column (ix, iy), layers k0 .. k1-1 (ONE: the single layer k0, every load issued at once).
-template <typename T, int MODE, bool INTERIOR, bool ONE>
-__device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int chunk, long long step,
+// Column t (interior index, or entry of the boundary list), layers k0 .. k1-1
+// (ONE: the single layer k0, every load issued at once).  Interior waves have
+// one k0; a boundary wave may give each lane its own k0.
+template <typename T, int MODE, bool INTERIOR, bool ONE, bool UK = INTERIOR>
+__device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int k0, long long step,
                                            int iter, double &acc_abs, double &acc_den) {
   const int nx = A.nx, ny = A.ny, nxp = nx + 1, npl = A.npl, nzs = A.nzs;
   const long long cs = A.cs;
@@ -161,7 +166,6 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   }
   const T *C = A.coef + cse * 234;
   const Roles<T> R = roles<T, MODE>(A, b, step, n_iter);
-  const int k0 = 1 + chunk * A.kc;
   const int k1 = ONE ? k0 + 1 : min(k0 + A.kc, nzs);
   const int nid0 = ix + nxp * iy;
   const Strides B = strides(A);
@@ -181,7 +185,7 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
     layer<T, INTERIOR>(w0, k == 1 ? R.Flo : R.Pin, B, cs, k - 1, npl, nxp, ix, iy, nx, ny, nid0);
     layer<T, INTERIOR>(w1, R.Pin, B, cs, k, npl, nxp, ix, iy, nx, ny, nid0);
     layer<T, INTERIOR>(w2, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
-    state_loads<T, MODE>(R, B, k, nid0, n_iter, v0, a0, old);
+    state_loads<T, MODE, UK>(R, B, k, nid0, n_iter, v0, a0, old);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       ctr[c] = w1[4][c];
@@ -190,7 +194,7 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
     slab<T, INTERIOR, -1>(A.cb, C, w0, ctr, acc);
     slab<T, INTERIOR, 0>(A.cb, C, w1, ctr, acc);
     slab<T, INTERIOR, 1>(A.cb, C, w2, ctr, acc);
-    update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
+    update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (rec && A.rec_s) {
       if (k == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, w0, rcol);
       if (k == nzs - 1 && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, w2, rcol);
@@ -214,10 +218,10 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
 
   for (int k = k0; k < k1; ++k) {
     T v0[3], a0[3], old[3];
-    state_loads<T, MODE>(R, B, k, nid0, n_iter, v0, a0, old);
+    state_loads<T, MODE, UK>(R, B, k, nid0, n_iter, v0, a0, old);
     layer<T, INTERIOR>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
     slab<T, INTERIOR, 1>(A.cb, C, nxt, ctr, acc);
-    update_node<T, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
+    update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (k + 1 < k1) {
       // start layer k+1: contributions of layers k (dz = -1) and k+1 (dz = 0)
 #pragma unroll
@@ -236,7 +240,9 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   if (rec && A.rec_s && k1 == nzs && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, nxt, rcol);
 }
 
-template <typename T, int MODE, bool ONE>
+// PACKB: boundary waves may hold several layer chunks (A.bnd_l > 1, fused
+// sweeps); otherwise every wave has one layer chunk and one wave-uniform layer.
+template <typename T, int MODE, bool ONE, bool PACKB = false>
 __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
   const int b = blockIdx.y;
   const Status *stp = A.status + b;
@@ -248,16 +254,66 @@ __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
 
   double acc_abs = 0.0, acc_den = 0.0;
   const int bx = xcd_block(xblk, A.nblocks);
-  // work by wave: a layer chunk is wi groups of 64 interior columns then wb groups
-  // of 64 boundary columns (one case per group); wave w of the grid takes group
-  // w % (wi + wb) of chunk w / (wi + wb), so workgroups pack whole groups
-  const int wi = (A.n_int + 63) >> 6, wb = (A.n_bnd + 63) >> 6;
+  // work by wave, in super-chunks of A.bnd_l layer chunks (the grid order is
+  // layer order, so every XCD gets its share of both kinds): per super-chunk of
+  // cs chunks, wi groups of 64 interior columns per chunk, then the boundary:
+  // case group g of n columns takes, per wave, L = min(64 / n, A.bnd_l) chunks
+  // of its columns when n < 64 (one lane range per chunk, each lane its own
+  // layers; fewer waves, but every load touches up to L times more lines),
+  // else 64 of its columns in one chunk
+  const int wi = (A.n_int + 63) >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(bx * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6));
-  const int chunk = wave / (wi + wb), wc = wave - chunk * (wi + wb);
   const int lane = threadIdx.x & 63;
-  if (chunk < A.n_chunks) {
-    if (wc < wi) fe_columns<T, MODE, true, ONE>(A, b, wc * 64 + lane, chunk, step, iter, acc_abs, acc_den);
-    else fe_columns<T, MODE, false, ONE>(A, b, (wc - wi) * 64 + lane, chunk, step, iter, acc_abs, acc_den);
+  const int bl = PACKB ? A.bnd_l : 1;
+  auto bnd_waves = [&](int cs) {   // boundary waves of a super-chunk of cs chunks
+    int w = 0;
+    for (int g = 0; g < A.nbg; ++g) {
+      const int ng = A.bg_n[g], L = min(64 / ng, bl);
+      w += ng >= 64 ? ((ng + 63) >> 6) * cs : (cs + L - 1) / L;
+    }
+    return w;
+  };
+  const int nsc = (A.n_chunks + bl - 1) / bl;
+  const int wfull = wi * bl + bnd_waves(bl);
+  const int sc = min(wave / wfull, nsc - 1);
+  const int c0 = sc * bl, cs = min(bl, A.n_chunks - c0);
+  int v = wave - sc * wfull;
+  if (v < wi * cs) {
+    const int chunk = c0 + v / wi, wc = v - (v / wi) * wi;
+    fe_columns<T, MODE, true, ONE>(A, b, wc * 64 + lane, 1 + chunk * A.kc, step, iter, acc_abs, acc_den);
+  } else {
+    v -= wi * cs;
+    int t = -1, k0 = 0;
+    for (int g = 0; g < A.nbg; ++g) {
+      const int ng = A.bg_n[g];
+      if (ng >= 64) {
+        const int per = (ng + 63) >> 6, nw = per * cs;
+        if (v < nw) {
+          const int chunk = v / per, col = (v - chunk * per) * 64 + lane;
+          if (col < ng) {
+            t = A.bg_start[g] + col;
+            k0 = 1 + (c0 + chunk) * A.kc;
+          }
+          break;
+        }
+        v -= nw;
+      } else {
+        const int L = min(64 / ng, bl), nw = (cs + L - 1) / L;
+        if (v < nw) {
+          const int lb = lane / ng, chunk = v * L + lb;
+          if (lb < L && chunk < cs) {
+            t = A.bg_start[g] + lane - lb * ng;
+            k0 = 1 + (c0 + chunk) * A.kc;
+          }
+          break;
+        }
+        v -= nw;
+      }
+    }
+    if (t >= 0) {
+      if (PACKB) fe_columns<T, MODE, false, ONE, false>(A, b, t, k0, step, iter, acc_abs, acc_den);
+      else fe_columns<T, MODE, false, ONE, true>(A, b, t, __builtin_amdgcn_readfirstlane(k0), step, iter, acc_abs, acc_den);
+    }
   }
   if (MODE == kModeInit) return;
 

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kLdsThreads) fe_lds_kernel(FeArgs<float> A) {
     // one column at a time; the next column's state loads are issued before this one is computed
     int nnid = column(tid);
     float nv0[3], na0[3], nold[3];
-    if (tid < A.n_int) state_loads<float, MODE>(R, B, k, nnid, n_iter, nv0, na0, nold);
+    if (tid < A.n_int) state_loads<float, MODE, true>(R, B, k, nnid, n_iter, nv0, na0, nold);
 #pragma unroll 1
     for (int w = tid; w < A.n_int; w += kLdsThreads) {
       const int nid0 = nnid;
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(kLdsThreads) fe_lds_kernel(FeArgs<float> A) {
       }
       if (w + kLdsThreads < A.n_int) {
         nnid = column(w + kLdsThreads);
-        state_loads<float, MODE>(R, B, k, nnid, n_iter, nv0, na0, nold);
+        state_loads<float, MODE, true>(R, B, k, nnid, n_iter, nv0, na0, nold);
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) ctr[c] = Sc[c * npl + nid0];
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kLdsThreads) fe_lds_kernel(FeArgs<float> A) {
         for (int c = 0; c < 3; ++c) wf[4][c] = S[c * npl + nid0];
         record_face<float>(A, b, k == 1 ? 0 : 1, nid0, wf, rcol);
       }
-      update_node<float, MODE>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
+      update_node<float, MODE, true>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     }
     if (k + 1 < k1) {
       __syncthreads();              // every column of layer k is done with slot (k-1) % 3

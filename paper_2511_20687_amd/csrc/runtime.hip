@@ -372,9 +372,10 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   if (st) return ctx->fail(st, "out of device memory");
   if ((st = ctx->upload(sd->coef, C.data(), C.size()))) return st;
   // state buffers are allocated when the coupling is wired (FOM subdomains only)
-  // boundary columns grouped by stencil case, every group padded to whole waves
-  // (entries -1), so all lanes of a wave share one coefficient block
+  // boundary columns grouped by stencil case (a wave never mixes groups, so all
+  // its lanes share one coefficient block)
   std::vector<int> bnd;
+  sd->nbg = 0;
   for (int cse = 0; cse < 9; ++cse) {
     if (cse == 4) continue;
     const size_t start = bnd.size();
@@ -383,8 +384,11 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
         const int cx = ix == 0 ? 0 : (ix == d->nx ? 2 : 1), cy = iy == 0 ? 0 : (iy == d->ny ? 2 : 1);
         if (cx + 3 * cy == cse) bnd.push_back(ix + (d->nx + 1) * iy);
       }
-    if (bnd.size() > start)
-      while (bnd.size() % 64) bnd.push_back(-1);
+    if (bnd.size() > start) {
+      sd->bg_start[sd->nbg] = (int)start;
+      sd->bg_n[sd->nbg] = (int)(bnd.size() - start);
+      ++sd->nbg;
+    }
   }
   sd->n_bnd = (int)bnd.size();
   sd->n_int = (d->nx - 1) * (d->ny - 1);
