@@ -1002,16 +1002,16 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
 int32_t Ctx::launch_round_fused(const Opts &o) {
   const std::string why = fusion_unsupported();
   if (!why.empty()) return fail(OSAM_E_INVALID, why);
+  RomPreArgs pre[kSweepRom];
+  int npre = 0;
   for (size_t i = 0; i < sds.size(); ++i) {
     Subdomain &d = *sds[i];
-    if (!d.rom) {
-      fuse_layout(d);
-    } else if (d.pre) {
-      RomPreArgs P;
-      fill_pre_args(*this, d, (int)i, o, P);
-      const hipError_t e = launch_rom_pre(P, stream);
-      if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("batched OpInf kernels: ") + hipGetErrorString(e));
-    }
+    if (!d.rom) fuse_layout(d);
+    else if (d.pre) fill_pre_args(*this, d, (int)i, o, pre[npre++]);
+  }
+  if (npre > 0) {   // the batched parts of every OpInf subdomain, f0 in one launch
+    const hipError_t e = launch_rom_pre_multi(pre, npre, stream);
+    if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("batched OpInf kernels: ") + hipGetErrorString(e));
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timing) {   // every subdomain reports the fused launch

@@ -330,6 +330,7 @@ struct RomPreArgs {
 };
 
 hipError_t launch_rom_pre(const RomPreArgs &P, hipStream_t s);
+hipError_t launch_rom_pre_multi(const RomPreArgs *P, int n, hipStream_t s);
 
 // One Schwarz sweep in a single launch: the subdomain in slot i owns the next
 // nblk[i] workgroups of the grid (x), instances along y; fe_idx / rom_idx pick

@@ -35,7 +35,10 @@ __device__ __forceinline__ short to_bf16(float x) {
 }
 
 constexpr int kPreThreads = 256;
-constexpr int kPreUnroll = 8;   // K blocks per wave and round; the next round's fragments are in flight
+// K blocks per wave and round (FP32 blocks are 4 wide, BF16 16 wide); the next
+// round's fragments are in flight while a round computes
+template <int PREC>
+constexpr int kPreUnroll = PREC == 0 ? 16 : 8;
 
 // Fragments of the K blocks kb = base, base + 4, ... (wave-strided) of one
 // round, A blocks (HP = false) or H blocks (HP = true); indices past the range
@@ -43,16 +46,16 @@ constexpr int kPreUnroll = 8;   // K blocks per wave and round; the next round's
 // issued without a branch and stays in flight while the previous round computes.
 template <int PREC, bool HP>
 struct Frags {
-  float a[kPreUnroll];    // FP32 operand (A blocks; H blocks when PREC == 0)
-  s4_t h[kPreUnroll];     // BF16 operand (H blocks when PREC == 1)
-  int ij[kPreUnroll];     // H block: row i of the triangle | first column j0 << 16
+  float a[kPreUnroll<PREC>];    // FP32 operand (A blocks; H blocks when PREC == 0)
+  s4_t h[kPreUnroll<PREC>];     // BF16 operand (H blocks when PREC == 1)
+  int ij[kPreUnroll<PREC>];     // H block: row i of the triangle | first column j0 << 16
 };
 
 template <int PREC, bool HP>
 __device__ __forceinline__ void load_frags(const RomPreArgs &P, int rt, int base, int hi, int lane,
                                            Frags<PREC, HP> &F) {
 #pragma unroll
-  for (int u = 0; u < kPreUnroll; ++u) {
+  for (int u = 0; u < kPreUnroll<PREC>; ++u) {
     const int kb = min(base + 4 * u, hi - 1);   // wave-uniform
     if (!HP) {
       F.a[u] = P.frag_a[((long long)rt * P.nkba + kb) * 64 + lane];
@@ -73,11 +76,11 @@ __device__ __forceinline__ void mfma_range(const RomPreArgs &P, const float *q1s
   if (lo + wid >= hi) return;
   Frags<PREC, HP> cur, nxt;
   load_frags<PREC, HP>(P, rt, lo + wid, hi, lane, nxt);
-  for (int base = lo + wid; base < hi; base += 4 * kPreUnroll) {
+  for (int base = lo + wid; base < hi; base += 4 * kPreUnroll<PREC>) {
     cur = nxt;
-    if (base + 4 * kPreUnroll < hi) load_frags<PREC, HP>(P, rt, base + 4 * kPreUnroll, hi, lane, nxt);
+    if (base + 4 * kPreUnroll<PREC> < hi) load_frags<PREC, HP>(P, rt, base + 4 * kPreUnroll<PREC>, hi, lane, nxt);
 #pragma unroll
-    for (int u = 0; u < kPreUnroll; ++u) {
+    for (int u = 0; u < kPreUnroll<PREC>; ++u) {
       const int kb = base + 4 * u;
       if (kb >= hi) break;
       if (!HP) {   // linear part, FP32 operands
@@ -118,9 +121,9 @@ __device__ __forceinline__ void mfma_range(const RomPreArgs &P, const float *q1s
 // j0 .. j0 + 15 (BF16) of row i of the triangle (rows padded to whole blocks),
 // so z = q_i q_j needs no per-lane index table.
 template <int PREC, int NI>
-__global__ void __launch_bounds__(kPreThreads) rom_f0_kernel(RomPreArgs P) {
+__device__ __forceinline__ void f0_body(const RomPreArgs &P, int bxl) {
   const int b0 = blockIdx.y * NI * 16;
-  const int rt = blockIdx.x % P.nrt, ksi = blockIdx.x / P.nrt;
+  const int rt = bxl % P.nrt, ksi = bxl / P.nrt;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   extern __shared__ float q1s[];   // [NI * 16][r]: the predictor of the group's instances
@@ -178,6 +181,25 @@ __global__ void __launch_bounds__(kPreThreads) rom_f0_kernel(RomPreArgs P) {
   }
 }
 
+template <int PREC, int NI>
+__global__ void __launch_bounds__(kPreThreads) rom_f0_kernel(RomPreArgs P) {
+  f0_body<PREC, NI>(P, blockIdx.x);
+}
+
+// f0 of several OpInf subdomains in one launch: subdomain i owns the next
+// nrt * ks workgroups of the grid (x)
+struct RomPreMulti {
+  int n;
+  RomPreArgs p[2];
+};
+
+template <int PREC, int NI>
+__global__ void __launch_bounds__(kPreThreads) rom_f0_multi_kernel(RomPreMulti M) {
+  const int n0 = M.p[0].nrt * M.p[0].ks;
+  if ((int)blockIdx.x < n0) f0_body<PREC, NI>(M.p[0], blockIdx.x);
+  else f0_body<PREC, NI>(M.p[1], blockIdx.x - n0);
+}
+
 size_t rom_f0_smem_bytes(int r, int ni) {
   const size_t q = sizeof(float) * 16 * (size_t)ni * r, red = sizeof(f4_t) * 4 * (size_t)ni * 64;
   return q > red ? q : red;
@@ -228,6 +250,49 @@ static void launch_f0(const RomPreArgs &P, dim3 grid, size_t smem, hipStream_t s
   if (P.ni == 4) hipLaunchKernelGGL((rom_f0_kernel<PREC, 4>), grid, dim3(kPreThreads), smem, s, P);
   else if (P.ni == 2) hipLaunchKernelGGL((rom_f0_kernel<PREC, 2>), grid, dim3(kPreThreads), smem, s, P);
   else hipLaunchKernelGGL((rom_f0_kernel<PREC, 1>), grid, dim3(kPreThreads), smem, s, P);
+}
+
+template <int PREC>
+static void launch_f0_multi(const RomPreMulti &M, dim3 grid, size_t smem, hipStream_t s) {
+  const int ni = M.p[0].ni;
+  if (ni == 4) hipLaunchKernelGGL((rom_f0_multi_kernel<PREC, 4>), grid, dim3(kPreThreads), smem, s, M);
+  else if (ni == 2) hipLaunchKernelGGL((rom_f0_multi_kernel<PREC, 2>), grid, dim3(kPreThreads), smem, s, M);
+  else hipLaunchKernelGGL((rom_f0_multi_kernel<PREC, 1>), grid, dim3(kPreThreads), smem, s, M);
+}
+
+// The batched parts of n (1 or 2) OpInf subdomains of one context: the f0
+// contractions in one launch when both have one (same precision and instance
+// grouping), then the g^ splits of each.
+hipError_t launch_rom_pre_multi(const RomPreArgs *P, int n, hipStream_t s) {
+  if (n == 2 && P[0].nkba + P[0].nkbh > 0 && P[1].nkba + P[1].nkbh > 0 && P[0].prec == P[1].prec &&
+      P[0].ni == P[1].ni && P[0].nit == P[1].nit) {
+    RomPreMulti M;
+    M.n = 2;
+    size_t smem = 0;
+    for (int i = 0; i < 2; ++i) {
+      if (!(P[i].ni == 1 || P[i].ni == 2 || P[i].ni == 4) || P[i].ni * 4 * P[i].r > 16 * kPreThreads)
+        return hipErrorInvalidValue;
+      M.p[i] = P[i];
+      smem = std::max(smem, rom_f0_smem_bytes(P[i].r, P[i].ni));
+    }
+    if (smem > 65536) return hipErrorInvalidValue;
+    const dim3 grid(P[0].nrt * P[0].ks + P[1].nrt * P[1].ks, (P[0].nit + P[0].ni - 1) / P[0].ni);
+    if (P[0].prec == 0) launch_f0_multi<0>(M, grid, smem, s);
+    else launch_f0_multi<1>(M, grid, smem, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < 2; ++i)
+      if (P[i].nface > 0 && P[i].rs > 0) {
+        hipLaunchKernelGGL(rom_ghat_kernel, dim3(P[i].gs, P[i].batch), dim3(kPreThreads), 0, s, P[i]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+    return hipSuccess;
+  }
+  for (int i = 0; i < n; ++i) {
+    const hipError_t e = launch_rom_pre(P[i], s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_rom_pre(const RomPreArgs &P, hipStream_t s) {

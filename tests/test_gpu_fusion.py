@@ -4,8 +4,9 @@ launch, the decision of Eq. conv_criterion in the finisher kernel.
 Checked against the sequential launches of the same context: identical records and
 iteration counts, with host launches and with graph replays (eager work between them),
 for FOM-FOM, FOM-OpInf, OpInf-FOM-OpInf (batch 20, fused and batched OpInf paths) and
-OpInf-OpInf (the OpInf source's predictor formed from its accepted state), in FP64 and
-FP32, with one and three node layers per FE thread.  FP64 FOM-FOM is also checked
+OpInf-OpInf (the OpInf source's predictor formed from its accepted state; batched path with
+both f0 contractions in one launch), in FP64 and FP32, with one and three node layers per FE
+thread.  FP64 FOM-FOM is also checked
 against the oracle.
 """
 import numpy as np
@@ -26,6 +27,7 @@ pytestmark = pytest.mark.gpu
     (("opinf", "fom", "opinf"), "f32", 20, 61, 1),
     (("opinf", "fom", "opinf"), "f32", 20, 61, 2),
     (("opinf", "opinf"), "f32", 3, 90, 0),
+    (("opinf", "opinf"), "f32", 20, 61, 2),
     (("opinf", "opinf"), "f64", 2, 90, 0),
     (("fom", "opinf", "fom"), "f64", 2, 70, 0),
 ])
