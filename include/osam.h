@@ -280,6 +280,17 @@ int32_t osam_get_timing(osam_ctx *ctx, int32_t sd, double *ms, int64_t *launches
  * are added in another order).  OSAM_E_INVALID for other values, an OpInf
  * subdomain, or the layer-staged variant where it does not apply. */
 int32_t osam_set_fe_launch(osam_ctx *ctx, int32_t sd, int32_t block, int32_t kc);
+/* Interior layout of the FE step kernel of FOM subdomain sd (Sec. 2 explicit
+ * step; results are the same bits either way).  enable = 1: a wave covers 62
+ * consecutive nodes of the rows 1 .. ny-1 (their boundary columns included),
+ * loads for each of the 9 (y, z) rows of the 27-point neighbourhood only the
+ * value at its own x, and takes the x-neighbours from the adjacent lanes (a
+ * third of the neighbour loads; the default); enable = 0: 64 interior columns
+ * per wave, every neighbour loaded.  Applies to the column kernel; fused sweeps
+ * and the layer-staged variant's interior always use their own layouts.  OSAM_E_INVALID
+ * for a bad id or an OpInf subdomain. */
+int32_t osam_set_fe_xshare(osam_ctx *ctx, int32_t sd, int32_t enable);
+
 /* Current launch shape of FOM subdomain sd (any pointer may be NULL). */
 int32_t osam_get_fe_launch(osam_ctx *ctx, int32_t sd, int32_t *block, int32_t *kc);
 
@@ -337,7 +348,8 @@ int32_t osam_set_fusion(osam_ctx *ctx, int32_t enable, int32_t kc);
  * steps (after 2 warm-up steps) from the context's current state with `opts`,
  * and keeps, one coordinate at a time, the fastest: the FE launch shape of each
  * FOM subdomain (osam_set_fe_launch: 256/1, 128/1, 64/1, 64/2, 256/8, 64/8 and,
- * where it applies, the layer-staged 1024 with 4, 8, 16 layers), the OpInf
+ * where it applies, the layer-staged 1024 with 4, 8, 16 layers; the column
+ * kernel shapes with both interior layouts of osam_set_fe_xshare), the OpInf
  * path of each OpInf subdomain of an FP32 context (osam_set_rom_path 1 or 2)
  * the launch mode (osam_set_graph: none, 32 or 128 sweeps on one stream,
  * 32 on two) and sweep fusion (osam_set_fusion with 1, 2 or 4 layers per thread,
@@ -354,6 +366,7 @@ typedef struct {
   double ms_per_step;              /* wall time per step of the chosen configuration's trial */
   int32_t from_cache;
   int32_t fusion_kc;               /* fused sweeps with this many layers per FE thread, 0: off */
+  int32_t fe_xs[8];                /* FOM subdomains: interior layout of osam_set_fe_xshare */
 } osam_tuning;
 int32_t osam_autotune(osam_ctx *ctx, int64_t trial_steps, const osam_schwarz_opts *opts, osam_tuning *out);
 

@@ -63,13 +63,18 @@ static int fe_waves_in(const Subdomain &s, int chunks, int wi, int bl) {
   const int nsc = (chunks + bl - 1) / bl, last = chunks - (nsc - 1) * bl;
   return (nsc - 1) * (wi * bl + fe_bnd_waves(s, bl, bl)) + wi * last + fe_bnd_waves(s, last, bl);
 }
+static int fe_interior_waves(const Subdomain &s, bool xs) {   // per chunk
+  return xs ? ((s.ny - 1) * (s.nx + 1) + 61) / 62 : (s.n_int + 63) / 64;
+}
 static int fe_waves(const Subdomain &s, int kc, int bl = 1) {
-  return fe_waves_in(s, (s.nzs - 1 + kc - 1) / kc, (s.n_int + 63) / 64, bl);
+  return fe_waves_in(s, (s.nzs - 1 + kc - 1) / kc, fe_interior_waves(s, s.fe_xs), bl);
 }
 
 bool Ctx::choose_fe_launch(Subdomain &s, int block, int kc) {
   const int nl = s.nzs - 1;
-  s.max_nblocks = std::max(s.max_nblocks, fe_waves(s, 1) + nl);   // bound on the workgroups of any shape
+  // bound on the workgroups of any shape, with either interior layout
+  s.max_nblocks = std::max(s.max_nblocks, fe_waves_in(s, nl, std::max(fe_interior_waves(s, false),
+                                                                      fe_interior_waves(s, true)), 1) + nl);
   if (block == 1024) {
     // layer-staged interior + column kernel for the boundary (FP32, cross-section fits the LDS)
     if (prec == OSAM_FP64 || s.npl > kFeLdsMaxNodes) return false;
@@ -658,6 +663,7 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.part_off = 0;
   A.bnd_cols = s.bnd_cols;
   A.nbg = s.nbg;
+  A.xs = s.fe_xs ? 1 : 0;
   A.bnd_l = 1;
   for (int g = 0; g < 8; ++g) {
     A.bg_start[g] = s.bg_start[g];
@@ -695,6 +701,7 @@ int32_t Ctx::launch_fe_sd(int sdi, const Opts &o, int mode, hipEvent_t ev0, hipE
         Ab.kc = 1;
         Ab.n_chunks = nl;
         Ab.n_int = 0;   // boundary groups only
+        Ab.xs = 0;
         Ab.nblocks = fe_waves_in(s, nl, 0, 1);
         Ab.part_off = s.fe_chunks;
         e = launch_fe<float>(Ab, batch, 64, mode, stream, nullptr, ev1);
@@ -922,7 +929,8 @@ void Ctx::fuse_layout(Subdomain &s) {
   const int nl = s.nzs - 1;
   s.fz_kc = std::max(1, std::min(fuse_kc, nl));
   s.fz_chunks = (nl + s.fz_kc - 1) / s.fz_kc;
-  s.fz_nblocks = (fe_waves(s, s.fz_kc, kFusedBndChunks) + 7) / 8;   // 8 waves per workgroup; <= max_nblocks
+  // (the fused sweep keeps the plain interior layout); 8 waves per workgroup; <= max_nblocks
+  s.fz_nblocks = (fe_waves_in(s, s.fz_chunks, fe_interior_waves(s, false), kFusedBndChunks) + 7) / 8;
 }
 
 std::string Ctx::fusion_unsupported() const {
@@ -967,6 +975,7 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
       A.kc = d.fz_kc;
       A.n_chunks = d.fz_chunks;
       A.bnd_l = kFusedBndChunks;
+      A.xs = 0;
       A.nblocks = d.fz_nblocks;
       A.part_stride = d.fz_nblocks;
       A.part_off = 0;

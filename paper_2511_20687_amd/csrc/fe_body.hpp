@@ -133,24 +133,37 @@ __device__ __forceinline__ void state_loads(const Roles<T> &R, const Strides &B,
 
 // One layer's 3x3 neighbourhood: interior columns through wave-uniform row bases,
 // boundary columns (clamped indices) through per-lane addresses.
-template <typename T, bool INTERIOR>
+// XS: interior rows shared across lanes (load_layer_xshare).
+template <typename T, bool INTERIOR, bool XS = false>
 __device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B, long long cs, int L, int npl,
                                       int nxp, int ix, int iy, int nx, int ny, int nid0) {
-  if (INTERIOR) load_layer_uniform<T>(w, P, B, L, (unsigned)(nid0 - nxp - 1) * (unsigned)sizeof(T));
+  if (INTERIOR && XS) load_layer_xshare<T>(w, P, B, L, (unsigned)(nid0 - nxp) * (unsigned)sizeof(T));
+  else if (INTERIOR) load_layer_uniform<T>(w, P, B, L, (unsigned)(nid0 - nxp - 1) * (unsigned)sizeof(T));
   else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
 }
 
 // Column t (interior index, or entry of the boundary list), layers k0 .. k1-1
 // (ONE: the single layer k0, every load issued at once).  Interior waves have
 // one k0; a boundary wave may give each lane its own k0.
-template <typename T, int MODE, bool INTERIOR, bool ONE, bool UK = INTERIOR>
+// XS (interior only): t indexes the nodes of rows 1 .. ny-1 including their
+// boundary columns, 62 per wave from lane 1 (lanes 0 and 63 and the boundary
+// columns only supply x-neighbours); every lane runs through, and only lanes
+// of interior nodes store.
+template <typename T, int MODE, bool INTERIOR, bool ONE, bool UK = INTERIOR, bool XS = false>
 __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int k0, long long step,
                                            int iter, double &acc_abs, double &acc_den) {
   const int nx = A.nx, ny = A.ny, nxp = nx + 1, npl = A.npl, nzs = A.nzs;
   const long long cs = A.cs;
   const int n_iter = iter + 1;
   int ix, iy, cse;
-  if (INTERIOR) {
+  bool act = true;   // this lane's node is updated
+  if (INTERIOR && XS) {
+    const int nf = (ny - 1) * nxp, f = min(max(t, 0), nf - 1), lane = threadIdx.x & 63;
+    ix = f % nxp;
+    iy = 1 + f / nxp;
+    cse = 4;
+    act = t == f && lane >= 1 && lane <= 62 && ix >= 1 && ix < nx;
+  } else if (INTERIOR) {
     if (t >= A.n_int) return;
     ix = 1 + t % (nx - 1);
     iy = 1 + t / (nx - 1);
@@ -182,9 +195,9 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   if (ONE) {
     const int k = k0;
     T w0[9][3], w1[9][3], w2[9][3], v0[3], a0[3], old[3], acc[3], ctr[3];
-    layer<T, INTERIOR>(w0, k == 1 ? R.Flo : R.Pin, B, cs, k - 1, npl, nxp, ix, iy, nx, ny, nid0);
-    layer<T, INTERIOR>(w1, R.Pin, B, cs, k, npl, nxp, ix, iy, nx, ny, nid0);
-    layer<T, INTERIOR>(w2, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR, XS>(w0, k == 1 ? R.Flo : R.Pin, B, cs, k - 1, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR, XS>(w1, R.Pin, B, cs, k, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR, XS>(w2, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
     state_loads<T, MODE, UK>(R, B, k, nid0, n_iter, v0, a0, old);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -194,6 +207,7 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
     slab<T, INTERIOR, -1>(A.cb, C, w0, ctr, acc);
     slab<T, INTERIOR, 0>(A.cb, C, w1, ctr, acc);
     slab<T, INTERIOR, 1>(A.cb, C, w2, ctr, acc);
+    if (!act) return;
     update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (rec && A.rec_s) {
       if (k == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, w0, rcol);
@@ -205,8 +219,8 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   // rolling window: cur = layer k, nxt = layer k+1; acc holds the partial force
   // of layer k from layers k-1 and k until layer k+1 arrives.
   T cur[9][3], nxt[9][3], acc[3], ctr[3];
-  layer<T, INTERIOR>(nxt, k0 == 1 ? R.Flo : R.Pin, B, cs, k0 - 1, npl, nxp, ix, iy, nx, ny, nid0);
-  layer<T, INTERIOR>(cur, R.Pin, B, cs, k0, npl, nxp, ix, iy, nx, ny, nid0);
+  layer<T, INTERIOR, XS>(nxt, k0 == 1 ? R.Flo : R.Pin, B, cs, k0 - 1, npl, nxp, ix, iy, nx, ny, nid0);
+  layer<T, INTERIOR, XS>(cur, R.Pin, B, cs, k0, npl, nxp, ix, iy, nx, ny, nid0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     ctr[c] = cur[4][c];
@@ -214,14 +228,15 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   }
   slab<T, INTERIOR, -1>(A.cb, C, nxt, ctr, acc);
   slab<T, INTERIOR, 0>(A.cb, C, cur, ctr, acc);
-  if (rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, nxt, rcol);
+  if (act && rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, nxt, rcol);
 
   for (int k = k0; k < k1; ++k) {
     T v0[3], a0[3], old[3];
     state_loads<T, MODE, UK>(R, B, k, nid0, n_iter, v0, a0, old);
-    layer<T, INTERIOR>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR, XS>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
     slab<T, INTERIOR, 1>(A.cb, C, nxt, ctr, acc);
-    update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
+    if (act)
+      update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (k + 1 < k1) {
       // start layer k+1: contributions of layers k (dz = -1) and k+1 (dz = 0)
 #pragma unroll
@@ -237,12 +252,14 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
         for (int c = 0; c < 3; ++c) cur[n][c] = nxt[n][c];
     }
   }
-  if (rec && A.rec_s && k1 == nzs && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, nxt, rcol);
+  if (act && rec && A.rec_s && k1 == nzs && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, nxt, rcol);
 }
 
 // PACKB: boundary waves may hold several layer chunks (A.bnd_l > 1, fused
 // sweeps); otherwise every wave has one layer chunk and one wave-uniform layer.
-template <typename T, int MODE, bool ONE, bool PACKB = false>
+// XSOK: the x-shared interior layout (A.xs) is compiled in (not in the fused
+// sweep kernel, where its shuffles push the register budget into spills).
+template <typename T, int MODE, bool ONE, bool PACKB = false, bool XSOK = true>
 __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
   const int b = blockIdx.y;
   const Status *stp = A.status + b;
@@ -261,7 +278,10 @@ __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
   // of its columns when n < 64 (one lane range per chunk, each lane its own
   // layers; fewer waves, but every load touches up to L times more lines),
   // else 64 of its columns in one chunk
-  const int wi = (A.n_int + 63) >> 6;
+  // interior waves per chunk: 64 interior columns each, or (A.xs) 62 nodes of
+  // the rows 1 .. ny-1 counted with their boundary columns
+  const bool xs = XSOK && A.xs;
+  const int wi = xs ? ((A.ny - 1) * (A.nx + 1) + 61) / 62 : (A.n_int + 63) >> 6;
   const int wave = __builtin_amdgcn_readfirstlane(bx * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int bl = PACKB ? A.bnd_l : 1;
@@ -280,7 +300,11 @@ __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
   int v = wave - sc * wfull;
   if (v < wi * cs) {
     const int chunk = c0 + v / wi, wc = v - (v / wi) * wi;
-    fe_columns<T, MODE, true, ONE>(A, b, wc * 64 + lane, 1 + chunk * A.kc, step, iter, acc_abs, acc_den);
+    if (XSOK && xs)
+      fe_columns<T, MODE, true, ONE, true, XSOK>(A, b, wc * 62 + lane - 1, 1 + chunk * A.kc, step, iter, acc_abs,
+                                                 acc_den);
+    else
+      fe_columns<T, MODE, true, ONE>(A, b, wc * 64 + lane, 1 + chunk * A.kc, step, iter, acc_abs, acc_den);
   } else {
     v -= wi * cs;
     int t = -1, k0 = 0;

@@ -233,6 +233,7 @@ struct FeArgs {
   int kc, n_chunks, n_int, n_bnd, nblocks;   // nblocks: workgroups of the launch (waves packed, see fe_body)
   const int *bnd_cols;     // boundary columns (ids in the layer), grouped by cross-section case
   int nbg;                 // case groups of the boundary list (at most 8)
+  int xs;                  // 1: interior waves share x-neighbours across lanes (62 nodes per wave)
   int bnd_l;               // layer chunks per boundary wave (1..4): a wave of a group of
                            // n < 64 columns holds min(64 / n, bnd_l) chunks
   int bg_start[8], bg_n[8];   // first entry and number of columns of each group

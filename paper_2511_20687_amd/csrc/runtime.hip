@@ -600,6 +600,19 @@ int32_t osam_set_fe_launch(osam_ctx *c, int32_t sd, int32_t block, int32_t kc) {
   return OSAM_OK;
 }
 
+int32_t osam_set_fe_xshare(osam_ctx *c, int32_t sd, int32_t enable) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  ctx->err.clear();
+  if (sd < 0 || sd >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  Subdomain &s = *ctx->sds[sd];
+  if (s.rom) return ctx->fail(OSAM_E_INVALID, "not a FOM subdomain");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  s.fe_xs = enable != 0;
+  if (!ctx->choose_fe_launch(s, s.fe_block, s.fe_kc)) return ctx->fail(OSAM_E_INVALID, "FE launch shape");
+  return OSAM_OK;
+}
+
 int32_t osam_get_fe_launch(osam_ctx *c, int32_t sd, int32_t *block, int32_t *kc) {
   if (!c) return OSAM_E_INVALID;
   Ctx *ctx = reinterpret_cast<Ctx *>(c);

@@ -42,6 +42,7 @@ struct Subdomain {
   int *bnd_cols = nullptr;          // boundary columns grouped by cross-section case
   int n_int = 0, n_bnd = 0;
   int nbg = 0, bg_start[8] = {}, bg_n[8] = {};   // the case groups of bnd_cols
+  bool fe_xs = true;               // interior waves share x-neighbours across lanes
   double *partials = nullptr;
   // FE launch shape: fe_block 64/128/256 = column kernel; 1024 = layer-staged kernel for the
   // interior (fe_chunks workgroups of fe_kc layers) plus the column kernel (64 threads, one

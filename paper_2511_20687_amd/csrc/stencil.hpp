@@ -112,6 +112,31 @@ __device__ __forceinline__ void load_layer_uniform(T (&w)[9][3], const T *P, con
     }
 }
 
+// Interior rows shared across lanes: consecutive lanes hold consecutive nodes of
+// a row, so each lane loads only the x-centred value of rows dy = -1, 0, 1 of
+// layer L and takes its x-neighbours from the adjacent lanes.  voff = (nid -
+// nxp) * sizeof(T) >= 0.  Every lane of the wave must take part; a lane whose
+// adjacent lane is not its x-neighbour (lanes 0 and 63) must not use the result.
+template <typename T>
+__device__ __forceinline__ void load_layer_xshare(T (&w)[9][3], const T *P, const Strides &B, int L,
+                                                  unsigned voff) {
+  const Field<T> F(P);
+  const unsigned lo = (unsigned)L * B.npl;
+  T x[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int ry = 0; ry < 3; ++ry) x[ry][c] = F.ld(voff, lo + c * B.cs + ry * B.nxp);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int ry = 0; ry < 3; ++ry) {
+      w[3 * ry + 1][c] = x[ry][c];
+      w[3 * ry][c] = __shfl_up(x[ry][c], 1, 64);
+      w[3 * ry + 2][c] = __shfl_down(x[ry][c], 1, 64);
+    }
+}
+
 // Contribution of one z-slab (dz = DZ) of the 27-point stencil to the node
 // whose own value is ctr: acc += sum_n C_(dx,dy,DZ) (w[n] - ctr).
 // cb: the interior block's 27 distinct values (kernel arguments), C: this

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(kRomThreads) sweep_kernel(SweepArgs<T> S) {
   int x = blockIdx.x, i = 0;
   while (i + 1 < S.n && x >= S.nblk[i]) x -= S.nblk[i++];
   if (FE == 0 || S.rom_idx[i] >= 0) rom_body<T, V>(S.rom[S.rom_idx[i]], x);
-  else fe_body<T, kModeStep, FE == 1, true>(S.fe[S.fe_idx[i]], x);
+  else fe_body<T, kModeStep, FE == 1, true, false>(S.fe[S.fe_idx[i]], x);
 }
 
 template <typename T, int V>

@@ -45,6 +45,7 @@ int32_t Ctx::apply_tuning(const osam_tuning &t) {
   for (size_t i = 0; i < sds.size(); ++i) {
     Subdomain &d = *sds[i];
     if (!d.rom) {
+      d.fe_xs = t.fe_xs[i] != 0;
       if (!choose_fe_launch(d, t.fe_block[i], t.fe_kc[i])) return fail(OSAM_E_INVALID, "cached FE launch does not apply");
     } else if (d.rom_path != t.rom_path[i]) {
       d.rom_path = t.rom_path[i];
@@ -104,16 +105,21 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
     Subdomain &d = *sds[i];
     if (d.rom) continue;
     int bb = d.fe_block, bk = d.fe_kc;
-    for (const auto &sh : shapes) {
-      if (!choose_fe_launch(d, sh[0], sh[1])) continue;
-      double ms;
-      if ((st = trial(&ms))) return st;
-      if (ms < best) {
-        best = ms;
-        bb = d.fe_block;
-        bk = d.fe_kc;
+    bool bx = d.fe_xs;
+    for (const auto &sh : shapes)
+      for (int xs = 0; xs < (sh[0] == 1024 ? 1 : 2); ++xs) {
+        d.fe_xs = xs != 0;
+        if (!choose_fe_launch(d, sh[0], sh[1])) continue;
+        double ms;
+        if ((st = trial(&ms))) return st;
+        if (ms < best) {
+          best = ms;
+          bb = d.fe_block;
+          bk = d.fe_kc;
+          bx = d.fe_xs;
+        }
       }
-    }
+    d.fe_xs = bx;
     choose_fe_launch(d, bb, bk);
   }
   // 2. OpInf path (FP32 contexts: fused or batched)
@@ -178,6 +184,7 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
   for (size_t i = 0; i < sds.size() && i < 8; ++i) {
     t.fe_block[i] = sds[i]->rom ? 0 : sds[i]->fe_block;
     t.fe_kc[i] = sds[i]->rom ? 0 : sds[i]->fe_kc;
+    t.fe_xs[i] = sds[i]->rom ? 0 : (sds[i]->fe_xs ? 1 : 0);
     t.rom_path[i] = sds[i]->rom ? (sds[i]->pre ? 2 : 1) : 0;
   }
   t.graph_rounds = gr;

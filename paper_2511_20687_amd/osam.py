@@ -27,7 +27,8 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_get_reduced", "osam_sizes", "osam_set_record", "learn_opinf", "osam_set_opinf",
             "osam_get_opinf", "schwarz_step", "run", "osam_set_timing", "osam_get_timing",
             "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
-            "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_set_fusion", "osam_autotune",
+            "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_set_fusion", "osam_set_fe_xshare",
+            "osam_autotune",
             "osam_sync"]
 
 
@@ -75,7 +76,7 @@ class Grads(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("fe_block", C.c_int32 * 8), ("fe_kc", C.c_int32 * 8), ("rom_path", C.c_int32 * 8),
                 ("graph_rounds", C.c_int32), ("graph_streams", C.c_int32), ("ms_per_step", C.c_double),
-                ("from_cache", C.c_int32), ("fusion_kc", C.c_int32)]
+                ("from_cache", C.c_int32), ("fusion_kc", C.c_int32), ("fe_xs", C.c_int32 * 8)]
 
 
 class SchwarzOpts(C.Structure):
@@ -154,6 +155,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_autotune.restype = i32
     lib.osam_set_graph.argtypes = [vp, i32, i32]
     lib.osam_set_graph.restype = i32
+    lib.osam_set_fe_xshare.argtypes = [vp, i32, i32]
+    lib.osam_set_fe_xshare.restype = i32
     lib.osam_set_fusion.argtypes = [vp, i32, i32]
     lib.osam_set_fusion.restype = i32
     lib.osam_set_rom_path.argtypes = [vp, i32, i32]
@@ -419,13 +422,18 @@ class Context:
         self._check(self.lib.osam_autotune(self.h, trial_steps, C.byref(o), C.byref(t)))
         n = self.n_sd
         return dict(fe=[(t.fe_block[i], t.fe_kc[i]) for i in range(n)], rom_path=list(t.rom_path[:n]),
-                    graph=(t.graph_rounds, t.graph_streams), fusion_kc=t.fusion_kc, ms_per_step=t.ms_per_step,
+                    fe_xs=list(t.fe_xs[:n]), graph=(t.graph_rounds, t.graph_streams), fusion_kc=t.fusion_kc,
+                    ms_per_step=t.ms_per_step,
                     from_cache=bool(t.from_cache))
 
     def set_graph(self, rounds: int, streams: int = 1):
         """Replay captured graphs of `rounds` Schwarz sweeps (0: launch every sweep);
         streams = 2 runs the FOM and OpInf kernels of a sweep concurrently."""
         self._check(self.lib.osam_set_graph(self.h, rounds, streams))
+
+    def set_fe_xshare(self, sd: int, enable: bool):
+        """Interior layout of the FE kernel (osam_set_fe_xshare): x-neighbours across lanes."""
+        self._check(self.lib.osam_set_fe_xshare(self.h, sd, int(bool(enable))))
 
     def set_fusion(self, enable: bool, kc: int = 1):
         """Run each Schwarz sweep as one launch (osam_set_fusion); kc node layers per FE thread."""

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s=False, lateral_fix=(),
-             fe_launch=None):
+             fe_launch=None, xshare=False, fusion_kc=0):
     import torch
     from paper_2511_20687_amd import osam
     ctx = osam.Context(0, precision, batch)
@@ -23,6 +23,10 @@ def _lib_run(bar, layers, dt, u0, v0, n, precision, opts=None, batch=1, record_s
         for sd in sds:
             ctx.set_fe_launch(sd, *fe_launch)
             assert ctx.get_fe_launch(sd)[0] == fe_launch[0]
+    for sd in sds:
+        ctx.set_fe_xshare(sd, xshare)
+    if fusion_kc:
+        ctx.set_fusion(True, fusion_kc)
     dev = torch.device("cuda:0")
     recs = []
     for sd in sds:
@@ -209,3 +213,41 @@ def test_layer_staged_fe_variant_f32(kc, lateral):
         e_s = rel_err(rl[i][1][1][:, lib_sch_index(bar, lo, hi)], ref["s"][i])
         print(f"subdomain {i}: u {e_u:.2e}, s {e_s:.2e}")
         assert e_u <= 1e-4 and e_s <= 1e-4
+
+
+@pytest.mark.parametrize("fusion_kc", [0, 1, 3])
+@pytest.mark.parametrize("kc", [1, 3])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("cross", [(6, 5), (70, 3)])
+def test_fe_xshare_layout_is_bitwise_identical(cross, precision, kc, fusion_kc):
+    """The interior layout with x-neighbours taken from adjacent lanes (osam_set_fe_xshare)
+    gives the same bits as the default layout: records of u and the Schwarz faces of three
+    slabs, batch of 2, iteration counts; with FE launches (one and three layers per thread)
+    and inside fused sweeps.  Rows of 71 nodes (70 x 3) wrap inside waves; FP64 is also
+    checked against the oracle.  Cubic elements of 1/36 m (Bar default lengths would make the
+    70 x 3 elements needle-shaped and the explicit step unstable)."""
+    nx, ny = cross
+    h = 1.0 / 36   # cubic elements (the explicit step size assumes them)
+    bar = Bar(nx, ny, 36, Lx=nx * h, Ly=ny * h, Lz=36 * h)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 3)
+    lateral = (0, 1)
+    u0 = [gaussian_pulse_u(bar, 1e-3, 0.3, 0.05), gaussian_pulse_u(bar, 2e-3, 0.6, 0.04)]
+    v0 = [np.zeros_like(u0[0]), np.zeros_like(u0[1])]
+    v0[1][0] = 2.0 * np.exp(-((bar.node_z() - 0.5) ** 2) / (2 * 0.05 ** 2))
+    n = 80
+    print(f"[xshare {cross} {precision} kc={kc} fusion={fusion_kc}] gpu", flush=True)
+    _, r0, i0 = _lib_run(bar, layers, dt, u0, v0, n, precision, batch=2, record_s=True, lateral_fix=lateral,
+                         fe_launch=(256, kc), fusion_kc=fusion_kc)
+    _, r1, i1 = _lib_run(bar, layers, dt, u0, v0, n, precision, batch=2, record_s=True, lateral_fix=lateral,
+                         fe_launch=(256, kc), xshare=True, fusion_kc=fusion_kc)
+    for i in range(len(layers)):
+        assert np.array_equal(r1[i][0], r0[i][0]), (i, float(np.abs(r1[i][0] - r0[i][0]).max()))
+        assert np.array_equal(r1[i][1], r0[i][1])
+    assert [x["total_iters"] for x in i1] == [x["total_iters"] for x in i0]
+    if precision == "f64" and kc == 1 and fusion_kc == 0:
+        models, ref = oracle_fom_coupled(bar, layers, dt, u0[1], v0[1], n, record=("u", "s"), lateral_fix=lateral)
+        for i, m in enumerate(models):
+            lo, hi = layers[i]
+            assert rel_err(r1[i][0][1][:, lib_index_of(m)], ref["u"][i]) <= 1e-10
+            assert rel_err(r1[i][1][1][:, lib_sch_index(bar, lo, hi)], ref["s"][i]) <= 1e-10
