@@ -281,12 +281,15 @@ int32_t osam_get_timing(osam_ctx *ctx, int32_t sd, double *ms, int64_t *launches
  * subdomain, or the layer-staged variant where it does not apply. */
 int32_t osam_set_fe_launch(osam_ctx *ctx, int32_t sd, int32_t block, int32_t kc);
 /* Interior layout of the FE step kernel of FOM subdomain sd (Sec. 2 explicit
- * step; results are the same bits either way).  enable = 1: a wave covers 62
+ * step; results are the same bits either way: every interior path adds the
+ * stencil in the same x-resolved order).  enable = 1: a wave covers 62
  * consecutive nodes of the rows 1 .. ny-1 (their boundary columns included),
  * loads for each of the 9 (y, z) rows of the 27-point neighbourhood only the
- * value at its own x, and takes the x-neighbours from the adjacent lanes (a
- * third of the neighbour loads; the default); enable = 0: 64 interior columns
- * per wave, every neighbour loaded.  Applies to the column kernel; fused sweeps
+ * value at its own x (a third of the neighbour loads; the default); with one
+ * layer per thread each lane forms the x-offset partial sums of its own column
+ * and only those 3-vectors cross lanes, otherwise the x-neighbours come from
+ * the adjacent lanes; enable = 0: 64 interior columns per wave, every
+ * neighbour loaded.  Applies to the column kernel; fused sweeps
  * and the layer-staged variant's interior always use their own layouts.  OSAM_E_INVALID
  * for a bad id or an OpInf subdomain. */
 int32_t osam_set_fe_xshare(osam_ctx *ctx, int32_t sd, int32_t enable);
@@ -336,8 +339,8 @@ int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds, int32_t streams);
  * predictor) from the source's accepted state.  Results and iteration counts
  * equal those of the sequential launches.  FOM steps run the column kernel
  * with 512 threads per workgroup and kc (>= 1; 0 means 1) node layers per
- * thread, whatever osam_set_fe_launch chose (that choice still serves the
- * initial acceleration).  Combines with osam_set_graph (its streams setting is
+ * thread (FP64 contexts: always one), whatever osam_set_fe_launch chose (that
+ * choice still serves the initial acceleration).  Combines with osam_set_graph (its streams setting is
  * then unused).  At most 4 subdomains, 3 FOM and 2 OpInf: OSAM_E_INVALID here
  * when the context already has more, and from run when a sweep does not fit
  * (also when an OpInf step needs more than 64 KB of LDS).  enable = 0 (the

@@ -116,6 +116,14 @@ __device__ __forceinline__ void record_face(const FeArgs<T> &A, int b, int f, in
   for (int c = 0; c < 3; ++c) A.rec_s[so + (long long)c * A.nsch_nodes + nid0] = w[4][c];
 }
 
+template <typename T>
+__device__ __forceinline__ void record_face_value(const FeArgs<T> &A, int b, int f, int nid0, const T (&u)[3],
+                                                  long long rcol) {
+  const long long so = ((long long)b * A.rec_ncols + rcol) * 3 * A.nsch_nodes + (f ? A.face_off_hi : 0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) A.rec_s[so + (long long)c * A.nsch_nodes + nid0] = u[c];
+}
+
 // v0, a0 and the previous iterate (V1, or U0 at the first iteration) of one node.
 template <typename T, int MODE, bool UK>
 __device__ __forceinline__ void state_loads(const Roles<T> &R, const Strides &B, int k, int nid0, int n_iter,
@@ -142,6 +150,64 @@ __device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B
   else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
 }
 
+// One layer k of the x-shared interior layout in x-resolved form (xrow): lane j
+// forms S_dx(j) from its own x-centred values and node i takes S_-1 and S_+1
+// from lanes i-1 and i+1 (DPP wave shifts), so only 3-vectors cross lanes and no
+// 3x3 neighbourhood is held in registers.  Every lane of the wave takes part
+// (t: see fe_columns, XS).
+template <typename T, int MODE>
+__device__ __forceinline__ void fe_xs_one(const FeArgs<T> &A, int b, int t, int k, long long step, int iter,
+                                          double &acc_abs, double &acc_den) {
+  const int nx = A.nx, ny = A.ny, nxp = nx + 1, nzs = A.nzs;
+  const int n_iter = iter + 1;
+  const int nf = (ny - 1) * nxp, f = min(max(t, 0), nf - 1), lane = threadIdx.x & 63;
+  const int ix = f % nxp;
+  const bool act = t == f && lane >= 1 && lane <= 62 && ix >= 1 && ix < nx;
+  const Roles<T> R = roles<T, MODE>(A, b, step, n_iter);
+  const int nid0 = f + nxp;   // ix + nxp * iy with iy = 1 + f / nxp
+  const Strides B = strides(A);
+  long long rcol = 0, rbase = 0;
+  bool rec = false;
+  if (A.rec_every > 0) {
+    rcol = (MODE == kModeInit) ? 0 : (step + 1) / A.rec_every;
+    rec = rcol < A.rec_ncols && (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
+    rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
+  }
+  const unsigned voff = (unsigned)f * (unsigned)sizeof(T);   // (nid0 - nxp) bytes
+  T x[3][3][3], v0[3], a0[3], old[3];   // x[dz][dy][c] at this lane's x
+  load_rows<T>(x[0], k == 1 ? R.Flo : R.Pin, B, k - 1, voff);
+  load_rows<T>(x[1], R.Pin, B, k, voff);
+  load_rows<T>(x[2], k + 1 == nzs ? R.Fhi : R.Pin, B, k + 1, voff);
+  state_loads<T, MODE, true>(R, B, k, nid0, n_iter, v0, a0, old);
+  if (act && rec && A.rec_s) {
+    if (k == 1 && A.face_src[0] >= 0) record_face_value<T>(A, b, 0, nid0, x[0][1], rcol);
+    if (k == nzs - 1 && A.face_src[1] >= 0) record_face_value<T>(A, b, 1, nid0, x[2][1], rcol);
+  }
+  T ctr[3], sm[3], s0[3], sp[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ctr[c] = x[1][1][c];
+    sm[c] = s0[c] = sp[c] = T(0);
+  }
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      if (dz == 1 && dy == 1) continue;   // the node's own row: u_row(j) - u(j) = 0
+      const T du[3] = {x[dz][dy][0] - ctr[0], x[dz][dy][1] - ctr[1], x[dz][dy][2] - ctr[2]};
+      xrow<T>(A.cb, dz * 9 + dy * 3, du, sm);
+      xrow<T>(A.cb, dz * 9 + dy * 3 + 1, du, s0);
+      xrow<T>(A.cb, dz * 9 + dy * 3 + 2, du, sp);
+    }
+  T acc[3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+    acc[p] = x_combine(s0[p], lane_prev(sm[p]), lane_next(sp[p]), kx_diag(A.cb, p), lane_prev(ctr[p]), ctr[p],
+                       lane_next(ctr[p]));
+  if (!act) return;
+  update_node<T, MODE, true>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
+}
+
 // Column t (interior index, or entry of the boundary list), layers k0 .. k1-1
 // (ONE: the single layer k0, every load issued at once).  Interior waves have
 // one k0; a boundary wave may give each lane its own k0.
@@ -152,6 +218,10 @@ __device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B
 template <typename T, int MODE, bool INTERIOR, bool ONE, bool UK = INTERIOR, bool XS = false>
 __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int k0, long long step,
                                            int iter, double &acc_abs, double &acc_den) {
+  if constexpr (INTERIOR && XS && ONE) {
+    fe_xs_one<T, MODE>(A, b, t, k0, step, iter, acc_abs, acc_den);
+    return;
+  }
   const int nx = A.nx, ny = A.ny, nxp = nx + 1, npl = A.npl, nzs = A.nzs;
   const long long cs = A.cs;
   const int n_iter = iter + 1;
@@ -204,9 +274,18 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
       ctr[c] = w1[4][c];
       acc[c] = T(0);
     }
-    slab<T, INTERIOR, -1>(A.cb, C, w0, ctr, acc);
-    slab<T, INTERIOR, 0>(A.cb, C, w1, ctr, acc);
-    slab<T, INTERIOR, 1>(A.cb, C, w2, ctr, acc);
+    if (INTERIOR) {
+      T sm[3] = {T(0), T(0), T(0)}, s0[3] = {T(0), T(0), T(0)}, sp[3] = {T(0), T(0), T(0)};
+      xslab<T>(A.cb, 0, w0, w1, sm, s0, sp);
+      xslab<T>(A.cb, 1, w1, w1, sm, s0, sp);
+      xslab<T>(A.cb, 2, w2, w1, sm, s0, sp);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) acc[p] = x_combine(s0[p], sm[p], sp[p], kx_diag(A.cb, p), w1[3][p], ctr[p], w1[5][p]);
+    } else {
+      slab<T, false, -1>(A.cb, C, w0, ctr, acc);
+      slab<T, false, 0>(A.cb, C, w1, ctr, acc);
+      slab<T, false, 1>(A.cb, C, w2, ctr, acc);
+    }
     if (!act) return;
     update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (rec && A.rec_s) {
@@ -218,23 +297,35 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
 
   // rolling window: cur = layer k, nxt = layer k+1; acc holds the partial force
   // of layer k from layers k-1 and k until layer k+1 arrives.
-  T cur[9][3], nxt[9][3], acc[3], ctr[3];
+  // (interior: the x-resolved sums sm, s0, sp instead of acc until layer k+1 arrives)
+  T cur[9][3], nxt[9][3], acc[3], ctr[3], sm[3], s0[3], sp[3];
   layer<T, INTERIOR, XS>(nxt, k0 == 1 ? R.Flo : R.Pin, B, cs, k0 - 1, npl, nxp, ix, iy, nx, ny, nid0);
   layer<T, INTERIOR, XS>(cur, R.Pin, B, cs, k0, npl, nxp, ix, iy, nx, ny, nid0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     ctr[c] = cur[4][c];
-    acc[c] = T(0);
+    acc[c] = sm[c] = s0[c] = sp[c] = T(0);
   }
-  slab<T, INTERIOR, -1>(A.cb, C, nxt, ctr, acc);
-  slab<T, INTERIOR, 0>(A.cb, C, cur, ctr, acc);
+  if (INTERIOR) {
+    xslab<T>(A.cb, 0, nxt, cur, sm, s0, sp);
+    xslab<T>(A.cb, 1, cur, cur, sm, s0, sp);
+  } else {
+    slab<T, false, -1>(A.cb, C, nxt, ctr, acc);
+    slab<T, false, 0>(A.cb, C, cur, ctr, acc);
+  }
   if (act && rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, nxt, rcol);
 
   for (int k = k0; k < k1; ++k) {
     T v0[3], a0[3], old[3];
     state_loads<T, MODE, UK>(R, B, k, nid0, n_iter, v0, a0, old);
     layer<T, INTERIOR, XS>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
-    slab<T, INTERIOR, 1>(A.cb, C, nxt, ctr, acc);
+    if (INTERIOR) {
+      xslab<T>(A.cb, 2, nxt, cur, sm, s0, sp);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) acc[p] = x_combine(s0[p], sm[p], sp[p], kx_diag(A.cb, p), cur[3][p], ctr[p], cur[5][p]);
+    } else {
+      slab<T, false, 1>(A.cb, C, nxt, ctr, acc);
+    }
     if (act)
       update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
     if (k + 1 < k1) {
@@ -242,10 +333,15 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         ctr[c] = nxt[4][c];
-        acc[c] = T(0);
+        acc[c] = sm[c] = s0[c] = sp[c] = T(0);
       }
-      slab<T, INTERIOR, -1>(A.cb, C, cur, ctr, acc);
-      slab<T, INTERIOR, 0>(A.cb, C, nxt, ctr, acc);
+      if (INTERIOR) {
+        xslab<T>(A.cb, 0, cur, nxt, sm, s0, sp);
+        xslab<T>(A.cb, 1, nxt, nxt, sm, s0, sp);
+      } else {
+        slab<T, false, -1>(A.cb, C, cur, ctr, acc);
+        slab<T, false, 0>(A.cb, C, nxt, ctr, acc);
+      }
 #pragma unroll
       for (int n = 0; n < 9; ++n)
 #pragma unroll
@@ -253,6 +349,31 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
     }
   }
   if (act && rec && A.rec_s && k1 == nzs && A.face_src[1] >= 0) record_face<T>(A, b, 1, nid0, nxt, rcol);
+}
+
+// Fixed-order workgroup reduction of the two FP64 sums into the workgroup's
+// partial slot; the sweep's finisher adds the partials (no fences or atomics).
+template <typename T>
+__device__ __forceinline__ void store_partials(const FeArgs<T> &A, int b, int bx, double acc_abs, double acc_den) {
+  __shared__ double red[2][16];
+  acc_abs = wave_sum(acc_abs);
+  acc_den = wave_sum(acc_den);
+  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wid] = acc_abs;
+    red[1][wid] = acc_den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sd = 0.0;
+    for (int i = 0; i < nw; ++i) {
+      sa += red[0][i];
+      sd += red[1][i];
+    }
+    double *pp = A.partials + ((long long)b * A.part_stride + A.part_off + bx) * 2;
+    pp[0] = sa;
+    pp[1] = sd;
+  }
 }
 
 // PACKB: boundary waves may hold several layer chunks (A.bnd_l > 1, fused
@@ -340,28 +461,7 @@ __device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
     }
   }
   if (MODE == kModeInit) return;
-
-  // fixed-order workgroup reduction of the two FP64 sums; the sweep's finisher
-  // adds the workgroups' partials (no fences or atomics here)
-  __shared__ double red[2][16];
-  acc_abs = wave_sum(acc_abs);
-  acc_den = wave_sum(acc_den);
-  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) {
-    red[0][wid] = acc_abs;
-    red[1][wid] = acc_den;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double sa = 0.0, sd = 0.0;
-    for (int i = 0; i < nw; ++i) {
-      sa += red[0][i];
-      sd += red[1][i];
-    }
-    double *pp = A.partials + ((long long)b * A.part_stride + A.part_off + bx) * 2;
-    pp[0] = sa;
-    pp[1] = sd;
-  }
+  store_partials(A, b, bx, acc_abs, acc_den);
 }
 
 }  // namespace osam

@@ -127,6 +127,14 @@ __device__ __forceinline__ T wave_total(T x) {
 
 __device__ __forceinline__ double wave_sum64(double x) { return wave_total(x); }
 
+// The value held by lane l - 1 (wave_shr:1) or lane l + 1 (wave_shl:1), moved by
+// the vector ALU rather than an LDS permute.  Lane 0 (lane_prev) and lane 63
+// (lane_next) have no source and receive 0.  Every lane must be active.
+template <typename T>
+__device__ __forceinline__ T lane_prev(T x) { return dpp_src<0x138, 0xf, 0xf>(x); }
+template <typename T>
+__device__ __forceinline__ T lane_next(T x) { return dpp_src<0x130, 0xf, 0xf>(x); }
+
 // Sums of FOM subdomain k's partials, computed by one wave (lane 0 holds them).
 // Loads are issued in batches of U per lane before any is consumed.
 template <int U>

@@ -41,6 +41,34 @@ __host__ __device__ constexpr int box_index(int d27, int p, int q) {
 __host__ __device__ constexpr int box_sign(int d27, int p, int q) {
   return p == q ? 1 : d27_axis(d27, p) * d27_axis(d27, q);
 }
+// Row sums of the interior stencil along x: K = sum over the nine (dy, dz) of
+// C_(dx,dy,dz) for dx = +1 or -1.  Its entry (p, q) collects, with signs, the
+// box values listed below; kx_count returns the signed multiplicity of box value
+// i in it.  Off the diagonal the signs cancel in pairs (edges and corners carry
+// s_p s_q, odd in dy or dz), so K is diagonal: K_pp = F[0][p] + 2 E[2][p] +
+// 2 E[1][p] + 4 V[p] (checked at compile time below).
+__host__ __device__ constexpr int kx_count(int dx, int p, int q, int i) {
+  int n = 0;
+  for (int dz = 0; dz < 3; ++dz)
+    for (int dy = 0; dy < 3; ++dy) {
+      const int d27 = dz * 9 + dy * 3 + (dx + 1);
+      if (box_index(d27, p, q) == i) n += box_sign(d27, p, q);
+    }
+  return n;
+}
+__host__ __device__ constexpr bool kx_is_diagonal_sum() {
+  for (int dx = -1; dx <= 1; dx += 2)
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q)
+        for (int i = 0; i < 27; ++i) {
+          int want = 0;
+          if (p == q) want = (i == p) + 2 * (i == 15 + p) + 2 * (i == 12 + p) + 4 * (i == 21 + p);
+          if (kx_count(dx, p, q, i) != want) return false;
+        }
+  return true;
+}
+static_assert(kx_is_diagonal_sum(), "x row sums of the interior stencil");
+
 // XCD-aware order: hardware hands workgroup i to XCD i % 8; give every XCD a
 // contiguous range of logical blocks (chunk-major, i.e. neighbouring layers).
 __device__ __forceinline__ int xcd_block(int bid, int n) {
@@ -117,24 +145,82 @@ __device__ __forceinline__ void load_layer_uniform(T (&w)[9][3], const T *P, con
 // layer L and takes its x-neighbours from the adjacent lanes.  voff = (nid -
 // nxp) * sizeof(T) >= 0.  Every lane of the wave must take part; a lane whose
 // adjacent lane is not its x-neighbour (lanes 0 and 63) must not use the result.
+// The x-centred values x[ry][c] of rows dy = ry - 1 of layer L at this lane's node.
 template <typename T>
-__device__ __forceinline__ void load_layer_xshare(T (&w)[9][3], const T *P, const Strides &B, int L,
-                                                  unsigned voff) {
+__device__ __forceinline__ void load_rows(T (&x)[3][3], const T *P, const Strides &B, int L, unsigned voff) {
   const Field<T> F(P);
   const unsigned lo = (unsigned)L * B.npl;
-  T x[3][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int ry = 0; ry < 3; ++ry) x[ry][c] = F.ld(voff, lo + c * B.cs + ry * B.nxp);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_layer_xshare(T (&w)[9][3], const T *P, const Strides &B, int L,
+                                                  unsigned voff) {
+  T x[3][3];
+  load_rows<T>(x, P, B, L, voff);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int ry = 0; ry < 3; ++ry) {
       w[3 * ry + 1][c] = x[ry][c];
-      w[3 * ry][c] = __shfl_up(x[ry][c], 1, 64);
-      w[3 * ry + 2][c] = __shfl_down(x[ry][c], 1, 64);
+      w[3 * ry][c] = lane_prev(x[ry][c]);
+      w[3 * ry + 2][c] = lane_next(x[ry][c]);
     }
+}
+
+// Interior nodes in x-resolved form.  With d = (dx, dy, dz) and u_{i+dx} the
+// node of the same row at x offset dx, u_{i+d} - u_i = (u_{i+d} - u_{i+dx}) +
+// (u_{i+dx} - u_i), so
+//   sum_d C_d (u_{i+d} - u_i) = (S_0(i) + S_-1(i-1) + S_+1(i+1))
+//                               + K ((u_{i-1} - u_i) + (u_{i+1} - u_i)),
+// S_dx(j) = sum over the (dy, dz) rows of C_(dx,dy,dz) (u_row(j) - u(j)) formed
+// at column j from its own values, K the x row sum of the blocks (diagonal:
+// kx_is_diagonal_sum).  Every interior path adds in this order (rows in (dz, dy)
+// order into S_-1, S_0, S_+1, then x_combine), so all layouts give the same bits;
+// the x-shared one forms S_dx where the values are and moves only 3-vectors
+// across lanes.
+//
+// s[p] += sum_q C_(d27)[p][q] d[q] over the box values (structural zeros skipped).
+template <typename T>
+__device__ __forceinline__ void xrow(const T *cb, int d27, const T (&d)[3], T (&s)[3]) {
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int bi = box_index(d27, p, q);
+      if (bi < 0) continue;
+      if (box_sign(d27, p, q) > 0) s[p] += cb[bi] * d[q];
+      else s[p] -= cb[bi] * d[q];
+    }
+}
+// Rows (dy = 0, 1, 2 - 1) of z-slab dz = DZ - 1 into S_-1 (sm), S_0 (s0), S_+1 (sp),
+// from the slab's full 3x3 neighbourhood w and the centre slab wc (the three
+// columns' own values wc[3], wc[4], wc[5]).
+template <typename T>
+__device__ __forceinline__ void xslab(const T *cb, int DZ, const T (&w)[9][3], const T (&wc)[9][3], T (&sm)[3],
+                                      T (&s0)[3], T (&sp)[3]) {
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy) {
+    if (DZ == 1 && dy == 1) continue;   // the node's own row: u_row - u = 0
+#pragma unroll
+    for (int rx = 0; rx < 3; ++rx) {
+      const T d[3] = {w[3 * dy + rx][0] - wc[3 + rx][0], w[3 * dy + rx][1] - wc[3 + rx][1],
+                      w[3 * dy + rx][2] - wc[3 + rx][2]};
+      xrow<T>(cb, DZ * 9 + dy * 3 + rx, d, rx == 0 ? sm : (rx == 1 ? s0 : sp));
+    }
+  }
+}
+// The x row sum K (diagonal entry p) and the final combination.
+template <typename T>
+__device__ __forceinline__ T kx_diag(const T *cb, int p) {
+  return cb[p] + T(2) * (cb[15 + p] + cb[12 + p]) + T(4) * cb[21 + p];
+}
+template <typename T>
+__device__ __forceinline__ T x_combine(T s0, T sm, T sp, T kx, T um, T u, T up) {
+  return (s0 + sm + sp) + kx * ((um - u) + (up - u));
 }
 
 // Contribution of one z-slab (dz = DZ) of the 27-point stencil to the node

@@ -26,13 +26,17 @@ __global__ void __launch_bounds__(kRomThreads) sweep_kernel(SweepArgs<T> S) {
   else fe_body<T, kModeStep, FE == 1, true, false>(S.fe[S.fe_idx[i]], x);
 }
 
+// FP64: one FE layer per thread only (fe != 2).
 template <typename T, int V>
-static void launch_sweep_v(const SweepArgs<T> &S, dim3 grid, int fe, size_t smem, hipStream_t s, hipEvent_t ev0,
+static bool launch_sweep_v(const SweepArgs<T> &S, dim3 grid, int fe, size_t smem, hipStream_t s, hipEvent_t ev0,
                            hipEvent_t ev1) {
   const dim3 block(kRomThreads);
   if (fe == 0) hipExtLaunchKernelGGL((sweep_kernel<T, 0, V>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
   else if (fe == 1) hipExtLaunchKernelGGL((sweep_kernel<T, 1, V>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
-  else hipExtLaunchKernelGGL((sweep_kernel<T, 2, V>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
+  else if constexpr (sizeof(T) == 4)
+    hipExtLaunchKernelGGL((sweep_kernel<T, 2, V>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
+  else return false;
+  return true;
 }
 
 template <typename T>
@@ -47,15 +51,17 @@ hipError_t launch_sweep(const SweepArgs<T> &S, int batch, bool one, size_t smem,
   const int fe = nfe == 0 ? 0 : (one ? 1 : 2);
   if (total <= 0 || smem > 65536) return hipErrorInvalidValue;
   const dim3 grid(total, batch);
+  bool ok;
   if constexpr (sizeof(T) == 8) {   // the batched parts are FP32 only
-    if (v & kRomNoPushRegs) launch_sweep_v<T, kRomNoPushRegs>(S, grid, fe, smem, s, ev0, ev1);
-    else launch_sweep_v<T, 0>(S, grid, fe, smem, s, ev0, ev1);
+    if (v & kRomNoPushRegs) ok = launch_sweep_v<T, kRomNoPushRegs>(S, grid, fe, smem, s, ev0, ev1);
+    else ok = launch_sweep_v<T, 0>(S, grid, fe, smem, s, ev0, ev1);
   } else {
-    if (v == 3) launch_sweep_v<T, 3>(S, grid, fe, smem, s, ev0, ev1);
-    else if (v == 2) launch_sweep_v<T, 2>(S, grid, fe, smem, s, ev0, ev1);
-    else if (v == 1) launch_sweep_v<T, 1>(S, grid, fe, smem, s, ev0, ev1);
-    else launch_sweep_v<T, 0>(S, grid, fe, smem, s, ev0, ev1);
+    if (v == 3) ok = launch_sweep_v<T, 3>(S, grid, fe, smem, s, ev0, ev1);
+    else if (v == 2) ok = launch_sweep_v<T, 2>(S, grid, fe, smem, s, ev0, ev1);
+    else if (v == 1) ok = launch_sweep_v<T, 1>(S, grid, fe, smem, s, ev0, ev1);
+    else ok = launch_sweep_v<T, 0>(S, grid, fe, smem, s, ev0, ev1);
   }
+  if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

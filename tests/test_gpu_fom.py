@@ -221,11 +221,15 @@ def test_layer_staged_fe_variant_f32(kc, lateral):
 @pytest.mark.parametrize("cross", [(6, 5), (70, 3)])
 def test_fe_xshare_layout_is_bitwise_identical(cross, precision, kc, fusion_kc):
     """The interior layout with x-neighbours taken from adjacent lanes (osam_set_fe_xshare)
-    gives the same bits as the default layout: records of u and the Schwarz faces of three
-    slabs, batch of 2, iteration counts; with FE launches (one and three layers per thread)
-    and inside fused sweeps.  Rows of 71 nodes (70 x 3) wrap inside waves; FP64 is also
-    checked against the oracle.  Cubic elements of 1/36 m (Bar default lengths would make the
-    70 x 3 elements needle-shaped and the explicit step unstable)."""
+    against the layout that loads every neighbour: the same bits (every interior path adds
+    the stencil in one x-resolved order, whether the x-offset partial sums are formed where
+    the values are and moved across lanes, with one layer per thread, or formed from whole
+    neighbourhoods): records of u and the Schwarz faces of three slabs, batch of 2, iteration
+    counts; with FE launches (one and three layers per thread) and inside fused sweeps.
+    Rows of 71 nodes (70 x 3) wrap
+    inside waves; FP64 is also checked against the oracle.  Cubic elements of 1/36 m (Bar
+    default lengths would make the 70 x 3 elements needle-shaped and the explicit step
+    unstable)."""
     nx, ny = cross
     h = 1.0 / 36   # cubic elements (the explicit step size assumes them)
     bar = Bar(nx, ny, 36, Lx=nx * h, Ly=ny * h, Lz=36 * h)

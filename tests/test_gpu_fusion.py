@@ -6,7 +6,7 @@ iteration counts, with host launches and with graph replays (eager work between 
 for FOM-FOM, FOM-OpInf, OpInf-FOM-OpInf (batch 20, fused and batched OpInf paths) and
 OpInf-OpInf (the OpInf source's predictor formed from its accepted state; batched path with
 both f0 contractions in one launch), in FP64 and FP32, with one and three node layers per FE
-thread.  FP64 FOM-FOM is also checked
+thread (FP64 contexts run one whatever kc asks).  FP64 FOM-FOM is also checked
 against the oracle.
 """
 import numpy as np
