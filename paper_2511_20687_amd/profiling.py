@@ -147,7 +147,7 @@ CASES = {
               "FE step kernel, 24x24x240 bar, Omega_1 268125 FE DOFs, FP32, launch 256 threads x 1 layer"),
     "bar64": ("large_", "fe_kernel<float, 0", 28 * 16 * 4322175, "fe_kernel_bar64x64x640_b16_traffic.txt", "fe",
               "FE step kernel, 64x64x640 bar, middle FOM subdomain 4322175 FE DOFs x 16 instances, FP32, "
-              "launch 64 threads x 8 layers"),
+              "launch 256 threads x 1 layer, x-shared interior rows"),
     "bar24_sweep": ("sweep_", "sweep_kernel<float, 1", _SWEEP24_BYTES, "sweep_kernel_bar24x24x240_traffic.txt",
                     "sweep", "fused sweep kernel (FE step of Omega_1, 268125 FE DOFs, + OpInf step r=40), "
                     "24x24x240 bar, FP32, 512 threads x 1 layer"),
@@ -168,7 +168,7 @@ def summarize(outdir: str, case: str = "bar24") -> None:
     sw = kib / wc if wc else None
     fetch_b = ff * sf * 1024 if (ff and sf) else None
     write_b = wf * sw * 1024 if (wf and sw) else None
-    args = {"bar24": "workload 100", "bar24_sweep": "workload 100 fused", "bar64": "large 4 64 8"}[case]
+    args = {"bar24": "workload 100", "bar24_sweep": "workload 100 fused", "bar64": "large 4 256 1"}[case]
     lines = [
         f"# HBM traffic (rocprofv3 --pmc), {title}",
         "# commands, from the repository root after `cd /tmp && export TMPDIR=/tmp` (OUT: an output folder):",
