@@ -51,7 +51,8 @@ def build_context(w, precision, batch=1):
 
 def opts_for(w):
     from paper_2511_20687_amd import osam
-    return osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter)
+    return osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter,
+                        guess=w.guess)
 
 
 def train_and_learn(w, pulse, precision):
@@ -261,6 +262,7 @@ def main():
                    "subdomains": "z node layers 0-144 FOM, 96-240 linear OpInf", "r": learned["r"],
                    "r_s": learned["r_s"], "lambda_star": learned["lambda_star"],
                    "controller_steps_per_run": n, "dt": w.dt, "train_snapshots": w.train_steps,
+                   "schwarz_initial_guess": "predictor" if w.guess else "hold",
                    "parallelism": "single GPU"},
         "schwarz_iters_per_step": iters / n,
         "fom_fom_steps_per_s": fom_fom_value,
@@ -350,7 +352,7 @@ def cpu_baseline(w, pulse, n_steps, learned):
         u0 = pulse.u0(w.bar)
         st = cp.initial_states(u0, np.zeros_like(u0))
         t_setup = time.perf_counter() - t0
-        opts = SchwarzOptions(tol_abs=w.tol_abs, tol_rel=w.tol_rel)
+        opts = SchwarzOptions(tol_abs=w.tol_abs, tol_rel=w.tol_rel, guess="predictor" if w.guess else "hold")
         t0 = time.perf_counter()
         its = 0
         for _ in range(n_steps):

@@ -347,9 +347,10 @@ int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds, int32_t streams);
  * default) returns to one launch per subdomain. */
 int32_t osam_set_fusion(osam_ctx *ctx, int32_t enable, int32_t kc);
 
-/* Launch-configuration autotuner.  Times trial runs of trial_steps controller
- * steps (after 2 warm-up steps) from the context's current state with `opts`,
- * and keeps, one coordinate at a time, the fastest: the FE launch shape of each
+/* Launch-configuration autotuner.  Times trial runs of trial_steps and
+ * 2 trial_steps controller steps (after 2 warm-up steps) from the context's
+ * current state with `opts`, takes their difference per step (what every run
+ * pays once, such as graph capture, cancels), and keeps, one coordinate at a time, the fastest: the FE launch shape of each
  * FOM subdomain (osam_set_fe_launch: 256/1, 128/1, 64/1, 64/2, 256/8, 64/8 and,
  * where it applies, the layer-staged 1024 with 4, 8, 16 layers; the column
  * kernel shapes with both interior layouts of osam_set_fe_xshare), the OpInf

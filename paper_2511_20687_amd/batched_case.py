@@ -37,7 +37,8 @@ def _train_and_learn(w, log):
     for b, p in enumerate(draw_pulses(w.seed, ntr, skip=256, s=w.pulse_width)):
         u0 = p.u0(w.bar)
         ctx.set_initial(b, u0, np.zeros_like(u0))
-    opts = osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter)
+    opts = osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter,
+                        guess=w.guess)
     t0 = time.perf_counter()
     ctx.run(stride * (T - 1), opts)
     torch.cuda.synchronize()
@@ -73,11 +74,13 @@ def run(w=None, n_acc=16, fom_steps=100, every=100, log=print) -> dict:
     from paper_2511_20687_amd.inputs import CFG3
     w = w or CFG3
     B, n = w.batch, w.steps
-    opts = osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter)
+    opts = osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter,
+                        guess=w.guess)
     ops, learned, t_train, t_learn = _train_and_learn(w, log)
     dev = "cuda:0"
     ncol = n // every + 1
-    result = dict(workload=w.name, batch=B, steps=n, train_s=t_train, learn_s=t_learn,
+    result = dict(workload=w.name, batch=B, steps=n, schwarz_initial_guess="predictor" if w.guess else "hold",
+                  train_s=t_train, learn_s=t_learn,
                   learned={str(k): v for k, v in learned.items()})
     lifted = {}
     for prec in ("f32", "f32_bf16h"):
@@ -87,7 +90,7 @@ def run(w=None, n_acc=16, fom_steps=100, every=100, log=print) -> dict:
             o = ops[sd]
             ctx.set_opinf(sd, o["Phi"], o["PhiS"], o["A"], o["H"], o["B"], o["c"])
         _initial(ctx, w, B)
-        tune = ctx.autotune(trial_steps=20, opts=opts)
+        tune = ctx.autotune(trial_steps=50, opts=opts)
         recs = [torch.zeros((B, ncol, learned[sd]["r"]), device=dev) for sd in sds]
         for sd in sds:
             ctx.set_record(sd, every, ncol, u=recs[sd])

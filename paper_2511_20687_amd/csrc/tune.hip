@@ -83,15 +83,21 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
       return st;
     }
   }
-  // wall time per controller step of a trial (after a short warm-up)
+  // wall time per controller step of a trial (after a short warm-up): runs of n and
+  // 2n steps, the difference per step, so that what every run pays once (graph
+  // capture and instantiation, host set-up) cancels
   auto trial = [&](double *ms) -> int32_t {
     int32_t s = run(2, op, nullptr);
     if (s) return s;
     HIPCHK(hipStreamSynchronize(stream));
-    const auto t0 = std::chrono::steady_clock::now();
-    if ((s = run(n, op, nullptr))) return s;
-    HIPCHK(hipStreamSynchronize(stream));
-    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / (double)n;
+    double t[2];
+    for (int k = 0; k < 2; ++k) {
+      const auto t0 = std::chrono::steady_clock::now();
+      if ((s = run(n * (k + 1), op, nullptr))) return s;
+      HIPCHK(hipStreamSynchronize(stream));
+      t[k] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    *ms = std::max(t[1] - t[0], 1e-3 * t[1]) / (double)n;
     return OSAM_OK;
   };
   graph_rounds = 0;

@@ -209,6 +209,10 @@ class Workload:
     tol_rel: float = 1.0e-12
     min_iter: int = 2
     max_iter: int = 32
+    # initial guess of the Schwarz iteration: 0 HOLD (the neighbour's accepted value at
+    # t_{k-1}), 1 PREDICTOR (its Newmark displacement predictor at t_k, which the explicit
+    # scheme's step does not change: the iteration then converges at its second iterate)
+    guess: int = 0
     # displacement components held at zero on the lateral faces: x and y, as for
     # the effectively-1D bar of Sec. 5.1 (empty = traction-free lateral faces)
     lateral_fix: Tuple[int, ...] = (0, 1)
@@ -231,10 +235,10 @@ class Workload:
 CFG1 = Workload("fom_fom_bar_4x4x40_f64", Bar(4, 4, 40), 2, ("fom", "fom"), 1000, "f64",
                 pulse_width=0.05)
 CFG2 = Workload("fom_opinf_bar_24x24x240_r40", Bar(24, 24, 240), 2, ("fom", "opinf"), 5000,
-                "f32", form="linear", r=40, seed=2, train_steps=2000, tol_rel=1.0e-6)
+                "f32", form="linear", r=40, seed=2, train_steps=2000, tol_rel=1.0e-6, guess=1)
 CFG3 = Workload("opinf_opinf_bar_48x48x480_r100_b256", Bar(48, 48, 480), 2, ("opinf", "opinf"),
                 2000, "f32", form="quadratic", r=100, batch=256, seed=3, train_steps=2000,
-                train_runs=4, train_stride=4, tol_rel=1.0e-6, pulse_width=0.05)
+                train_runs=4, train_stride=4, tol_rel=1.0e-6, pulse_width=0.05, guess=1)
 CFG4 = Workload("adjoint_fom_qopinf_bar_24x24x240_r60", Bar(24, 24, 240), 2, ("fom", "opinf"),
                 2000, "f32", form="quadratic", r=60, seed=4, train_steps=2000, checkpoint=100,
                 tol_rel=1.0e-6)

@@ -58,6 +58,49 @@ def test_fused_sweeps_equal_sequential_launches(kinds, precision, batch, n, rom_
             assert rel_err(got[i][0][:, lib_index_of(m)], oref["u"][i]) <= 1e-10
 
 
+@pytest.mark.parametrize("kinds,precision,batch,n,rom_path", [
+    (("fom", "fom"), "f64", 1, 120, 0),
+    (("fom", "opinf"), "f32", 1, 137, 0),
+    (("opinf", "fom", "opinf"), "f32", 20, 61, 2),
+    (("opinf", "opinf"), "f64", 2, 90, 0),
+])
+def test_fused_sweeps_with_predictor_guess(kinds, precision, batch, n, rom_path):
+    """PREDICTOR initial guess (the neighbour's Newmark displacement predictor at t_k): fused
+    sweeps and graph replays give the bits and iteration counts of the sequential launches;
+    the explicit step leaves that displacement unchanged, so every step converges at its
+    second iterate and ends where HOLD's iteration ends (same bits).  FP64 FOM-FOM is also
+    checked against the oracle with the same guess."""
+    from paper_2511_20687_amd import osam
+    bar = Bar(3, 3, 36)
+    ctx, sds, layers = _context(kinds, precision, batch, bar)
+    if rom_path:
+        for i, k in enumerate(kinds):
+            if k == "opinf":
+                ctx.set_rom_path(sds[i], rom_path)
+    pred = osam.Options(guess=1)
+    print(f"[fusion predictor {kinds} {precision} B={batch} n={n} path={rom_path}]", flush=True)
+    ref, info_ref = _run(ctx, sds, bar, batch, n, 0, precision, opts=pred)
+    assert [x["total_iters"] for x in info_ref] == [2 * n] * batch
+    hold, _ = _run(ctx, sds, bar, batch, n, 0, precision)
+    for i in range(len(sds)):
+        assert np.array_equal(hold[i], ref[i]), i
+    for graph in (0, 16):
+        ctx.set_fusion(True, 1)
+        got, info = _run(ctx, sds, bar, batch, n, graph, precision, opts=pred)
+        ctx.set_fusion(False)
+        for i in range(len(sds)):
+            assert np.array_equal(got[i], ref[i]), (graph, i)
+        assert [x["total_iters"] for x in info] == [x["total_iters"] for x in info_ref]
+    if kinds == ("fom", "fom") and precision == "f64":
+        from oracle.schwarz import SchwarzOptions
+        u0 = draw_pulses(71, 1, s=0.06)[0].u0(bar)
+        models, oref = oracle_fom_coupled(bar, layers, bar.explicit_dt(), u0, np.zeros_like(u0), n,
+                                          opts=SchwarzOptions(guess="predictor"))
+        assert int(oref["iters"].sum()) == 2 * n
+        for i, m in enumerate(models):
+            assert rel_err(ref[i][0][:, lib_index_of(m)], oref["u"][i]) <= 1e-10
+
+
 def test_fusion_rejects_too_many_subdomains():
     from paper_2511_20687_amd import osam
     bar = Bar(3, 3, 60)

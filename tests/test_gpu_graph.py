@@ -36,7 +36,7 @@ def _context(kinds, precision, batch, bar, seed=61):
     return ctx, sds, layers
 
 
-def _run(ctx, sds, bar, batch, n, graph, precision, streams=1):
+def _run(ctx, sds, bar, batch, n, graph, precision, streams=1, opts=None):
     import torch
     dtp = torch.float64 if precision == "f64" else torch.float32
     recs = []
@@ -50,7 +50,7 @@ def _run(ctx, sds, bar, batch, n, graph, precision, streams=1):
         u0 = p.u0(bar)
         ctx.set_initial(b, u0, np.zeros_like(u0))
     ctx.set_graph(graph, streams)
-    info = ctx.run(n)
+    info = ctx.run(n) if opts is None else ctx.run(n, opts)
     ctx.sync()
     return [t.cpu().numpy() for t in recs], info
 
