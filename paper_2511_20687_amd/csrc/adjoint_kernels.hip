@@ -43,13 +43,13 @@ __global__ void __launch_bounds__(256) stencil_kernel(SlabGeo<T> G, const T *__r
   if (k > 0) {
     T wl[9][3];
     load_layer<T, false>(wl, in, G.cs, k - 1, G.npl, nxp, ix, iy, G.nx, G.ny);
-    slab<T, false, -1>(nullptr, C, wl, ctr, acc);
+    slab<T, -1>(C, wl, ctr, acc);
   }
-  slab<T, false, 0>(nullptr, C, w, ctr, acc);
+  slab<T, 0>(C, w, ctr, acc);
   if (k < G.nzs) {
     T wh[9][3];
     load_layer<T, false>(wh, in, G.cs, k + 1, G.npl, nxp, ix, iy, G.nx, G.ny);
-    slab<T, false, 1>(nullptr, C, wh, ctr, acc);
+    slab<T, 1>(C, wh, ctr, acc);
   }
   const T sc = SCALED ? G.mass[cse] : T(1);
   const long long id = (long long)k * G.npl + col;

@@ -141,7 +141,8 @@ __global__ void __launch_bounds__(kLdsThreads) fe_lds_kernel(FeArgs<float> A) {
 #pragma unroll 1
     for (int w = tid; w < A.n_int; w += kLdsThreads) {
       const int nid0 = nnid;
-      float v0[3], a0[3], old[3], ctr[3], acc[3] = {0.f, 0.f, 0.f};
+      float v0[3], a0[3], old[3], ctr[3], acc[3], wc[9][3];
+      float sm[3] = {0.f, 0.f, 0.f}, s0[3] = {0.f, 0.f, 0.f}, sp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         v0[c] = nv0[c];
@@ -152,8 +153,13 @@ __global__ void __launch_bounds__(kLdsThreads) fe_lds_kernel(FeArgs<float> A) {
         nnid = column(w + kLdsThreads);
         state_loads<float, MODE, true>(R, B, k, nnid, n_iter, nv0, na0, nold);
       }
+      // the centre row of layer k (columns x-1, x, x+1), then the x-resolved sums slab by slab
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ctr[c] = Sc[c * npl + nid0];
+      for (int rx = 0; rx < 3; ++rx)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) wc[3 + rx][c] = Sc[c * npl + nid0 + rx - 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ctr[c] = wc[4][c];
 #pragma unroll
       for (int dz = -1; dz <= 1; ++dz) {
         const float *S = (dz < 0 ? Sl : (dz == 0 ? Sc : Sh)) + nid0;
@@ -162,11 +168,11 @@ __global__ void __launch_bounds__(kLdsThreads) fe_lds_kernel(FeArgs<float> A) {
         for (int n = 0; n < 9; ++n)
 #pragma unroll
           for (int c = 0; c < 3; ++c) wv[n][c] = S[c * npl + (n / 3 - 1) * nxp + (n % 3 - 1)];
-        if (dz < 0) slab<float, true, -1>(A.cb, nullptr, wv, ctr, acc);
-        else if (dz == 0) slab<float, true, 0>(A.cb, nullptr, wv, ctr, acc);
-        else slab<float, true, 1>(A.cb, nullptr, wv, ctr, acc);
+        xslab<float>(A.cb, dz + 1, wv, wc, sm, s0, sp);
         __builtin_amdgcn_sched_barrier(0);   // one slab of neighbours live at a time
       }
+#pragma unroll
+      for (int p = 0; p < 3; ++p) acc[p] = x_combine(s0[p], sm[p], sp[p], kx_diag(A.cb, p), wc[3][p], ctr[p], wc[5][p]);
       if (rec && A.rec_s && ((k == 1 && A.face_src[0] >= 0) || (k == nzs - 1 && A.face_src[1] >= 0))) {
         float wf[9][3];
         const float *S = k == 1 ? Sl : Sh;

@@ -223,13 +223,11 @@ __device__ __forceinline__ T x_combine(T s0, T sm, T sp, T kx, T um, T u, T up) 
   return (s0 + sm + sp) + kx * ((um - u) + (up - u));
 }
 
-// Contribution of one z-slab (dz = DZ) of the 27-point stencil to the node
-// whose own value is ctr: acc += sum_n C_(dx,dy,DZ) (w[n] - ctr).
-// cb: the interior block's 27 distinct values (kernel arguments), C: this
-// node's case block (memory), used when !INTERIOR.
-template <typename T, bool INTERIOR, int DZ>
-__device__ __forceinline__ void slab(const T *cb, const T *C, const T (&w)[9][3], const T (&ctr)[3],
-                                     T (&acc)[3]) {
+// Contribution of one z-slab (dz = DZ) of the 27-point stencil to a node of
+// the boundary columns (interior nodes: xslab) whose own value is ctr:
+// acc += sum_n C_(dx,dy,DZ) (w[n] - ctr), C the node's case block (memory).
+template <typename T, int DZ>
+__device__ __forceinline__ void slab(const T *C, const T (&w)[9][3], const T (&ctr)[3], T (&acc)[3]) {
 #pragma unroll
   for (int n = 0; n < 9; ++n) {
     const int d27 = (DZ + 1) * 9 + n;
@@ -237,19 +235,9 @@ __device__ __forceinline__ void slab(const T *cb, const T *C, const T (&w)[9][3]
     const int d26 = d27 < 13 ? d27 : d27 - 1;
     const T du[3] = {w[n][0] - ctr[0], w[n][1] - ctr[1], w[n][2] - ctr[2]};
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < 3; ++p)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        if (INTERIOR) {
-          const int bi = box_index(d27, p, q);
-          if (bi < 0) continue;
-          if (box_sign(d27, p, q) > 0) acc[p] += cb[bi] * du[q];
-          else acc[p] -= cb[bi] * du[q];
-        } else {
-          acc[p] += C[d26 * 9 + p * 3 + q] * du[q];
-        }
-      }
-    }
+      for (int q = 0; q < 3; ++q) acc[p] += C[d26 * 9 + p * 3 + q] * du[q];
   }
 }
 
