@@ -195,11 +195,16 @@ int32_t osam_get_opinf(osam_ctx *ctx, int32_t sd, double *Phi, double *PhiS, dou
  * sum_i ||du_i + dt_i dv_i||^2 < tol_abs^2 or that sum < tol_rel^2 sum_i
  * ||u_i + dt_i v_i||^2 (free DOFs; reduced coordinates for OpInf).  At most
  * max_iter iterations per controller step; reaching the cap is not an error.
- * guess: initial data of a neighbour not yet advanced in the step. */
+ * guess: initial data of a neighbour not yet advanced in the step.
+ * additive: 0 = multiplicative sweeps (Alg. 1: each subdomain takes the newest
+ * iterate of its neighbours), 1 = the additive variant of Remark additive_sam
+ * (each subdomain takes its neighbours' iterates of the previous iteration, so
+ * the first iteration of a step starts every face from `guess`). */
 typedef struct {
   double tol_abs, tol_rel;
   int32_t min_iter, max_iter;
   int32_t guess;
+  int32_t additive;
 } osam_schwarz_opts;
 
 /* Per-instance progress and statistics. */
@@ -215,7 +220,8 @@ typedef struct {
 } osam_instance_info;
 
 /* One controller step of Alg. 1 for every instance (multiplicative sweeps over
- * the subdomains in index order until Eq. conv_criterion).  info: [batch] or NULL. */
+ * the subdomains in index order, or the additive variant, until Eq.
+ * conv_criterion).  info: [batch] or NULL. */
 int32_t schwarz_step(osam_ctx *ctx, const osam_schwarz_opts *opts, osam_instance_info *info);
 
 /* n_steps controller steps for every instance; the host does not wait on

@@ -5,7 +5,9 @@ Newmark step per controller step here); within each, Alg. 1 iterates the
 subdomain problems in index order (Gauss-Seidel, Remark additive_sam: the
 multiplicative variant), each taking Dirichlet data on its Schwarz boundary
 from the newest iterate of the neighbour that contains it, until the
-criterion Eq. conv_criterion holds.  Sec. 4.2 (OpInf-FOM, OpInf-OpInf) uses
+criterion Eq. conv_criterion holds.  The additive variant of the same remark
+(additive=True) solves the subdomains of an iteration independently: each takes
+its data from the neighbours' iterates of the previous iteration (Jacobi).  Sec. 4.2 (OpInf-FOM, OpInf-OpInf) uses
 the same loop with ROM subdomains (transfer = pointwise projection of the
 lifted field, then Phi_S^T restriction inside the ROM).
 
@@ -90,6 +92,7 @@ class SchwarzOptions:
     min_iter: int = 2
     max_iter: int = 32
     guess: str = "hold"          # "hold" | "predictor"
+    additive: bool = False       # True: every subdomain reads the previous iteration's iterates
 
 
 @dataclass
@@ -152,8 +155,11 @@ class Coupled:
         prev: List[Optional[object]] = list(start)
         info = StepInfo(0, False, float('nan'), float('nan'))
         for n in range(1, opts.max_iter + 1):
+            # multiplicative: the newest iterates, updated as the sweep goes; additive: those of
+            # the previous iteration for every subdomain
+            src = list(latest) if opts.additive else latest
             for i in range(S):
-                s = self.schwarz_data(i, latest, start, opts.guess)
+                s = self.schwarz_data(i, src, start, opts.guess)
                 new = self.models[i].step(start[i], s)
                 prev[i] = latest[i] if latest[i] is not None else start[i]
                 latest[i] = new

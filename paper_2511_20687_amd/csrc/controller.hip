@@ -1041,7 +1041,8 @@ int32_t Ctx::launch_round_fused(const Opts &o) {
 
 int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_info *info) {
   if (!(op.tol_abs >= 0) || !(op.tol_rel >= 0) || op.min_iter < 1 || op.max_iter < op.min_iter ||
-      op.max_iter > 1000000 || (op.guess != OSAM_GUESS_HOLD && op.guess != OSAM_GUESS_PREDICTOR))
+      op.max_iter > 1000000 || (op.guess != OSAM_GUESS_HOLD && op.guess != OSAM_GUESS_PREDICTOR) ||
+      (op.additive != 0 && op.additive != 1))
     return fail(OSAM_E_INVALID, "bad Schwarz options");
   int32_t st = couple();
   if (st) return st;
@@ -1056,6 +1057,7 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
   o.min_iter = op.min_iter;
   o.max_iter = op.max_iter;
   o.guess = op.guess;
+  o.additive = op.additive;
   o.nsd = (int)sds.size();
   bool any = false;
   for (int b = 0; b < batch; ++b) {

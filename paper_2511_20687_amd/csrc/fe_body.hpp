@@ -37,14 +37,17 @@ __device__ __forceinline__ Roles<T> roles(const FeArgs<T> &A, int b, long long s
   R.V1 = A.v[1 - s2] + boff;
   R.A0 = A.a[s2] + boff;
   R.A1 = A.a[1 - s2] + boff;
-  // Face layers: HOLD at iteration 1 when the source comes later in the sweep
-  // reads the neighbour's value at t_{k-1} (role U0), otherwise at t_k (role P).
+  // Face layers: HOLD at iteration 1 when the source has not advanced in this
+  // iteration (it comes later in the sweep, or every source in the additive
+  // variant) reads the neighbour's value at t_{k-1} (role U0), otherwise at t_k
+  // (role P; with the explicit step a source's t_k displacement is fixed by its
+  // state at t_{k-1}, so later iterations read the same data in either variant).
   R.Pin = (MODE == kModeInit) ? R.U0 : R.P;
   R.Flo = R.Pin;
   R.Fhi = R.Pin;
   if (MODE == kModeStep && n_iter == 1 && A.opts.guess == 0) {
-    if (A.face_src[0] > A.sd) R.Flo = R.U0;
-    if (A.face_src[1] > A.sd) R.Fhi = R.U0;
+    if (A.face_src[0] > A.sd || A.opts.additive) R.Flo = R.U0;
+    if (A.face_src[1] > A.sd || A.opts.additive) R.Fhi = R.U0;
   }
   return R;
 }

@@ -31,6 +31,7 @@ constexpr int kNeedInit = 4;
 struct Opts {
   double tol_abs2, tol_rel2;
   int min_iter, max_iter, guess, nsd;
+  int additive;   // 1: every face reads the previous iteration (the first: `guess`)
 };
 
 // Convergence decision of Eq. conv_criterion after the last subdomain of a

@@ -196,7 +196,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     for (int kk = 0; kk < 12; ++kk) part[kk] = 0.0;
     if (small_face) {
       const RomFaceIn<T> &f = A.fin[0];
-      const bool hold = n_iter == 1 && f.src_sd > A.sd && A.opts.guess == 0;
+      const bool hold = n_iter == 1 && (f.src_sd > A.sd || A.opts.additive) && A.opts.guess == 0;
       const int ro = hold ? (int)(step % 3) : (int)((step + 1) % 3);
 #pragma unroll
       for (int d = 0; d < kFaceDofs; ++d) {
@@ -222,7 +222,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   }
   for (int fi = small_face ? 1 : 0; fi < A.nfaces; ++fi) {
     const RomFaceIn<T> &f = A.fin[fi];
-    const bool hold = n_iter == 1 && f.src_sd > A.sd && A.opts.guess == 0;
+    const bool hold = n_iter == 1 && (f.src_sd > A.sd || A.opts.additive) && A.opts.guess == 0;
     if (f.type == kFaceFom) {
       // g^_k += sum_m Phi_S[m, k] s_m : threads over the face DOFs, 8 modes per pass
       const T *src = f.sface[hold ? (int)(step % 3) : (int)((step + 1) % 3)] + (long long)b * f.n;
@@ -255,7 +255,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
       // the source's predictor at t_k when it is not read back from this sweep:
       // fused sweeps, and the first sweep of a step before the source has run
       // (PREDICTOR guess with the source later in the sweep)
-      const bool pred = !hold && (f.pred || (n_iter == 1 && f.src_sd > A.sd));
+      const bool pred = !hold && (f.pred || (n_iter == 1 && (f.src_sd > A.sd || A.opts.additive)));
       const T *qs = f.src_q[hold || pred ? s2 : 1 - s2] + so;
       for (int k = wid; k < rs; k += kRomWaves) {
         double v = 0.0;

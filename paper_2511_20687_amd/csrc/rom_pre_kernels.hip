@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(kPreThreads) rom_ghat_kernel(RomPreArgs P) {
       const long long n = P.fn[f];
       const long long per = (n + P.gs - 1) / P.gs;
       const long long m0 = gsi * per, m1 = min(n, m0 + per);
-      const bool hold = n_iter == 1 && P.fsrc[f] > P.sd && P.opts.guess == 0;
+      const bool hold = n_iter == 1 && (P.fsrc[f] > P.sd || P.opts.additive) && P.opts.guess == 0;
       const float *src = P.sface[f][hold ? (int)(step % 3) : (int)((step + 1) % 3)] + (long long)b * n;
       for (long long m = m0 + tid; m < m1; m += kPreThreads) {
         const float sv = src[m];

@@ -81,7 +81,7 @@ class Tuning(C.Structure):
 
 class SchwarzOpts(C.Structure):
     _fields_ = [("tol_abs", C.c_double), ("tol_rel", C.c_double), ("min_iter", C.c_int32),
-                ("max_iter", C.c_int32), ("guess", C.c_int32)]
+                ("max_iter", C.c_int32), ("guess", C.c_int32), ("additive", C.c_int32)]
 
 
 class InstanceInfo(C.Structure):
@@ -192,9 +192,10 @@ class Options:
     min_iter: int = 2
     max_iter: int = 32
     guess: int = 0          # 0 HOLD, 1 PREDICTOR
+    additive: bool = False  # the additive variant (neighbours' iterates of the previous iteration)
 
     def c(self) -> SchwarzOpts:
-        return SchwarzOpts(self.tol_abs, self.tol_rel, self.min_iter, self.max_iter, self.guess)
+        return SchwarzOpts(self.tol_abs, self.tol_rel, self.min_iter, self.max_iter, self.guess, int(self.additive))
 
 
 class Context:

@@ -20,16 +20,18 @@ def _free_ref(m, sd, traj):
     return np.array([st.u[sdofs] for st in traj])
 
 
-@pytest.mark.parametrize("S,guess", [(2, "hold"), (2, "predictor"), (3, "hold")])
-def test_explicit_schwarz_recovers_single_domain(S, guess):
+@pytest.mark.parametrize("S,guess,additive", [(2, "hold", False), (2, "predictor", False), (3, "hold", False),
+                                              (3, "hold", True), (3, "predictor", True)])
+def test_explicit_schwarz_recovers_single_domain(S, guess, additive):
     """Conforming meshes, explicit Newmark: the converged FOM-FOM iterate equals the
-    single-domain FE solution (every free row of K is complete in some subdomain)."""
+    single-domain FE solution (every free row of K is complete in some subdomain), for the
+    multiplicative and the additive variant."""
     bar = Bar(3, 3, 30, Lx=0.1, Ly=0.1, Lz=1.0)
     dt = bar.explicit_dt()
     u0 = gaussian_pulse_u(bar, 1e-3, 0.3, 0.05)
     models = [FomModel(bar, lo, hi, dt) for lo, hi in slab_layers(bar.nz, S)]
     n = 150
-    out = Coupled(models).run(u0, np.zeros_like(u0), n, SchwarzOptions(guess=guess))
+    out = Coupled(models).run(u0, np.zeros_like(u0), n, SchwarzOptions(guess=guess, additive=additive))
     sd, traj = _single_ref(bar, dt, u0, n)
     for i, m in enumerate(models):
         assert rel_l2(out["u"][i], _free_ref(m, sd, traj)) <= 1e-13
@@ -57,6 +59,38 @@ def test_implicit_schwarz_converges_geometrically_to_single_domain():
     assert out["iters"].max() > 3            # genuinely iterative
     for i, m in enumerate(models):
         assert rel_l2(out["u"][i], _free_ref(m, sd, traj)) <= 1e-9
+
+
+def test_additive_schwarz_converges_to_the_same_fixed_point_more_slowly():
+    """Additive variant (Remark additive_sam), implicit Newmark with a narrow overlap: the
+    iteration still converges to the single-domain solution, the subdomains of an iteration
+    see only the previous iteration's data (with two subdomains the second one's additive
+    iterate 2n is its multiplicative iterate n), and it needs more iterations than the
+    multiplicative variant (Jacobi vs Gauss-Seidel: close to twice as many for two
+    subdomains)."""
+    bar = Bar(2, 2, 24, Lx=0.1, Ly=0.1, Lz=1.0)
+    dt = 8.0 * bar.explicit_dt()
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.4, 0.08)
+    models = [FomModel(bar, lo, hi, dt, beta=0.25) for lo, hi in ((0, 13), (11, 24))]
+    n = 30
+    mult = Coupled(models).run(u0, np.zeros_like(u0), n, SchwarzOptions(tol_abs=1e-14, tol_rel=1e-14, max_iter=200))
+    add = Coupled(models).run(u0, np.zeros_like(u0), n,
+                              SchwarzOptions(tol_abs=1e-14, tol_rel=1e-14, max_iter=200, additive=True))
+    sd, traj = _single_ref(bar, dt, u0, n, beta=0.25)
+    assert np.all(add["converged"]) and np.all(mult["converged"])
+    for i, m in enumerate(models):
+        assert rel_l2(add["u"][i], _free_ref(m, sd, traj)) <= 1e-9
+    ratio = add["iters"].sum() / mult["iters"].sum()
+    assert 1.4 <= ratio <= 2.3, ratio
+    # one controller step with a fixed iteration count: additive iterate 2n of subdomain 1
+    # pairs with multiplicative iterate n (two subdomains: Jacobi's even iterates of one
+    # subdomain follow the Gauss-Seidel sequence)
+    c = Coupled(models)
+    st = c.initial_states(u0, np.zeros_like(u0))
+    fixed = dict(tol_abs=0.0, tol_rel=0.0, min_iter=1)
+    a4, _ = c.step(st, SchwarzOptions(max_iter=4, additive=True, **fixed))
+    m2, _ = c.step(st, SchwarzOptions(max_iter=2, **fixed))
+    assert rel_l2(a4[1].u, m2[1].u) <= 1e-14
 
 
 def test_cap_and_unreachable_tolerance():
