@@ -112,3 +112,47 @@ def test_one_dimensional_reduction():
                                             + layer_vals[k[free_nodes] - 1])
     assert np.allclose(a[free_nodes, 2], expect, rtol=1e-10, atol=1e-10 * np.abs(expect).max())
     assert np.abs(a[:, :2]).max() == 0.0
+
+
+def test_interior_stencil_x_rows_sum_to_a_diagonal_block_and_resolve_in_x():
+    """The x-resolved form of the interior stencil that the FE kernels add in: on a uniform
+    box grid (unequal hx, hy, hz) the nine blocks K_(+-1,dy,dz) of an interior node sum to a
+    diagonal block (the off-diagonal edge and corner entries cancel in pairs), the same for
+    dx = +1 and -1, and for any
+    field sum_d K_d (u_{i+d} - u_i) = S_0(i) + S_-1(i-1) + S_+1(i+1)
+    + K_x ((u_{i-1} - u_i) + (u_{i+1} - u_i)), with S_dx(j) = sum over the (dy, dz) rows of
+    K_(dx,dy,dz) (u_row(j) - u(j)) formed at column j and K_x that row sum."""
+    bar = Bar(6, 5, 6, Lx=0.12, Ly=0.2, Lz=0.45)
+    mesh = SubMesh(bar, 0, bar.nz)
+    K, _ = assemble(mesh)
+    K = K.tocsr()
+
+    def block(n, m):
+        return K[3 * n:3 * n + 3, 3 * m:3 * m + 3].toarray()
+
+    i, j, k = 3, 2, 3
+    node = mesh.node_id(i, j, k)
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    C = {d: block(node, mesh.node_id(i + d[0], j + d[1], k + d[2])) for d in offs if d != (0, 0, 0)}
+    scale = np.abs(C[(1, 0, 0)]).max()
+    for dx in (-1, 1):
+        Kx = sum(C[(dx, dy, dz)] for dz in (-1, 0, 1) for dy in (-1, 0, 1))
+        assert np.abs(Kx - np.diag(np.diag(Kx))).max() <= 1e-12 * scale
+        assert np.all(np.abs(np.diag(Kx)) > 1e-3 * scale)
+    Kx = sum(C[(1, dy, dz)] for dz in (-1, 0, 1) for dy in (-1, 0, 1))
+    Kxm = sum(C[(-1, dy, dz)] for dz in (-1, 0, 1) for dy in (-1, 0, 1))
+    assert np.abs(Kxm - Kx).max() <= 1e-12 * scale   # one K serves both sides
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((mesh.n_nodes, 3))
+
+    def U(a, b, c):
+        return u[mesh.node_id(a, b, c)]
+
+    direct = sum(C[d] @ (U(i + d[0], j + d[1], k + d[2]) - U(i, j, k)) for d in C)
+
+    def S(dx, col):   # formed at column col from its own values
+        return sum(C[(dx, dy, dz)] @ (U(col, j + dy, k + dz) - U(col, j, k))
+                   for dz in (-1, 0, 1) for dy in (-1, 0, 1) if (dy, dz) != (0, 0))
+
+    resolved = S(0, i) + S(-1, i - 1) + S(1, i + 1) + Kx @ ((U(i - 1, j, k) - U(i, j, k)) + (U(i + 1, j, k) - U(i, j, k)))
+    assert np.abs(resolved - direct).max() <= 1e-12 * np.abs(direct).max()
