@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched OpInf-OpInf comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-large-fe", action="store_true", help="skip the 64x64x640 FE step timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -240,6 +241,11 @@ def main():
     if not args.no_adjoint:
         adjoint = adjoint_timing(_log)
 
+    # ---- the FE step at the large bar's size (HBM-bound) ----
+    large_fe = None
+    if not args.no_large_fe:
+        large_fe = large_fe_timing(_log)
+
     # ---- CPU oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -290,8 +296,51 @@ def main():
         "cpu_baseline": cpu,
         "batched_opinf_opinf": batched,
         "adjoint": adjoint,
+        "large_fe": large_fe,
     }
     print(json.dumps(line), flush=True)
+
+
+def large_fe_timing(log):
+    """The FE step kernel at the 64x64x640 bar's size: three FOM slabs, 16 instances of seeded
+    multi-pulse initial velocities, the middle slab's launches timed with HIP events over a few
+    controller steps (the launch shape the library picks by default).  A failure is reported in
+    the result instead of ending the bench."""
+    import torch
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import CFG5, draw_multi_pulse_v
+    from paper_2511_20687_amd.profiling import read_traffic
+    w = CFG5
+    try:
+        ctx = osam.Context(0, "f32", w.batch)
+        sds = osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
+        mid = sds[1]
+        u0 = np.zeros((3, w.bar.n_nodes))
+        for b, mp in enumerate(draw_multi_pulse_v(w.seed, w.batch)):
+            ctx.set_initial(b, u0, mp.v0(w.bar))
+        opts = osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, guess=w.guess)
+        ctx.run(2, opts)
+        ctx.set_timing(True)
+        ctx.run(6, opts)
+        torch.cuda.synchronize()
+        ms, launches = ctx.get_timing(mid)
+        ctx.set_timing(False)
+        us = 1e3 * ms / max(launches, 1)
+        dofs = ctx.sizes(mid)["n_free"] * w.batch
+        alg = FE_BYTES_PER_DOF * dofs
+        gbs = alg / (us * 1e-6) / 1e9
+        traffic, src = read_traffic("bar64")
+        block, kc = ctx.get_fe_launch(mid)
+        del ctx
+        torch.cuda.empty_cache()
+        log(f"large FE step: {us:.1f} us per launch, {gbs:.0f} GB/s algorithmic")
+        return {"workload": "fom_bar_64x64x640_b16 (middle of three FOM slabs, FE step)", "fe_kernel_avg_us": us,
+                "launches": launches, "dofs_per_launch": dofs, "algorithmic_bytes_per_launch": alg,
+                "achieved_GBs": gbs, "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+                "traffic": traffic, "traffic_source": src, "launch_shape": [block, kc]}
+    except Exception as e:   # reported, not fatal: the headline line must still print
+        log(f"large FE step failed: {e!r}")
+        return {"error": repr(e)}
 
 
 def adjoint_timing(log):
