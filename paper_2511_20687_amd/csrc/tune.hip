@@ -97,7 +97,8 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
       HIPCHK(hipStreamSynchronize(stream));
       t[k] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
-    *ms = std::max(t[1] - t[0], 1e-3 * t[1]) / (double)n;
+    // noise can make the longer run look no longer: then the plain per-step time of it
+    *ms = t[1] > t[0] ? (t[1] - t[0]) / (double)n : t[1] / (2.0 * (double)n);
     return OSAM_OK;
   };
   graph_rounds = 0;
