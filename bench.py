@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--no-large-fe", action="store_true", help="skip the 64x64x640 FE step timing")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(every instance and subdomain runs on one device); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
