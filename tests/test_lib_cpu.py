@@ -36,3 +36,37 @@ def test_binding_declares_the_same_symbols():
     assert sorted(osam.EXPORTED) == _declared()
     lib = osam.load_library()
     assert lib.osam_version() >= 10000
+
+
+# header struct -> ctypes class of the binding
+_STRUCTS = {"osam_subdomain_desc": "SubdomainDesc", "osam_record": "Record", "osam_opinf_desc": "OpinfDesc",
+            "osam_schwarz_opts": "SchwarzOpts", "osam_instance_info": "InstanceInfo", "osam_misfit": "Misfit",
+            "osam_grads": "Grads", "osam_tuning": "Tuning"}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every struct the binding marshals has the header's size and field offsets (a C program
+    built against include/osam.h prints them; gcc, no GPU)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    from paper_2511_20687_amd import osam
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "osam.h"', 'int main(void) {']
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(osam, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.rsplit(" ", 1)[0].split(" ")): int(l.rsplit(" ", 1)[1]) for l in out if l}
+    for cname, pyname in _STRUCTS.items():
+        cls = getattr(osam, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
