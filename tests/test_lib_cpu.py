@@ -70,3 +70,17 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for field, _ in cls._fields_:
             assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libosam.so not built")
+def test_binding_argument_counts_match_the_header():
+    """Each declared call takes as many arguments in the binding as in the header."""
+    from paper_2511_20687_amd import osam
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    protos = dict(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(([^)]*)\)\s*;", txt, flags=re.M))
+    lib = osam.load_library()
+    for name in osam.EXPORTED:
+        params = protos[name].strip()
+        n = 0 if params in ("", "void") else params.count(",") + 1
+        argtypes = getattr(lib, name).argtypes
+        assert len(argtypes or ()) == n, (name, n, argtypes)
