@@ -49,6 +49,15 @@ def build_context(w, precision, batch=1):
     return ctx
 
 
+def _guarded(name, fn):
+    """A secondary leg: its failure is reported in the JSON line instead of ending the bench."""
+    try:
+        return fn()
+    except Exception as e:
+        _log(f"{name} failed: {e!r}")
+        return {"error": repr(e)}
+
+
 def opts_for(w):
     from paper_2511_20687_amd import osam
     return osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, min_iter=w.min_iter, max_iter=w.max_iter,
@@ -234,12 +243,12 @@ def main():
         from paper_2511_20687_amd import batched_case
         del ctx, ff, ff2
         torch.cuda.empty_cache()
-        batched = batched_case.run(log=_log)
+        batched = _guarded("batched OpInf-OpInf", lambda: batched_case.run(log=_log))
 
     # ---- adjoint of the coupled rollout, 24x24x240 FOM + quadratic OpInf r=60 ----
     adjoint = None
     if not args.no_adjoint:
-        adjoint = adjoint_timing(_log)
+        adjoint = _guarded("adjoint", lambda: adjoint_timing(_log))
 
     # ---- the FE step at the large bar's size (HBM-bound) ----
     large_fe = None
@@ -249,7 +258,7 @@ def main():
     # ---- CPU oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, pulse, args.cpu_steps, learned)
+        cpu = _guarded("CPU baseline", lambda: cpu_baseline(w, pulse, args.cpu_steps, learned))
 
     line = {
         "metric": "coupled Schwarz steps/s (FOM-OpInf hybrid, <=1e-3 rel err target vs FOM-FOM)",
