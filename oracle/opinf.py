@@ -13,16 +13,22 @@ and reduced Schwarz data S^ = Phi_S^T S (r_S x T), find
     unit stride they equal the second difference quotient of U);
   * compressed quadratic columns q_i q_j, i <= j (width r(r+1)/2);
   * lambda is one scalar for all blocks (Remark on per-operator lambda: not
-    used).  The paper fixes neither units nor a normalisation of the data, yet
-    its grid 10^-10..1 only regularises operators of order one: in SI units the
-    stiffness block alone is of order (c/h)^2 ~ 1e11 and every grid value
-    would force it to zero.  The fit is therefore posed in step-normalised
-    time tau = t/dt and amplitude-normalised coordinates q/alpha, s^/alpha,
-    alpha = the largest ||q_j||_2 over all training columns:
+    used), applied in units of the training amplitude alpha = the largest
+    ||q_j||_2 over all training columns.  The paper fixes no units for its
+    absolute grid 10^-10..1, while the eigenvalues of D^T D scale with powers of
+    the length unit (about T alpha^2 for the linear and boundary columns, T alpha^4
+    for the quadratic ones; alpha ~ 1e-3 m here), so in raw SI data most of the
+    grid would shrink the operators and the choice would depend on the unit.
+    The fit is posed on the data scaled to unit amplitude (q/alpha, s^/alpha),
+    with time in steps (tau = t/dt):
         argmin || dt^2 Qdd/alpha - At Q/alpha - Ht (Q/alpha)^(2) - Bt S^/alpha - ct 1^T ||^2
                + lambda ||[At Ht Bt ct]||^2,
-    and mapped back with A = At/dt^2, H = Ht/(dt^2 alpha), B = Bt/dt^2,
-    c = alpha ct/dt^2 (dt = 1, alpha = 1 is the raw fit); no centering;
+    mapped back with A = At/dt^2, H = Ht/(dt^2 alpha), B = Bt/dt^2,
+    c = alpha ct/dt^2.  In physical units this is the raw ridge problem with
+    the penalty lambda (alpha^2 ||A||^2 + alpha^4 ||H||^2 + alpha^2 ||B||^2 + ||c||^2):
+    dt cancels from the minimiser (the time scaling only keeps the arithmetic
+    of order one) and a change of length unit maps the operators exactly
+    (dt = 1, alpha = 1 is the raw fit); no centering;
   * when T < p the objective still has a unique minimiser (lambda > 0).
 The ridge problem is solved by its definition as an ordinary least-squares
 problem on the stacked system [D; sqrt(lambda) I] X = [Qdd^T; 0] (library SVD

@@ -156,3 +156,50 @@ def test_interior_stencil_x_rows_sum_to_a_diagonal_block_and_resolve_in_x():
 
     resolved = S(0, i) + S(-1, i - 1) + S(1, i + 1) + Kx @ ((U(i - 1, j, k) - U(i, j, k)) + (U(i + 1, j, k) - U(i, j, k)))
     assert np.abs(resolved - direct).max() <= 1e-12 * np.abs(direct).max()
+
+
+@pytest.mark.parametrize("a,b", [(0, 1), (1, 0), (1, 2), (2, 1), (0, 2), (2, 0)])
+def test_simple_shear_energy(small, a, b):
+    """Simple shear u_a = g x_b (engineering shear strain g, App. A.1): the strain energy
+    1/2 u^T K u equals 1/2 mu g^2 V, the energy density of sigma = lam tr(eps) I + 2 mu eps
+    for a traceless strain with eps_ab = eps_ba = g/2.  A shear modulus taken as 2 mu on the
+    engineering strains (or mu/2 on tensor ones) doubles (halves) the energy."""
+    bar, mesh, K, m = small
+    lam, mu = lame(bar.E, bar.nu)
+    g = 1e-3
+    u = np.zeros((mesh.n_nodes, 3))
+    u[:, a] = g * mesh.X[:, b]
+    W = 0.5 * u.ravel() @ (K @ u.ravel())
+    V = bar.Lx * bar.Ly * bar.Lz
+    assert np.isclose(W, 0.5 * mu * g * g * V, rtol=1e-12)
+
+
+def test_shear_traction_on_end_face(small):
+    """u_x = g z: the nodal forces on the face z = L sum to the shear traction times the
+    area, sigma_xz A = mu g Lx Ly, and vanish in y and z (on z = 0 the opposite force)."""
+    bar, mesh, K, m = small
+    lam, mu = lame(bar.E, bar.nu)
+    g = 2e-4
+    u = np.zeros((mesh.n_nodes, 3))
+    u[:, 0] = g * mesh.X[:, 2]
+    f = (K @ u.ravel()).reshape(-1, 3)
+    top = mesh.ijk[:, 2] == bar.nz
+    bot = mesh.ijk[:, 2] == 0
+    area = bar.Lx * bar.Ly
+    assert np.isclose(f[top, 0].sum(), mu * g * area, rtol=1e-12)
+    assert np.isclose(f[bot, 0].sum(), -mu * g * area, rtol=1e-12)
+    assert abs(f[top, 1].sum()) <= 1e-12 * mu * g * area
+    assert abs(f[top, 2].sum()) <= 1e-12 * mu * g * area
+
+
+def test_general_uniform_strain_energy(small):
+    """Any uniform strain eps (symmetric part of a displacement gradient G): energy
+    1/2 u^T K u = 1/2 (lam tr(eps)^2 + 2 mu eps:eps) V (App. A.1 energy density)."""
+    bar, mesh, K, m = small
+    lam, mu = lame(bar.E, bar.nu)
+    G = np.array([[0.3, -1.1, 0.4], [0.2, -0.5, 0.9], [-0.7, 0.6, 0.8]]) * 1e-4
+    u = mesh.X @ G.T
+    eps = 0.5 * (G + G.T)
+    W = 0.5 * u.ravel() @ (K @ u.ravel())
+    V = bar.Lx * bar.Ly * bar.Lz
+    assert np.isclose(W, 0.5 * (lam * np.trace(eps) ** 2 + 2 * mu * np.sum(eps * eps)) * V, rtol=1e-12)

@@ -252,3 +252,47 @@ def test_strided_rollout_equals_every_stride_th_step_of_the_full_rollout():
     assert np.allclose(strided, full[:, ::stride], rtol=1e-12, atol=1e-14)
     # and stride 1 is the plain rule
     assert np.array_equal(rollout_frozen(ops, q0, qd0, qdd0, S_full, full_n, dt, stride=1), full)
+
+
+@pytest.mark.parametrize("with_c", [False, True])
+def test_normalised_fit_is_a_block_weighted_ridge_independent_of_dt(with_c):
+    """What the normalised fit is, in physical units: the ridge problem on the raw data with
+    the penalty lambda (alpha^2 ||A||^2 + alpha^4 ||H||^2 + alpha^2 ||B||^2 + ||c||^2)
+    (Eq. quadratic_opinf with one scalar lambda, posed in units of the training amplitude).
+    dt cancels from the minimiser, and a change of the length unit by s maps the operators as
+    A -> A, B -> B, H -> H / s, c -> s c (lambda keeps its meaning).  The weighted problem is
+    solved here by its own stacked system, not through fit()."""
+    r, rs, T = 4, 2, 60
+    Q = 3e-4 * random_normal(51, (r, T))
+    Sh = 2e-4 * random_normal(52, (rs, T))
+    Qdd = 5e6 * random_normal(53, (r, T))
+    lam = 1e-3
+    alpha = amplitude_scale([Q])
+    o1 = fit([Q], [Qdd], [Sh], lam, form="quadratic", with_c=with_c, dt=2.5e-6, alpha=alpha)
+    o2 = fit([Q], [Qdd], [Sh], lam, form="quadratic", with_c=with_c, dt=7.0e-3, alpha=alpha)
+    for x, y in ((o1.A, o2.A), (o1.H, o2.H), (o1.B, o2.B)) + (((o1.c, o2.c),) if with_c else ()):
+        assert np.abs(x - y).max() <= 1e-9 * np.abs(x).max()
+    # the block-weighted ridge written out directly
+    D = data_matrix(Q, Sh, "quadratic", with_c)
+    w = r * (r + 1) // 2
+    weights = np.concatenate([np.full(r, alpha), np.full(w, alpha ** 2), np.full(rs, alpha)]
+                             + ([np.ones(1)] if with_c else []))
+    p = D.shape[1]
+    Daug = np.vstack([D, np.sqrt(lam) * np.diag(weights)])
+    Raug = np.vstack([Qdd.T, np.zeros((p, r))])
+    X, *_ = np.linalg.lstsq(Daug, Raug, rcond=None)
+    O = X.T
+    assert np.abs(O[:, :r] - o1.A).max() <= 1e-8 * np.abs(o1.A).max()
+    assert np.abs(O[:, r:r + w] - o1.H).max() <= 1e-8 * np.abs(o1.H).max()
+    assert np.abs(O[:, r + w:r + w + rs] - o1.B).max() <= 1e-8 * np.abs(o1.B).max()
+    if with_c:
+        assert np.abs(O[:, -1] - o1.c).max() <= 1e-8 * np.abs(o1.c).max()
+    # unit change (metres -> millimetres): every datum scales by s, alpha too
+    s = 1e3
+    o3 = fit([s * Q], [s * Qdd], [s * Sh], lam, form="quadratic", with_c=with_c, dt=2.5e-6,
+             alpha=amplitude_scale([s * Q]))
+    assert np.abs(o3.A - o1.A).max() <= 1e-8 * np.abs(o1.A).max()
+    assert np.abs(o3.B - o1.B).max() <= 1e-8 * np.abs(o1.B).max()
+    assert np.abs(s * o3.H - o1.H).max() <= 1e-8 * np.abs(o1.H).max()
+    if with_c:
+        assert np.abs(o3.c - s * o1.c).max() <= 1e-8 * np.abs(s * o1.c).max()
