@@ -124,7 +124,8 @@ int32_t osam_set_reduced(osam_ctx *ctx, int32_t sd, int32_t inst, const double *
 
 /* Current accepted state of subdomain sd, instance inst, as host float64
  * [3][n_nodes] arrays (any may be NULL).  OpInf subdomains return the lifted
- * field Phi q on free DOFs, the imposed Schwarz data and zero Dirichlet DOFs. */
+ * fields Phi q, Phi q', Phi q'' (Sec. 4.2), lifted on the device, on free DOFs and
+ * zero on Schwarz and Dirichlet DOFs. */
 int32_t osam_get_state(osam_ctx *ctx, int32_t sd, int32_t inst, double *u, double *v, double *a);
 /* Reduced state (q, q', q'') of an OpInf subdomain, host float64 [r] each. */
 int32_t osam_get_reduced(osam_ctx *ctx, int32_t sd, int32_t inst, double *q, double *qd,
@@ -221,7 +222,9 @@ typedef struct {
 
 /* One controller step of Alg. 1 for every instance (multiplicative sweeps over
  * the subdomains in index order, or the additive variant, until Eq.
- * conv_criterion).  info: [batch] or NULL. */
+ * conv_criterion).  info: [batch] or NULL.  The sweeps are launched from the host
+ * even in graph mode (osam_set_graph), so the call does no more sweeps than the step
+ * needs; results equal those of run(ctx, 1, ...). */
 int32_t schwarz_step(osam_ctx *ctx, const osam_schwarz_opts *opts, osam_instance_info *info);
 
 /* n_steps controller steps for every instance; the host does not wait on

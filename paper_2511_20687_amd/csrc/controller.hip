@@ -1039,7 +1039,7 @@ int32_t Ctx::launch_round_fused(const Opts &o) {
   return OSAM_OK;
 }
 
-int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_info *info) {
+int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_info *info, bool host_sweeps) {
   if (!(op.tol_abs >= 0) || !(op.tol_rel >= 0) || op.min_iter < 1 || op.max_iter < op.min_iter ||
       op.max_iter > 1000000 || (op.guess != OSAM_GUESS_HOLD && op.guess != OSAM_GUESS_PREDICTOR) ||
       (op.additive != 0 && op.additive != 1))
@@ -1080,7 +1080,9 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
     }
   } guard;
   hipGraphExec_t &gexec = guard.g;
-  const bool graph = graph_rounds > 0 && !timing && any;
+  // a single controller step (schwarz_step) launches its sweeps from the host: a captured
+  // graph would replay graph_rounds sweeps for it
+  const bool graph = graph_rounds > 0 && !timing && any && !host_sweeps;
   if (graph) {
     if (!aux) {
       HIPCHK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));

@@ -531,7 +531,10 @@ int32_t osam_get_opinf(osam_ctx *c, int32_t sdi, double *Phi, double *PhiS, doub
 }
 
 int32_t schwarz_step(osam_ctx *c, const osam_schwarz_opts *opts, osam_instance_info *info) {
-  return run(c, 1, opts, info);
+  if (!c || !opts) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  ctx->err.clear();
+  return ctx->run(1, *opts, info, /*host_sweeps=*/true);
 }
 
 int32_t run(osam_ctx *c, int64_t n_steps, const osam_schwarz_opts *opts, osam_instance_info *info) {

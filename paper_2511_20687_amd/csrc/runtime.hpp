@@ -131,7 +131,7 @@ struct Ctx {
   int32_t install_opinf_device(int sd, const OpinfHost &oh, const double *phi_dev);
   int32_t phi_layer_rows(Subdomain &s, int layer, std::vector<double> &out);
   int32_t sync_status();
-  int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info);
+  int32_t run(int64_t n_steps, const osam_schwarz_opts &o, osam_instance_info *info, bool host_sweeps = false);
   int32_t launch_round(const Opts &o);
   // graph mode: rounds replayed from a captured HIP graph, the FOM and OpInf
   // kernels of a round on two streams, the decision in the finisher kernel

@@ -202,20 +202,45 @@ class Context:
     """One libosam context: a batch of coupled-subdomain instances on one GPU."""
 
     def __init__(self, device: int = 0, precision: str = "f64", batch: int = 1, stream=None):
+        """stream: None = torch's current stream on `device` when the context is created
+        (if that is torch's default stream, a stream of the context's own, ordered after
+        torch's current stream on entry to every call that reads device tensors and before
+        it on return); a torch.cuda.Stream or a raw hipStream_t handle (int) otherwise."""
+        import torch
         self.lib = load_library()
         self.precision = precision
         self.device = device
         self.batch = batch
+        if stream is None:
+            cur = torch.cuda.current_stream(device)
+            stream = cur if cur.cuda_stream != 0 else torch.cuda.Stream(device)
+        elif isinstance(stream, int):
+            stream = torch.cuda.ExternalStream(stream, device=device)
+        self.stream = stream
         h = C.c_void_p()
         prec = {"f64": 0, "f32": 1, "f32_bf16h": 2}[precision]
-        st = self.lib.osam_ctx_create(C.byref(h), device, prec, batch,
-                                      None if stream is None else C.c_void_p(stream))
+        st = self.lib.osam_ctx_create(C.byref(h), device, prec, batch, C.c_void_p(stream.cuda_stream))
         if st != OSAM_OK:
             raise OsamError(st, "osam_ctx_create failed")
         self.h = h
         self.n_sd = 0
 
     # -- helpers -----------------------------------------------------------
+    def _order_in(self):
+        """The context's stream waits for what torch has queued on its current stream
+        (device inputs written by torch)."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def _order_out(self):
+        """Torch's current stream waits for the context's work (device outputs)."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
+
     def _check(self, st: int):
         if st != OSAM_OK:
             raise OsamError(st, self.lib.osam_last_error(self.h).decode())
@@ -277,8 +302,38 @@ class Context:
         self._check(self.lib.osam_get_reduced(self.h, sd, inst, _dptr(q), _dptr(qd), _dptr(qdd)))
         return q, qd, qdd
 
+    def _torch_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def _check_buffer(self, name: str, t, shape):
+        """A device buffer handed to the library: a contiguous torch tensor on this context's
+        GPU, in the context precision, of exactly ``shape`` (the library writes or reads that
+        many elements through the raw pointer)."""
+        if t is None:
+            return
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+        if t.dtype != self._torch_dtype():
+            raise ValueError(f"{name}: dtype {t.dtype} does not match the context precision {self.precision}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+        if tuple(t.shape) != tuple(int(x) for x in shape):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_cuda or (t.device.index if t.device.index is not None else 0) != self.device:
+            raise ValueError(f"{name}: must live on cuda:{self.device}, is on {t.device}")
+
     def set_record(self, sd: int, every: int, n_cols: int, u=None, a=None, s=None):
-        """u, a, s: torch device tensors [batch][n_cols][len] in the context precision."""
+        """u, a, s: torch device tensors [batch][n_cols][len] in the context precision:
+        u and a of a FOM subdomain len = free DOFs, u of an OpInf subdomain len = r (q),
+        s len = Schwarz DOFs."""
+        if every > 0:
+            z = self.sizes(sd)
+            lu = z["r"] if z["r"] > 0 else z["n_free"]
+            self._check_buffer("u", u, (self.batch, n_cols, lu))
+            self._check_buffer("a", a, (self.batch, n_cols, z["n_free"]))
+            self._check_buffer("s", s, (self.batch, n_cols, z["n_sch"]))
         self._keep = getattr(self, "_keep", {})
         self._keep[sd] = (u, a, s)
         rec = Record(every, n_cols, _devptr(u), _devptr(a), _devptr(s))
@@ -315,6 +370,15 @@ class Context:
                     lambdas: Sequence[float] = (1e-10,), with_c: bool = False, stride: int = 1):
         lam = _f64(list(lambdas))
         z = self.sizes(sd)
+        if n_traj < 1 or T < 1:
+            raise ValueError("n_traj and T must be >= 1")
+        for name, t, ln in (("U", U, z["n_free"]), ("Udd", Udd, z["n_free"]), ("S", S, z["n_sch"])):
+            if t is None:
+                raise ValueError(f"{name}: snapshots are required")
+            self._check_buffer(name, t, (n_traj, T, ln))
+        if V0 is None:
+            raise ValueError("V0: initial velocities are required")
+        self._check_buffer("V0", V0, (n_traj, z["n_free"]))
         nsig = min(z["n_free"], n_traj * T)
         sig = np.zeros(nsig)
         E = np.zeros(len(lam))
@@ -323,7 +387,9 @@ class Context:
         d = OpinfDesc(1 if form == "quadratic" else 0, int(with_c), r, r_s, energy, energy_bnd, len(lam),
                       _dptr(lam), n_traj, T, _devptr(U), _devptr(Udd), _devptr(S), _devptr(V0),
                       _dptr(sig), _dptr(E), C.pointer(ls), C.pointer(ro), C.pointer(rso), stride)
+        self._order_in()
         self._check(self.lib.learn_opinf(self.h, sd, C.byref(d)))
+        self._order_out()
         return dict(sigma=sig, E_lambda=E, lambda_star=ls.value, r=ro.value, r_s=rso.value)
 
     # -- time loop ---------------------------------------------------------
@@ -339,13 +405,17 @@ class Context:
     def schwarz_step(self, opts: Options = Options()) -> List[dict]:
         info = self._infos()
         o = opts.c()
+        self._order_in()
         self._check(self.lib.schwarz_step(self.h, C.byref(o), info))
+        self._order_out()
         return self._info_list(info)
 
     def run(self, n_steps: int, opts: Options = Options(), check: bool = True) -> List[dict]:
         info = self._infos()
         o = opts.c()
+        self._order_in()
         st = self.lib.run(self.h, n_steps, C.byref(o), info)
+        self._order_out()
         if check:
             self._check(st)
         return self._info_list(info)
@@ -395,7 +465,9 @@ class Context:
                 g.dv0[sd] = d["v0"].data_ptr()
             out[sd] = d
         J = C.c_double()
+        self._order_in()
         self._check(self.lib.run_adjoint(self.h, n_steps, checkpoint_every, C.byref(m), C.byref(J), C.byref(g)))
+        self._order_out()
         del keep
         return J.value, out
 
@@ -420,7 +492,9 @@ class Context:
         state, so set the initial condition again afterwards."""
         t = Tuning()
         o = (opts or Options()).c()
+        self._order_in()
         self._check(self.lib.osam_autotune(self.h, trial_steps, C.byref(o), C.byref(t)))
+        self._order_out()
         n = self.n_sd
         return dict(fe=[(t.fe_block[i], t.fe_kc[i]) for i in range(n)], rom_path=list(t.rom_path[:n]),
                     fe_xs=list(t.fe_xs[:n]), graph=(t.graph_rounds, t.graph_streams), fusion_kc=t.fusion_kc,
@@ -503,17 +577,20 @@ def rollout_misfit_function():
             octx.set_reduced(sd, 0, npy(q0), npy(qd0))
             J, grads = octx.run_adjoint(n_steps, K, every, obs)
             fctx.grads = grads[sd]
-            fctx.has = (H is not None, c is not None)
-            return torch.tensor(J, dtype=torch.float64)
+            # gradients go back on each input's device and dtype; None inputs get None
+            fctx.meta = [None if t is None else (t.device, t.dtype) for t in (A, H, B, c, q0, qd0)]
+            return torch.tensor(J, dtype=torch.float64, device=A.device)
 
         @staticmethod
         def backward(fctx, gJ):
             g = fctx.grads
             s = float(gJ)
-            t = lambda a: torch.tensor(np.asarray(a) * s, dtype=torch.float64)
-            dH = t(g["H"]) if fctx.has[0] else None
-            dc = t(g["c"]) if fctx.has[1] else None
-            return (None, None, None, None, None, None, None, None, None, None,
-                    t(g["A"]), dH, t(g["B"]), dc, t(g["q0"]), t(g["qd0"]))
+            out = []
+            for key, meta in zip(("A", "H", "B", "c", "q0", "qd0"), fctx.meta):
+                if meta is None:
+                    out.append(None)
+                else:
+                    out.append(torch.as_tensor(np.asarray(g[key]) * s, dtype=meta[1], device=meta[0]))
+            return (None,) * 10 + tuple(out)
 
     return RolloutMisfit

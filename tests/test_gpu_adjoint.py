@@ -353,3 +353,40 @@ def test_adjoint_cfg4_size_f32_against_f64():
         e = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
         print(f"dJ/d{k}: FP32 vs FP64 relative L2 {e:.3e}")
         assert e <= 1e-2
+
+
+def test_autograd_device_parameters_and_no_boundary_operator():
+    """The torch.autograd wrapper with parameters on cuda:0 and without a boundary operator
+    (r_S = 0, B = None): gradients come back on the parameters' device and dtype, None for
+    None inputs, equal to those of the same call with CPU parameters, and match a central
+    difference of J along a random direction of A."""
+    import torch
+    from paper_2511_20687_amd import osam
+    P = _setup()
+    ctx, obs = _gpu(P)
+    Phi, PhiS, A, H, B, c = _lib_rom(P)
+    q0 = P["R"]["Phi"].T @ P["g"].restrict(P["u0"])[P["g"].free_dofs]
+    qd0 = np.zeros(R_)
+    F = osam.rollout_misfit_function()
+    args = (ctx, 1, P["n"], 9, P["every"], obs, P["u0"], P["v0"], Phi, None)
+    grads = {}
+    for dev in ("cuda:0", "cpu"):
+        tA, tH, tc, tq, tqd = (torch.tensor(x, dtype=torch.float64, device=dev, requires_grad=True)
+                               for x in (A, H, c, q0, qd0))
+        J = F.apply(*args, tA, tH, None, tc, tq, tqd)
+        J.backward()
+        for t in (tA, tH, tc, tq, tqd):
+            assert t.grad is not None and t.grad.device == t.device and t.grad.dtype == torch.float64
+        grads[dev] = [t.grad.cpu().numpy() for t in (tA, tH, tc, tq, tqd)]
+    for a, b in zip(grads["cuda:0"], grads["cpu"]):
+        assert np.array_equal(a, b)
+    dA = random_normal(95, A.shape)
+    eps = 1e-3 * np.abs(A).max() / np.abs(dA).max()
+    Js = []
+    for sgn in (1, -1):
+        Jx = F.apply(*args, *(torch.tensor(x) for x in (A + sgn * eps * dA, H)), None,
+                     *(torch.tensor(x) for x in (c, q0, qd0)))
+        Js.append(float(Jx))
+    fd = (Js[0] - Js[1]) / (2 * eps)
+    ad = float(np.sum(grads["cpu"][0] * dA))
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)

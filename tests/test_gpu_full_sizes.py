@@ -34,9 +34,11 @@ def test_bar24_fom_opinf_tuned_launch_matches_oracle():
     layers = [(0, 144), (96, 240)]
     kinds = ("fom", "opinf")
     roms = _roms_for(bar, layers, kinds, dt, r=40, rs=4, quadratic=False, with_c=False, seed=31)
-    u0 = gaussian_pulse_u(bar, 1e-3, 0.25, 0.02)
+    # the pulse starts inside the overlap (z = 0.4 .. 0.6) and crosses both Schwarz faces
+    # within the 200 steps (c_p n dt = 0.21 m), so the transfers carry the wave
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.5, 0.02)
     v0 = np.zeros_like(u0)
-    n = 12
+    n = 200
     recs = {}
     print("[bar24 tuned launch] oracle set-up", flush=True)
     models, ctx64, _ = _build(bar, layers, dt, kinds, roms, "f64")
@@ -70,13 +72,22 @@ def test_bar24_fom_opinf_tuned_launch_matches_oracle():
     print("[bar24 tuned launch] oracle", flush=True)
     ref = Coupled(models).run(u0, v0, n, SchwarzOptions(), record=("u", "q"))
     u64, q64, it64 = recs["f64"]
-    e_u = rel_err(u64[:, lib_index_of(models[0])], ref["u"][0])
+    li = lib_index_of(models[0])
+    e_u = rel_err(u64[:, li], ref["u"][0])
     e_q = rel_err(q64, ref["q"][1])
-    print(f"FP64 vs oracle: u {e_u:.2e}, q {e_q:.2e}")
-    assert e_u <= 1e-10 and e_q <= 1e-10
+    # per-node check: the largest error of any DOF at any step against the field's largest value
+    m_u = np.abs(u64[:, li] - ref["u"][0]).max() / np.abs(ref["u"][0]).max()
+    print(f"FP64 vs oracle: u {e_u:.2e} (max-abs {m_u:.2e}), q {e_q:.2e}")
+    assert e_u <= 1e-10 and e_q <= 1e-10 and m_u <= 1e-10
     assert it64 == int(ref["iters"].sum())
+    # the transfers carried the wave: the overlap-face values are far above round-off
+    face = np.abs(ref["u"][0][:, -3 * (bar.nx + 1) * (bar.ny + 1):]).max()
+    assert face >= 1e-3 * np.abs(ref["u"][0]).max()
     u32, q32, _ = recs["f32"]
-    assert rel_err(u32, u64) <= 1e-4 and rel_err(q32, q64) <= 1e-4
+    e32 = rel_err(u32[:, li], ref["u"][0])
+    m32 = np.abs(u32[:, li] - ref["u"][0]).max() / np.abs(ref["u"][0]).max()
+    print(f"FP32 vs oracle: u {e32:.2e} (max-abs {m32:.2e}), q {rel_err(q32, ref['q'][1]):.2e}")
+    assert e32 <= 1e-4 and m32 <= 1e-4 and rel_err(q32, ref["q"][1]) <= 1e-4
 
 
 def _block_rom(seed, n_free, n_sch, r, rs, dt):
@@ -163,3 +174,60 @@ def test_bar64_fom_16_instances_layouts_and_fused_sweeps_are_bitwise_equal():
         for k in range(2):
             assert np.array_equal(states[mode][0][k], states["plain"][0][k]), (mode, k)
         assert states[mode][1] == states["plain"][1]
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f32_bf16h", 1e-2)])
+def test_bar48_opinf_opinf_256_matches_oracle(precision, tol):
+    """48x48x480 OpInf-OpInf, quadratic r = 100 on both slabs, 256 instances in the bench's
+    launch configuration (batched f0 on the matrix cores inside fused sweeps, graphs of 32):
+    4 instances against the FP64 oracle over 50 controller steps.  FP32 to 1e-4; BF16-H
+    (BF16 operands of the quadratic contraction) reports its error and is held to 1e-2."""
+    import scipy.sparse as sp
+    import torch
+    from paper_2511_20687_amd import osam
+    from oracle.newmark import SubdomainGeometry
+    from oracle.rom import OpInfModel
+    from oracle.schwarz import Coupled, SchwarzOptions
+    bar = Bar(48, 48, 480)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    batch, n, r, rs, n_or = 256, 50, 100, 12, 4
+    opts = osam.Options(tol_abs=1e-8, tol_rel=1e-6)
+    pulses = draw_pulses(3, batch, s=0.05)
+    ctx = osam.Context(0, precision, batch)
+    sds = osam.add_bar_subdomains(ctx, bar, layers, dt)
+    models = []
+    for i in sds:
+        z = ctx.sizes(i)
+        Phi, PhiS, A, H, B = _block_rom(40 + 10 * i, z["n_free"], z["n_sch"], r, rs, dt)
+        ctx.set_opinf(i, Phi, PhiS, A, H, B)
+        g = SubdomainGeometry(bar, *layers[i])
+        Phi_o = sp.csr_matrix(Phi)[lib_index_of(g)]          # oracle DOF order
+        del Phi
+        models.append(OpInfModel(g, Phi_o, PhiS[lib_sch_index(bar, *layers[i])], A, H, B, dt=dt))
+        ctx.set_rom_path(i, 2)
+    ctx.set_fusion(True, 1)
+    ctx.set_graph(32, 1)
+    recs = [torch.zeros((batch, n + 1, r), dtype=torch.float32, device="cuda:0") for _ in sds]
+    for i in sds:
+        ctx.set_record(i, 1, n + 1, u=recs[i])
+    for b, p in enumerate(pulses):
+        u0 = p.u0(bar)
+        ctx.set_initial(b, u0, np.zeros_like(u0))
+    print(f"[bar48 B=256 {precision} vs oracle] gpu", flush=True)
+    ctx.run(n, opts)
+    ctx.sync()
+    got = [t.cpu().numpy().astype(np.float64) for t in recs]
+    del ctx, recs
+    print("oracle", flush=True)
+    cp = Coupled(models)
+    worst = 0.0
+    for b in range(n_or):
+        u0 = pulses[b].u0(bar)
+        ref = cp.run(u0, np.zeros_like(u0), n, SchwarzOptions(tol_abs=1e-8, tol_rel=1e-6), record=("q",))
+        for i in range(2):
+            e = rel_err(got[i][b], ref["q"][i])
+            worst = max(worst, e)
+        print(f"instance {b}: worst subdomain error {worst:.2e}", flush=True)
+    print(f"{precision} vs FP64 oracle, worst of {n_or} instances: {worst:.2e}")
+    assert worst <= tol

@@ -1,0 +1,148 @@
+"""Least-squares fit of OpInf learning on the GPU (Eq. quadratic_opinf, Eq.
+opinf_schwarz_inference, Alg. 3) in both forms of the normal equations.
+
+The library solves the regularised problem by FP64 normal equations and Cholesky: the primal
+form (D^T D + lambda I) X = D^T R when p <= T, the dual form X = D^T Y, (D D^T + lambda I) Y = R
+when p > T (the quadratic widths of the large workloads exceed the snapshot count).  The oracle
+solves the stacked least-squares system by SVD (a different route).  Checked here:
+  * oracle parity of the learning pipeline with the dual form (quadratic r = 12 from 60
+    snapshots, p > T): POD singular values, r_S, lambda*, E(lambda) and the online FOM-OpInf
+    trajectory;
+  * the GPU's operators satisfy the first-order (KKT) conditions of the normalised objective
+    on the GPU's own reduced data, for the dual and the primal form, to the accuracy the
+    conditioning of the solved system allows (64 eps kappa, kappa the condition number of the
+    matrix that was factored), and reach the objective's minimum to 1e-10 relative.
+"""
+import numpy as np
+import pytest
+
+from paper_2511_20687_amd.inputs import Bar, gaussian_pulse_u, slab_layers
+from oracle.newmark import SubdomainGeometry
+from oracle.opinf import lambda_grid, select_lambda
+from oracle.pod import energy_rank, pod
+from oracle.rom import OpInfModel, kron2
+from oracle.schwarz import Coupled, SchwarzOptions
+from tests._gpu import lib_index_of, rel_err
+from tests.test_gpu_opinf import _train_oracle_and_gpu
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _gpu_normalised_system(ctx, sd, U, Udd, S, dt, quadratic, with_c):
+    """D, R of the normalised fit from the GPU's snapshots and bases (test-side numpy on the
+    library's own data: a property check of the library's solve, not an oracle value)."""
+    ops = ctx.get_opinf(sd, quadratic=quadratic, with_c=with_c)
+    Phi, PhiS = ops["Phi"], ops["PhiS"]
+    Ug = U[0].double().cpu().numpy().T
+    Ag = Udd[0].double().cpu().numpy().T
+    Sg = S[0].double().cpu().numpy().T
+    Q, Qdd, Sh = Phi.T @ Ug, Phi.T @ Ag, PhiS.T @ Sg
+    alpha = float(np.max(np.linalg.norm(Q, axis=0)))
+    cols = [Q.T / alpha]
+    if quadratic:
+        cols.append(kron2(Q / alpha).T)
+    if Sh.shape[0]:
+        cols.append(Sh.T / alpha)
+    if with_c:
+        cols.append(np.ones((Q.shape[1], 1)))
+    D = np.hstack(cols)
+    R = (dt * dt * Qdd / alpha).T
+    blocks = [dt * dt * ops["A"]]
+    if quadratic:
+        blocks.append(dt * dt * alpha * ops["H"])
+    if Sh.shape[0]:
+        blocks.append(dt * dt * ops["B"])
+    if with_c:
+        blocks.append((dt * dt / alpha) * ops["c"][:, None])
+    X = np.hstack(blocks).T                 # p x r, normalised operators
+    return D, R, X
+
+
+def _check_kkt_and_minimum(D, R, X, lam):
+    T, p = D.shape
+    dual = p > T
+    G = D @ D.T + lam * np.eye(T) if dual else D.T @ D + lam * np.eye(p)
+    kappa = np.linalg.cond(G)
+    DtR = D.T @ R
+    kkt = np.linalg.norm(D.T @ (D @ X) + lam * X - DtR) / np.linalg.norm(DtR)
+    J = lambda Y: np.sum((D @ Y - R) ** 2) + lam * np.sum(Y * Y)
+    Xs, *_ = np.linalg.lstsq(np.vstack([D, np.sqrt(lam) * np.eye(p)]), np.vstack([R, np.zeros((p, R.shape[1]))]),
+                             rcond=None)
+    dJ = (J(X) - J(Xs)) / J(Xs)
+    print(f"{'dual' if dual else 'primal'} p={p} T={T} lambda={lam:.1e}: kappa {kappa:.2e}, "
+          f"KKT residual {kkt:.2e} (bound {64 * EPS * kappa:.2e}), objective excess {dJ:.2e}")
+    assert kkt <= max(1e-10, 64 * EPS * kappa)
+    # the excess is quadratic in the solution error (<= 64 eps kappa relative), weighted by
+    # at most kappa relative to the minimum
+    assert dJ <= max(1e-10, kappa * (64 * EPS * kappa) ** 2)
+    return dual
+
+
+@pytest.mark.parametrize("with_c", [False, True])
+def test_dual_form_learning_matches_oracle(with_c):
+    import torch
+    bar = Bar(2, 2, 40)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.3, 0.06)
+    v0 = np.zeros_like(u0)
+    T, r = 60, 12
+    print(f"[dual learning with_c={with_c}]", flush=True)
+    models, ref, ctx, (U, A, S, V0) = _train_oracle_and_gpu(bar, layers, dt, u0, v0, T, "f64")
+    lams = lambda_grid(11)
+    out = ctx.learn_opinf(1, U, A, S, V0, 1, T, form="quadratic", r=r, r_s=0, energy_bnd=1 - 1e-6,
+                          lambdas=list(lams), with_c=with_c)
+    Uo, Ao, So, Vo = (ref[k][1].T for k in ("u", "a", "s", "v"))
+    Phi, sig = pod(Uo, r=r)
+    _, sS = pod(So)
+    rs = energy_rank(sS, 1 - 1e-6)
+    PhiS, _ = pod(So, r=rs)
+    p = r + r * (r + 1) // 2 + rs + int(with_c)
+    assert p > T, "the case must take the dual form"
+    traj = dict(Q=Phi.T @ Uo, Qd0=Phi.T @ Vo[:, 0], Qdd=Phi.T @ Ao, Shat=PhiS.T @ So)
+    lam, E, ops = select_lambda([traj], lams, form="quadratic", with_c=with_c, dt=dt)
+    print("E gpu", out["E_lambda"], "\nE ora", E, "\nlambda*", out["lambda_star"], lam)
+    assert out["r_s"] == rs
+    assert np.allclose(out["sigma"][:r], sig[:r], rtol=1e-8)
+    assert out["lambda_star"] == lam
+    fin = np.isfinite(E) & (E < 1.0)
+    assert fin.any()
+    assert np.allclose(out["E_lambda"][fin], E[fin], rtol=1e-5, atol=1e-9)
+    D, R, X = _gpu_normalised_system(ctx, 1, U, A, S, dt, True, with_c)
+    assert _check_kkt_and_minimum(D, R, X, lam)
+    # online FOM-OpInf on both sides with the learned operators
+    g = SubdomainGeometry(bar, *layers[1])
+    rom = OpInfModel(g, Phi, PhiS, ops.A, ops.H, ops.B, ops.c, dt=dt)
+    n = 200
+    on = Coupled([models[0], rom]).run(u0, v0, n, SchwarzOptions(), record=("u",))
+    recs = []
+    for sd in range(2):
+        z = ctx.sizes(sd)
+        t = torch.zeros((1, n + 1, z["n_free"] if sd == 0 else z["r"]), dtype=torch.float64, device="cuda:0")
+        ctx.set_record(sd, 1, n + 1, u=t)
+        recs.append(t)
+    ctx.set_initial(0, u0, v0)
+    ctx.run(n)
+    e0 = rel_err(recs[0][0].cpu().numpy()[:, lib_index_of(models[0])], on["u"][0])
+    Phi_g = ctx.get_opinf(1)["Phi"]
+    e1 = rel_err((Phi_g @ recs[1][0].cpu().numpy().T).T[:, lib_index_of(g)], on["u"][1])
+    print("online errors", e0, e1)
+    assert e0 <= 1e-7 and e1 <= 1e-7
+
+
+@pytest.mark.parametrize("form,r,T", [("quadratic", 12, 60), ("quadratic", 6, 200), ("linear", 8, 200)])
+@pytest.mark.parametrize("lam", [1e-8, 1e-4, 1e-1])
+def test_fit_satisfies_kkt_conditions(form, r, T, lam):
+    """One fixed lambda (no selection): the GPU's operators solve the normalised ridge
+    problem, dual (p > T) or primal form."""
+    bar = Bar(2, 2, 40)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.3, 0.06)
+    print(f"[kkt {form} r={r} T={T} lambda={lam}]", flush=True)
+    models, ref, ctx, (U, A, S, V0) = _train_oracle_and_gpu(bar, layers, dt, u0, np.zeros_like(u0), T, "f64")
+    ctx.learn_opinf(1, U, A, S, V0, 1, T, form=form, r=r, r_s=0, energy_bnd=1 - 1e-6, lambdas=[lam])
+    D, R, X = _gpu_normalised_system(ctx, 1, U, A, S, dt, form == "quadratic", False)
+    dual = _check_kkt_and_minimum(D, R, X, lam)
+    assert dual == (form == "quadratic" and r == 12)

@@ -84,3 +84,27 @@ def test_binding_argument_counts_match_the_header():
         n = 0 if params in ("", "void") else params.count(",") + 1
         argtypes = getattr(lib, name).argtypes
         assert len(argtypes or ()) == n, (name, n, argtypes)
+
+
+def test_binding_rejects_bad_device_buffers():
+    """The binding checks every device buffer it hands to the library (dtype of the context
+    precision, contiguity, exact shape, device) before any pointer crosses the ABI: a wrong
+    tensor would otherwise become out-of-bounds device reads or writes."""
+    import torch
+    from paper_2511_20687_amd.osam import Context
+    ctx = object.__new__(Context)          # no device needed for the checks themselves
+    ctx.precision, ctx.device, ctx.batch = "f32", 0, 2
+    good = torch.zeros((2, 5, 7), dtype=torch.float32)
+    with pytest.raises(ValueError, match="dtype"):
+        ctx._check_buffer("u", good.double(), (2, 5, 7))
+    with pytest.raises(ValueError, match="contiguous"):
+        ctx._check_buffer("u", torch.zeros((2, 7, 5)).transpose(1, 2), (2, 5, 7))
+    with pytest.raises(ValueError, match="shape"):
+        ctx._check_buffer("u", good, (2, 5, 8))
+    with pytest.raises(ValueError, match="shape"):
+        ctx._check_buffer("u", good[0], (2, 5, 7))
+    with pytest.raises(ValueError, match="cuda:0"):
+        ctx._check_buffer("u", good, (2, 5, 7))
+    with pytest.raises(ValueError, match="torch tensor"):
+        ctx._check_buffer("u", good.numpy(), (2, 5, 7))
+    ctx._check_buffer("u", None, (2, 5, 7))  # absent buffers are allowed
