@@ -11,10 +11,23 @@ its data from the neighbours' iterates of the previous iteration (Jacobi).  Sec.
 the same loop with ROM subdomains (transfer = pointwise projection of the
 lifted field, then Phi_S^T restriction inside the ROM).
 
+Sub-stepping (Sec. 4.1, Eq. schwarz_discrete and the figure of field transfer within a
+controller step): subdomain i advances each controller step of length Dt in n_i = n_sub
+Newmark steps of dt_i = Dt / n_i.  Its Schwarz data at t_{k-1} + l dt_i come from the
+source's trajectory over the same controller step (its states at t_{k-1} + m dt_j,
+m = 0 .. n_j, m = 0 being the accepted state) through the temporal interpolant Xi: linear
+interpolation in time between the two trajectory points that bracket the destination time
+(the source's own points when the times coincide, so equal n_sub needs no interpolation).
+A source not yet advanced in the step supplies its guess at every destination time.
+
 Readings (the paper is silent or ambiguous):
   * initial guess phi^(0) of a neighbour not yet advanced in this controller
     step: HOLD = its state at t_{k-1}; PREDICTOR = its Newmark displacement
-    predictor at t_k;
+    predictor u + tau v + tau^2/2 a from its state at t_{k-1}, at the time tau into
+    the step where the destination needs data (t_k for one step per controller step);
+  * Xi (garbled as a column vector of length n_j acting on n_j source states): the
+    source's trajectory includes its state at t_{k-1}, and interpolation is linear
+    in time;
   * the criterion needs iterate n-1, so it is tested from n >= min_iter (2);
     if min_iter = 1, iterate 0 is read as the subdomain's state at t_{k-1};
     "or": either the absolute or the relative test suffices; dt in the
@@ -132,25 +145,53 @@ class Coupled:
     def initial_states(self, u0_global, v0_global):
         return [m.initial_state(u0_global, v0_global) for m in self.models]
 
-    def schwarz_data(self, i, latest, start, guess):
+    def n_sub(self, i) -> int:
+        return int(getattr(self.models[i], "n_sub", 1))
+
+    def schwarz_data(self, i, latest, start, guess, l: int = None):
+        """Schwarz data of subdomain i at its sub-step l (time t_{k-1} + l dt_i; default
+        l = n_i, i.e. t_k).  latest[j]: trajectory of source j in this step (list of its
+        states at sub-steps 0 .. n_j) or None (not yet advanced: the guess)."""
         mi = self.models[i]
+        ni = self.n_sub(i)
+        l = ni if l is None else l
         dtype = np.result_type(*[m.field(s).dtype for m, s in zip(self.models, start)])
         s = np.zeros(mi.sch_dofs.size, dtype=dtype)
         for j, rows, Pi in self.blocks[i]:
             mj = self.models[j]
+            nj = self.n_sub(j)
             if latest[j] is not None:
-                fld = mj.field(latest[j])
+                # Xi: destination time l dt_i = (l nj / ni) dt_j on the source's grid
+                num = l * nj
+                m0, rem = divmod(num, ni)
+                if rem == 0:
+                    fld = mj.field(latest[j][m0])
+                else:
+                    w = rem / ni
+                    fld = (1.0 - w) * mj.field(latest[j][m0]) + w * mj.field(latest[j][m0 + 1])
             elif guess == "hold":
                 fld = mj.field(start[j])
             else:
-                fld = mj.predictor(start[j], mj.dt)
+                fld = mj.predictor(start[j], l * mi.dt)
             s[rows] = Pi @ fld
         return s
+
+    def advance(self, i, start_i, src, start, guess):
+        """Subdomain i through the n_i sub-steps of one controller step; its trajectory."""
+        traj = [start_i]
+        st = start_i
+        for l in range(1, self.n_sub(i) + 1):
+            st = self.models[i].step(st, self.schwarz_data(i, src, start, guess, l))
+            traj.append(st)
+        return traj
 
     def step(self, start: list, opts: SchwarzOptions):
         """One controller step (Alg. 1 inner loop). Returns (new states, StepInfo)."""
         S = len(self.models)
-        latest: List[Optional[object]] = [None] * S
+        dts = [m.dt * self.n_sub(i) for i, m in enumerate(self.models)]
+        if max(dts) - min(dts) > 1e-12 * max(dts):
+            raise ValueError("subdomains must share the controller step dt * n_sub")
+        latest: List[Optional[list]] = [None] * S
         # iterate 0 of each subdomain (only compared against when min_iter = 1)
         prev: List[Optional[object]] = list(start)
         info = StepInfo(0, False, float('nan'), float('nan'))
@@ -159,19 +200,18 @@ class Coupled:
             # the previous iteration for every subdomain
             src = list(latest) if opts.additive else latest
             for i in range(S):
-                s = self.schwarz_data(i, src, start, opts.guess)
-                new = self.models[i].step(start[i], s)
-                prev[i] = latest[i] if latest[i] is not None else start[i]
-                latest[i] = new
+                traj = self.advance(i, start[i], src, start, opts.guess)
+                prev[i] = latest[i][-1] if latest[i] is not None else start[i]
+                latest[i] = traj
             info.iters = n
             if n >= opts.min_iter:
-                abs2 = sum(m.diff_norm2(a, b) for m, a, b in zip(self.models, latest, prev))
-                den2 = sum(m.norm2(a) for m, a in zip(self.models, latest))
+                abs2 = sum(m.diff_norm2(a[-1], b) for m, a, b in zip(self.models, latest, prev))
+                den2 = sum(m.norm2(a[-1]) for m, a in zip(self.models, latest))
                 info.abs2, info.den2 = abs2, den2
                 if abs2 < opts.tol_abs ** 2 or abs2 < opts.tol_rel ** 2 * den2:
                     info.converged = True
                     break
-        return latest, info
+        return [t[-1] for t in latest], info
 
     def run(self, u0_global, v0_global, n_steps: int, opts: SchwarzOptions = SchwarzOptions(),
             every: int = 1, record=("u",), states=None):

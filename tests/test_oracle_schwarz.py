@@ -140,3 +140,98 @@ def test_union_field_reassembles_single_domain():
     ref = traj[-1].u.reshape(-1, 3).T
     interior = ~np.isnan(uni[0])
     assert np.abs(uni[:, interior] - ref[:, interior]).max() <= 1e-15
+
+
+# ---------------------------------------------------------------- sub-stepping (Xi)
+def _substepped(bar, layers, Dt, n_sub, beta=0.0, lateral_fix=()):
+    ms = []
+    for (lo, hi), ns in zip(layers, n_sub):
+        m = FomModel(bar, lo, hi, Dt / ns, beta=beta, lateral_fix=lateral_fix)
+        m.n_sub = ns
+        ms.append(m)
+    return ms
+
+
+@pytest.mark.parametrize("S,guess", [(2, "hold"), (2, "predictor"), (3, "hold")])
+def test_equal_substeps_recover_single_domain_with_the_substep(S, guess):
+    """Every subdomain takes m = 3 explicit Newmark steps per controller step (Sec. 4.1,
+    Eq. schwarz_discrete with n_1 = n_2): the source's trajectory points coincide with the
+    destination's times, and the converged iterate equals the single-domain solution with
+    step Dt/3.  Unlike one step per controller step with PREDICTOR, the guess is not the final
+    data at the inner sub-steps, so every step takes a third sweep."""
+    bar = Bar(3, 3, 30, Lx=0.1, Ly=0.1, Lz=1.0)
+    dt = bar.explicit_dt()
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.3, 0.05)
+    models = _substepped(bar, slab_layers(bar.nz, S), 3 * dt, [3] * S)
+    n = 50
+    opts = SchwarzOptions(guess=guess, tol_abs=1e-30, tol_rel=1e-14)
+    out = Coupled(models).run(u0, np.zeros_like(u0), n, opts)
+    sd, traj = _single_ref(bar, dt, u0, 3 * n)
+    for i, m in enumerate(models):
+        assert rel_l2(out["u"][i], _free_ref(m, sd, traj[::3])) <= 1e-12
+    assert np.all(out["converged"])
+    assert out["iters"].max() >= 3
+
+
+def test_equal_substeps_implicit_converge_to_single_domain():
+    bar = Bar(2, 2, 24, Lx=0.1, Ly=0.1, Lz=1.0)
+    dt = 4.0 * bar.explicit_dt()
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.4, 0.08)
+    models = _substepped(bar, ((0, 13), (11, 24)), 2 * dt, [2, 2], beta=0.25)
+    n = 30
+    out = Coupled(models).run(u0, np.zeros_like(u0), n, SchwarzOptions(tol_abs=1e-14, tol_rel=1e-14, max_iter=64))
+    sd, traj = _single_ref(bar, dt, u0, 2 * n, beta=0.25)
+    assert np.all(out["converged"]) and out["iters"].max() > 3
+    for i, m in enumerate(models):
+        assert rel_l2(out["u"][i], _free_ref(m, sd, traj[::2])) <= 1e-9
+
+
+def test_temporal_interpolant_is_exact_for_fields_linear_in_time():
+    """Xi on trajectories whose every nodal value is linear in time (value m dt_j at source
+    sub-step m): the data at destination sub-step l equal l dt_i for every pair of step
+    counts, the guess excluded (sources advanced)."""
+    bar = Bar(2, 2, 20)
+    Dt = 1.0
+    for ni, nj in ((1, 2), (2, 1), (3, 2), (2, 3), (4, 4)):
+        models = _substepped(bar, slab_layers(bar.nz, 2), Dt, [ni, nj])
+        cp = Coupled(models)
+        st = cp.initial_states(np.zeros((3, bar.n_nodes)), np.zeros((3, bar.n_nodes)))
+        src = models[1]
+
+        def state(val):
+            x = st[1].copy()
+            x.u[:] = val
+            return x
+
+        traj = [state(m * Dt / nj) for m in range(nj + 1)]
+        for l in range(1, ni + 1):
+            s = cp.schwarz_data(0, [None, traj], st, "hold", l)
+            assert np.allclose(s, l * Dt / ni, rtol=1e-15, atol=1e-15), (ni, nj, l)
+
+
+def test_mixed_substeps_second_order_in_time():
+    """Implicit Newmark (beta = 1/4) with 1 and 2 sub-steps per controller step on the two
+    subdomains of the 1D-reduced bar: the converged coupled solution approaches the
+    single-domain solution of the same mesh at second order in the controller step (a
+    temporal interpolant that held the end value instead of interpolating would be first
+    order)."""
+    from tests._bars import bar_1d
+    bar = bar_1d(40, L=1.0)
+    lf = (0, 1)
+    u0 = gaussian_pulse_u(bar, 1e-3, 0.45, 0.08)
+    t_end = 80 * bar.explicit_dt()
+    fine = FomModel(bar, 0, bar.nz, t_end / 640, beta=0.25, lateral_fix=lf)
+    ref = run_single(fine, u0, np.zeros_like(u0), 640)[-1].u
+    errs = []
+    for nsteps in (20, 40, 80):
+        Dt = t_end / nsteps
+        models = _substepped(bar, ((0, 24), (16, 40)), Dt, [1, 2], beta=0.25, lateral_fix=lf)
+        out = Coupled(models).run(u0, np.zeros_like(u0), nsteps, SchwarzOptions(tol_abs=1e-16, tol_rel=1e-13,
+                                                                                max_iter=100), every=nsteps)
+        m = models[0]
+        node, comp = m.free_dofs // 3, m.free_dofs % 3
+        exact = ref[3 * m.mesh.global_ids[node] + comp]
+        errs.append(np.linalg.norm(out["u"][0][-1] - exact) / np.linalg.norm(exact))
+        assert np.all(out["converged"])
+    rates = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert min(rates) >= 1.8, (errs, rates)
