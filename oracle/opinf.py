@@ -5,7 +5,8 @@ reduced snapshots Q = Phi^T U (r x T), reduced accelerations Qdd = Phi^T U''
 and reduced Schwarz data S^ = Phi_S^T S (r_S x T), find
 
     argmin_O  || O D^T - Qdd ||_F^2 + lambda ||O||_F^2,
-    D = [ Q^T | (Q (x) Q)^T | S^^T | 1 ]   (T x p),   O = [A | H | B | c]  (r x p)
+    D = [ Q^T | (Q (x) Q)^T | (Q (x) Q (x) Q)^T | S^^T | 1 ]   (T x p),
+    O = [A | H | C | B | c]  (r x p)   (linear: no H, C; quadratic: no C; cubic: all)
 
 (signs folded into the operators, see oracle/rom.py).  Readings:
   * D_t^2(U) "e.g. by finite differences": the FOM's own Newmark accelerations
@@ -23,8 +24,8 @@ and reduced Schwarz data S^ = Phi_S^T S (r_S x T), find
     with time in steps (tau = t/dt):
         argmin || dt^2 Qdd/alpha - At Q/alpha - Ht (Q/alpha)^(2) - Bt S^/alpha - ct 1^T ||^2
                + lambda ||[At Ht Bt ct]||^2,
-    mapped back with A = At/dt^2, H = Ht/(dt^2 alpha), B = Bt/dt^2,
-    c = alpha ct/dt^2.  In physical units this is the raw ridge problem with
+    mapped back with A = At/dt^2, H = Ht/(dt^2 alpha), C = Ct/(dt^2 alpha^2),
+    B = Bt/dt^2, c = alpha ct/dt^2 (the cubic block is weighted lambda alpha^6).  In physical units this is the raw ridge problem with
     the penalty lambda (alpha^2 ||A||^2 + alpha^4 ||H||^2 + alpha^2 ||B||^2 + ||c||^2):
     dt cancels from the minimiser (the time scaling only keeps the arithmetic
     of order one) and a change of length unit maps the operators exactly
@@ -49,7 +50,7 @@ from typing import List, Optional
 
 import numpy as np
 
-from .rom import Operators, kron2, newmark_reduced_step
+from .rom import Operators, kron2, kron3, newmark_reduced_step
 
 
 def lambda_grid(n: int = 11) -> np.ndarray:
@@ -62,8 +63,10 @@ def lambda_grid(n: int = 11) -> np.ndarray:
 def data_matrix(Q: np.ndarray, Shat: Optional[np.ndarray], form: str = "linear",
                 with_c: bool = False) -> np.ndarray:
     cols = [Q.T]
-    if form == "quadratic":
+    if form in ("quadratic", "cubic"):
         cols.append(kron2(Q).T)
+    if form == "cubic":
+        cols.append(kron3(Q).T)
     if Shat is not None and Shat.shape[0] > 0:
         cols.append(Shat.T)
     if with_c:
@@ -85,15 +88,20 @@ def split_operators(X: np.ndarray, r: int, form: str, rS: int, with_c: bool) -> 
     k = 0
     A = O[:, k:k + r]; k += r
     H = None
-    if form == "quadratic":
+    if form in ("quadratic", "cubic"):
         w = r * (r + 1) // 2
         H = O[:, k:k + w]; k += w
+    C = None
+    if form == "cubic":
+        w3 = r * (r + 1) * (r + 2) // 6
+        C = O[:, k:k + w3]; k += w3
     B = None
     if rS > 0:
         B = O[:, k:k + rS]; k += rS
     c = O[:, k] if with_c else None
     return Operators(A.copy(), None if H is None else H.copy(),
-                     None if B is None else B.copy(), None if c is None else c.copy())
+                     None if B is None else B.copy(), None if c is None else c.copy(),
+                     None if C is None else C.copy())
 
 
 def amplitude_scale(Qs: List[np.ndarray]) -> float:
@@ -118,7 +126,8 @@ def fit(Qs: List[np.ndarray], Qdds: List[np.ndarray], Shats: List[Optional[np.nd
     return Operators(o.A / dt2,
                      None if o.H is None else o.H / (dt2 * alpha),
                      None if o.B is None else o.B / dt2,
-                     None if o.c is None else o.c * alpha / dt2)
+                     None if o.c is None else o.c * alpha / dt2,
+                     None if o.C is None else o.C / (dt2 * alpha * alpha))
 
 
 def rollout_frozen(ops: Operators, q0, qd0, qdd0, Shat: Optional[np.ndarray], n_cols: int,

@@ -10,7 +10,8 @@ block of g^ vanishes and is omitted.
 
 Compressed quadratic power (footnote to Eq. quadratic_model): the symmetric
 q (x) q is parameterised by its independent entries q_i q_j, i <= j, listed
-row by row of the upper triangle; width r(r+1)/2.
+row by row of the upper triangle; width r(r+1)/2.  The cubic power of COpInf
+likewise: q_i q_j q_k, i <= j <= k, lexicographic; width r(r+1)(r+2)/6.
 
 The time integrator is the textbook Newmark-beta of oracle/newmark.py applied
 to the reduced state (the ROM equation in Eq. schwarz_opinf_discrete carries
@@ -44,6 +45,27 @@ def kron2_jacobian(q: np.ndarray) -> np.ndarray:
     return J
 
 
+def kron3(q: np.ndarray) -> np.ndarray:
+    """[q_i q_j q_k]_{i<=j<=k}, lexicographic in (i, j, k); width r(r+1)(r+2)/6 (the
+    compressed cubic power of Sec. 3, footnote to Eq. quadratic_model).  q: (r,) or (r, T)."""
+    r = q.shape[0]
+    idx = [(i, j, k) for i in range(r) for j in range(i, r) for k in range(j, r)]
+    i, j, k = (np.array(t, dtype=np.int64) for t in zip(*idx)) if idx else (np.zeros(0, np.int64),) * 3
+    return q[i] * q[j] * q[k]
+
+
+def kron3_jacobian(q: np.ndarray) -> np.ndarray:
+    """d kron3(q) / dq  ->  (r(r+1)(r+2)/6, r)."""
+    r = q.shape[0]
+    idx = [(i, j, k) for i in range(r) for j in range(i, r) for k in range(j, r)]
+    J = np.zeros((len(idx), r), dtype=q.dtype)
+    for m, (i, j, k) in enumerate(idx):
+        J[m, i] += q[j] * q[k]
+        J[m, j] += q[i] * q[k]
+        J[m, k] += q[i] * q[j]
+    return J
+
+
 def newmark_reduced_step(ops, q0, qd0, qdd0, gh, dt, beta=0.0, gamma=0.5):
     """One Newmark-beta step of q'' = ops.rhs(q, g^) with boundary input gh at the new time."""
     qt = q0 + dt * qd0 + (0.5 - beta) * dt * dt * qdd0
@@ -65,16 +87,19 @@ def newmark_reduced_step(ops, q0, qd0, qdd0, gh, dt, beta=0.0, gamma=0.5):
 
 
 class Operators:
-    """Reduced operators (A, H, B, c) of q'' = A q + H (q (x) q) + B g^ + c."""
+    """Reduced operators (A, H, B, c, C) of q'' = A q + H (q (x) q) + C (q (x) q (x) q) + B g^ + c
+    (C: the cubic operator of COpInf, Eq. opinf_rom)."""
 
-    def __init__(self, A, H=None, B=None, c=None):
-        self.A, self.H, self.B, self.c = A, H, B, c
+    def __init__(self, A, H=None, B=None, c=None, C=None):
+        self.A, self.H, self.B, self.c, self.C = A, H, B, c, C
         self.r = A.shape[0]
 
     def rhs(self, q, gh):
         out = self.A @ q
         if self.H is not None:
             out = out + self.H @ kron2(q)
+        if self.C is not None:
+            out = out + self.C @ kron3(q)
         if self.B is not None and gh.size:
             out = out + self.B @ gh
         if self.c is not None:
@@ -85,6 +110,8 @@ class Operators:
         J = self.A.astype(np.result_type(self.A, q))
         if self.H is not None:
             J = J + self.H @ kron2_jacobian(q)
+        if self.C is not None:
+            J = J + self.C @ kron3_jacobian(q)
         return J
 
 
@@ -103,13 +130,13 @@ class OpInfModel:
     kind = "opinf"
 
     def __init__(self, geom: SubdomainGeometry, Phi, PhiS, A, H=None, B=None, c=None,
-                 dt: float = 1.0, beta: float = 0.0, gamma: float = 0.5):
+                 dt: float = 1.0, beta: float = 0.0, gamma: float = 0.5, C=None):
         self.geom = geom
         self.Phi, self.PhiS = Phi, PhiS
-        self.A, self.H, self.B, self.c = A, H, B, c
+        self.A, self.H, self.B, self.c, self.C = A, H, B, c, C
         self.dt, self.beta, self.gamma = dt, beta, gamma
         self.r = A.shape[0]
-        self.ops = Operators(A, H, B, c)
+        self.ops = Operators(A, H, B, c, C)
         self.sch_dofs = geom.sch_dofs
         self.free_dofs = geom.free_dofs
         self.dir_dofs = geom.dir_dofs
