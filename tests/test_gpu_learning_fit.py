@@ -111,11 +111,13 @@ def test_dual_form_learning_matches_oracle(with_c):
     assert np.allclose(out["E_lambda"][fin], E[fin], rtol=1e-5, atol=1e-9)
     D, R, X = _gpu_normalised_system(ctx, 1, U, A, S, dt, True, with_c)
     assert _check_kkt_and_minimum(D, R, X, lam)
-    # online FOM-OpInf on both sides with the learned operators
+    # online FOM-OpInf on both sides with the learned operators, 40 steps past the training
+    # window (the model learned from 60 snapshots diverges after about 160 steps, on both sides)
     g = SubdomainGeometry(bar, *layers[1])
     rom = OpInfModel(g, Phi, PhiS, ops.A, ops.H, ops.B, ops.c, dt=dt)
-    n = 200
+    n = 100
     on = Coupled([models[0], rom]).run(u0, v0, n, SchwarzOptions(), record=("u",))
+    assert np.all(np.isfinite(on["u"][1]))
     recs = []
     for sd in range(2):
         z = ctx.sizes(sd)

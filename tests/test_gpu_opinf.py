@@ -120,9 +120,9 @@ def test_pod_of_prescribed_spectrum_matches_oracle():
     S = random_normal(33, (NS, T)) * 1e-3
     Udd = random_normal(34, (N, T))
     dev = "cuda:0"
-    Ut = torch.tensor(U.T.copy(), device=dev)          # [T][N]
-    Uddt = torch.tensor(Udd.T.copy(), device=dev)
-    St = torch.tensor(S.T.copy(), device=dev)
+    Ut = torch.tensor(U.T[None].copy(), device=dev)    # [1][T][N]
+    Uddt = torch.tensor(Udd.T[None].copy(), device=dev)
+    St = torch.tensor(S.T[None].copy(), device=dev)
     V0 = torch.zeros((1, N), dtype=torch.float64, device=dev)
     out = ctx.learn_opinf(1, Ut, Uddt, St, V0, 1, T, r=12, r_s=4, lambdas=[1e-8])
     assert out["r"] == 12 and out["r_s"] == 4
