@@ -84,8 +84,17 @@ const char *osam_last_error(const osam_ctx *ctx);
 /* One subdomain = one mesh + material + BCs + time integrator: the input of
  * Alg. 1 (overlapping subdomains, each with a mesh, initial condition, time
  * integrator and uniform time step).  Linear elasticity (App. A.1), 2x2x2-Gauss
- * hex8 stiffness, row-sum lumped mass, Newmark-beta (Sec. 4.1); beta must be 0
- * (explicit central difference, gamma = 1/2) in this version. */
+ * hex8 stiffness, row-sum lumped mass, textbook Newmark-beta (Sec. 4.1; the
+ * printed Eq. schwarz_discrete is garbled in its scaling): beta = 0 is the
+ * explicit central-difference scheme, beta > 0 the implicit one, whose free DOFs
+ * solve (M + beta dt^2 K_ff) a+ = -K [u~; u_c] (conjugate gradients on the GPU;
+ * an OpInf subdomain solves its reduced equation by Newton's method).  Each
+ * subdomain advances a controller step dt in n_sub Newmark steps of dt / n_sub
+ * (Sec. 4.1, mixed time steps; its Schwarz data at the intermediate times come
+ * from the source's trajectory through the temporal interpolant Xi, linear in
+ * time).  All subdomains share dt.  Contexts whose subdomains are all explicit
+ * with gamma = 1/2 and n_sub = 1 run the single-step path of run; any other
+ * context runs the window engine (osam_set_engine). */
 typedef struct {
   int32_t nx, ny, nz;          /* global grid, elements per axis (>= 1)     */
   double Lx, Ly, Lz;           /* box size                                  */
@@ -95,8 +104,11 @@ typedef struct {
   int32_t lateral_fix;         /* components held at zero on lateral faces:
                                   bit 0 = x, bit 1 = y, bit 2 = z (0 = traction-free);
                                   the same value for every subdomain          */
-  double dt;                   /* time step = controller step              */
-  double beta, gamma;          /* Newmark parameters: 0, 0.5               */
+  double dt;                   /* controller step (shared by all subdomains) */
+  double beta, gamma;          /* Newmark parameters: 0 <= beta <= 1/2,
+                                  1/2 <= gamma <= 1                         */
+  int32_t n_sub;               /* Newmark steps per controller step (0 or 1:
+                                  one; at most 64)                          */
 } osam_subdomain_desc;
 
 /* Append a FOM subdomain; *sd_id receives its index (0, 1, ...).  The
@@ -385,6 +397,30 @@ int32_t osam_autotune(osam_ctx *ctx, int64_t trial_steps, const osam_schwarz_opt
 
 /* Wait for all queued work of the context (host synchronisation). */
 int32_t osam_sync(osam_ctx *ctx);
+
+/* Controller engine of run and schwarz_step (Alg. 1).  engine = 0 (default):
+ * the single-step path (explicit central difference, one Newmark step per
+ * controller step: fused sweeps, graphs, batched OpInf path, autotuner, adjoint)
+ * when every subdomain has beta = 0, gamma = 1/2 and n_sub = 1 and no cubic
+ * operator, otherwise the window engine.  engine = 1: the window engine for
+ * every context.  The window engine runs each Schwarz iteration as every
+ * subdomain's whole window of n_sub Newmark steps from the accepted state at
+ * t_{k-1} (Sec. 4.1), with the Schwarz data at each sub-step interpolated in time
+ * from the source's trajectory of the newest iterate (the temporal interpolant
+ * Xi; the initial guess while the source has not run in the step), and the
+ * implicit solves of beta > 0; one workgroup per instance and subdomain.  Both
+ * engines compute the same iterates for explicit single-step contexts (up to
+ * rounding order).  The launch settings (osam_set_fe_launch, osam_set_fusion,
+ * osam_set_graph, osam_set_rom_path) do not apply to it; osam_autotune and
+ * run_adjoint return OSAM_E_INVALID for contexts it runs.  OSAM_E_INVALID for
+ * other values. */
+int32_t osam_set_engine(osam_ctx *ctx, int32_t engine);
+
+/* Iteration statistics of the window engine's solves for subdomain sd: iters
+ * [batch] receives, per instance, the most conjugate-gradient iterations (FOM)
+ * or Newton iterations (OpInf) any implicit sub-step took since the engine was
+ * set up (0 for explicit subdomains or before the first run). */
+int32_t osam_get_solver_stats(osam_ctx *ctx, int32_t sd, int32_t *iters);
 
 #ifdef __cplusplus
 }

@@ -1059,6 +1059,7 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
   o.guess = op.guess;
   o.additive = op.additive;
   o.nsd = (int)sds.size();
+  if (window_mode()) return run_window(n_steps, o, info);
   bool any = false;
   for (int b = 0; b < batch; ++b) {
     Status &S = h_status[b];
@@ -1309,6 +1310,7 @@ int32_t Ctx::install_opinf(int sdi, const OpinfHost &oh) {
   d.r = r;
   d.rs = rs;
   wired = false;
+  win_ready = false;
   std::fill(initialized.begin(), initialized.end(), 0);
   HIPCHK(hipStreamSynchronize(stream));
   return OSAM_OK;

@@ -322,8 +322,9 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   if (!(d->Lx > 0 && d->Ly > 0 && d->Lz > 0 && d->E > 0 && d->rho > 0 && d->nu > -1 && d->nu < 0.5 &&
         d->dt > 0))
     return ctx->fail(OSAM_E_INVALID, "bad geometry, material or dt");
-  if (d->beta != 0.0 || d->gamma != 0.5)
-    return ctx->fail(OSAM_E_INVALID, "only explicit Newmark (beta = 0, gamma = 1/2) is implemented");
+  if (!(d->beta >= 0.0 && d->beta <= 0.5 && d->gamma >= 0.5 && d->gamma <= 1.0))
+    return ctx->fail(OSAM_E_INVALID, "Newmark parameters outside 0 <= beta <= 1/2, 1/2 <= gamma <= 1");
+  if (d->n_sub < 0 || d->n_sub > 64) return ctx->fail(OSAM_E_INVALID, "n_sub must be in 0..64");
   const bool ext_lo = d->z_lo == 0, ext_hi = d->z_hi == d->nz;
   if ((ext_lo || ext_hi) && !d->clamp_ends)
     return ctx->fail(OSAM_E_INVALID, "traction-free exterior z-faces are not supported (clamp_ends = 1)");
@@ -351,6 +352,7 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   sd->face_type[1] = ext_hi ? kFaceClamped : kFaceFom;
   sd->nsch_nodes = (long long)sd->npl * ((ext_lo ? 0 : 1) + (ext_hi ? 0 : 1));
   sd->face_off_hi = ext_lo ? 0 : sd->npl;
+  sd->n_sub = d->n_sub > 1 ? d->n_sub : 1;
 
   // stencil coefficients
   std::vector<double> C;

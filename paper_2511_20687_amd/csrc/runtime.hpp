@@ -17,6 +17,19 @@ struct OpinfHost {
   int r = 0, rs = 0;
   bool quadratic = false;
   std::vector<double> Phi, PhiS, A, H, B, c;   // Phi [nfree x r], PhiS [nsch x rs], A [r x r], ...
+  std::vector<double> C3;                      // cubic operator [r x r(r+1)(r+2)/6] (COpInf) or empty
+};
+
+// Buffers of the window engine (window.hip), per subdomain.
+struct WinBufs {
+  void *wu[2] = {}, *wv[2] = {}, *wa[2] = {};   // FOM: end of the window by iteration parity
+  void *tu[2] = {}, *tv[2] = {}, *ta[2] = {};   // FOM: inner sub-steps
+  void *cr = nullptr, *cp = nullptr, *cq = nullptr;   // FOM: CG vectors
+  void *wq[2] = {}, *wqd[2] = {}, *wqdd[2] = {}, *tq[2] = {}, *tqd[2] = {}, *tqdd[2] = {};   // OpInf
+  void *sbuf = nullptr, *kbuf = nullptr, *Minv = nullptr, *C3 = nullptr;
+  void *traj[2][2] = {};           // per own Schwarz face: the source's trajectory by iteration parity
+  std::vector<std::pair<int, void *>> exp_rows;   // OpInf source: (2 dst + face, [r][3 npl] rows)
+  int *iters = nullptr;            // [batch] CG / Newton iteration statistics
 };
 
 // Pointwise projection of one z-face: ELL rows over the face's npl nodes.
@@ -76,6 +89,9 @@ struct Subdomain {
   std::vector<void *> piphi_rm;              // row-major device copy per export ([3 npl][r rounded up to 4])
   // records
   osam_record rec{};
+  // window engine
+  int n_sub = 1;
+  WinBufs win;
 };
 
 struct Ctx {
@@ -155,6 +171,14 @@ struct Ctx {
   int32_t launch_rom_sd(int sdi, const Opts &o, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                         hipStream_t st = nullptr, bool defer = false);
   int32_t learn(int sd, const osam_opinf_desc &d);
+  // window engine (window.hip): sub-stepped or implicit subdomains, or on request
+  int engine = 0;                  // 0 automatic, 1 window engine for every run
+  bool win_ready = false;
+  std::vector<void *> win_allocs;
+  double *win_sums = nullptr;      // [batch][nsd][2]
+  bool window_mode() const;
+  int32_t window_setup();
+  int32_t run_window(int64_t n_steps, const Opts &o, osam_instance_info *info);
 };
 
 }  // namespace osam

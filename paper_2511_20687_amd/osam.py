@@ -29,7 +29,7 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
             "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_set_fusion", "osam_set_fe_xshare",
             "osam_autotune",
-            "osam_sync"]
+            "osam_sync", "osam_set_engine", "osam_get_solver_stats"]
 
 
 class OsamError(RuntimeError):
@@ -44,7 +44,7 @@ class SubdomainDesc(C.Structure):
                 ("z_lo", C.c_int32), ("z_hi", C.c_int32),
                 ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
                 ("clamp_ends", C.c_int32), ("lateral_fix", C.c_int32), ("dt", C.c_double),
-                ("beta", C.c_double), ("gamma", C.c_double)]
+                ("beta", C.c_double), ("gamma", C.c_double), ("n_sub", C.c_int32)]
 
 
 class Record(C.Structure):
@@ -165,6 +165,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_get_rom_path.restype = i32
     lib.osam_sync.argtypes = [vp]
     lib.osam_sync.restype = i32
+    lib.osam_set_engine.argtypes = [vp, i32]
+    lib.osam_set_engine.restype = i32
+    lib.osam_get_solver_stats.argtypes = [vp, i32, C.POINTER(i32)]
+    lib.osam_get_solver_stats.restype = i32
     _lib = lib
     return lib
 
@@ -264,13 +268,14 @@ class Context:
 
     # -- set-up ------------------------------------------------------------
     def create_subdomain(self, nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, dt,
-                         clamp_ends=True, beta=0.0, gamma=0.5, lateral_fix=()) -> int:
-        """lateral_fix: components (0 = x, 1 = y, 2 = z) held at zero on the lateral faces."""
+                         clamp_ends=True, beta=0.0, gamma=0.5, lateral_fix=(), n_sub=1) -> int:
+        """lateral_fix: components (0 = x, 1 = y, 2 = z) held at zero on the lateral faces;
+        dt: the controller step, taken in n_sub Newmark steps of dt / n_sub."""
         mask = 0
         for c in lateral_fix:
             mask |= 1 << int(c)
         d = SubdomainDesc(nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, int(clamp_ends), mask, dt,
-                          beta, gamma)
+                          beta, gamma, int(n_sub))
         sid = C.c_int32()
         self._check(self.lib.create_subdomain(self.h, C.byref(d), C.byref(sid)))
         self.n_sd += 1
@@ -523,6 +528,16 @@ class Context:
         self._check(self.lib.osam_get_rom_path(self.h, sd, C.byref(p)))
         return p.value
 
+    def set_engine(self, engine: int):
+        """0: automatic (the single-step explicit path where it applies), 1: the window engine."""
+        self._check(self.lib.osam_set_engine(self.h, int(engine)))
+
+    def solver_stats(self, sd: int) -> List[int]:
+        """Most CG (FOM) or Newton (OpInf) iterations of an implicit sub-step, per instance."""
+        out = (C.c_int32 * self.batch)()
+        self._check(self.lib.osam_get_solver_stats(self.h, sd, out))
+        return list(out)
+
     def sync(self):
         self._check(self.lib.osam_sync(self.h))
 
@@ -539,10 +554,16 @@ def free_dof_map(nx: int, ny: int, nzs: int) -> np.ndarray:
     return out.ravel()
 
 
-def add_bar_subdomains(ctx: Context, bar, layers, dt: float, lateral_fix=()) -> List[int]:
-    """Create one FOM subdomain per node-layer range of a bar (inputs.Bar)."""
+def add_bar_subdomains(ctx: Context, bar, layers, dt: float, lateral_fix=(), beta=0.0, gamma=0.5,
+                       n_sub=None) -> List[int]:
+    """Create one FOM subdomain per node-layer range of a bar (inputs.Bar); beta, gamma: one
+    value or one per subdomain; n_sub: Newmark steps per controller step dt, per subdomain."""
+    k = len(layers)
+    per = lambda x: list(x) if isinstance(x, (list, tuple)) else [x] * k
+    betas, gammas, subs = per(beta), per(gamma), per(1 if n_sub is None else n_sub)
     return [ctx.create_subdomain(bar.nx, bar.ny, bar.nz, bar.Lx, bar.Ly, bar.Lz, lo, hi, bar.E, bar.nu,
-                                 bar.rho, dt, lateral_fix=lateral_fix) for lo, hi in layers]
+                                 bar.rho, dt, lateral_fix=lateral_fix, beta=b, gamma=g, n_sub=s)
+            for (lo, hi), b, g, s in zip(layers, betas, gammas, subs)]
 
 
 def lib_dof_index(nx: int, ny: int, nzs: int, dofs: np.ndarray) -> np.ndarray:
