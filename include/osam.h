@@ -245,6 +245,20 @@ int32_t schwarz_step(osam_ctx *ctx, const osam_schwarz_opts *opts, osam_instance
  * at its last finite step; the others complete).  info: [batch] or NULL. */
 int32_t run(osam_ctx *ctx, int64_t n_steps, const osam_schwarz_opts *opts, osam_instance_info *info);
 
+/* run without any device allocation, for callers that cannot allocate device
+ * memory (work under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels, results and iteration counts as run, except
+ * that the per-workgroup partial sums of Eq. conv_criterion live in a static
+ * device array of the library (32 MiB per GPU, held until the process ends)
+ * instead of the context's buffers, and graph mode and kernel timing are off for
+ * the call.  The context must be wired (osam_set_initial done for every instance)
+ * and, for a context the window engine runs (osam_set_engine), that engine set up
+ * by a first run call: OSAM_E_ORDER otherwise.  OSAM_E_INVALID when the partial
+ * sums need more than 32 MiB (16 bytes x batch x the FOM subdomains' workgroups).
+ * Every call on one GPU shares the array, so calls that overlap on the same GPU
+ * (other threads, other contexts) race: serialise them. */
+int32_t run_noalloc(osam_ctx *ctx, int64_t n_steps, const osam_schwarz_opts *opts, osam_instance_info *info);
+
 /* Trajectory misfit of the coupled rollout and its gradient (discrete adjoint).
  *
  * Not a passage of the paper: a calibration tool around its method.  With the

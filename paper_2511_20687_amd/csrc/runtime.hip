@@ -258,6 +258,9 @@ int32_t osam_ctx_create(osam_ctx **out, int32_t device, int32_t precision, int32
   ctx->device = device;
   ctx->prec = precision;
   ctx->batch = batch;
+  // the static scratch array of run_noalloc, looked up once per device (null on failure:
+  // run_noalloc then reports it)
+  if (static_scratch_address(device, &ctx->static_scratch) != OSAM_OK) ctx->static_scratch = nullptr;
   if (stream) {
     ctx->stream = static_cast<hipStream_t>(stream);
     ctx->own_stream = false;

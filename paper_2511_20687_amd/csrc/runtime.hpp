@@ -179,6 +179,10 @@ struct Ctx {
   bool window_mode() const;
   int32_t window_setup();
   int32_t run_window(int64_t n_steps, const Opts &o, osam_instance_info *info);
+  // device address of the static scratch array on this context's device (noalloc.hip)
+  void *static_scratch = nullptr;
 };
+
+int32_t static_scratch_address(int device, void **out);
 
 }  // namespace osam

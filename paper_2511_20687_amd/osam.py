@@ -29,7 +29,7 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
             "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_set_fusion", "osam_set_fe_xshare",
             "osam_autotune",
-            "osam_sync", "osam_set_engine", "osam_get_solver_stats"]
+            "osam_sync", "osam_set_engine", "osam_get_solver_stats", "run_noalloc"]
 
 
 class OsamError(RuntimeError):
@@ -165,6 +165,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_get_rom_path.restype = i32
     lib.osam_sync.argtypes = [vp]
     lib.osam_sync.restype = i32
+    lib.run_noalloc.argtypes = [vp, i64, C.POINTER(SchwarzOpts), C.POINTER(InstanceInfo)]
+    lib.run_noalloc.restype = i32
     lib.osam_set_engine.argtypes = [vp, i32]
     lib.osam_set_engine.restype = i32
     lib.osam_get_solver_stats.argtypes = [vp, i32, C.POINTER(i32)]
@@ -413,6 +415,16 @@ class Context:
         self._order_in()
         self._check(self.lib.schwarz_step(self.h, C.byref(o), info))
         self._order_out()
+        return self._info_list(info)
+
+    def run_noalloc(self, n_steps: int, opts: Options = Options()) -> List[dict]:
+        """run without device allocation (partial sums in the library's static array)."""
+        info = self._infos()
+        o = opts.c()
+        self._order_in()
+        st = self.lib.run_noalloc(self.h, n_steps, C.byref(o), info)
+        self._order_out()
+        self._check(st)
         return self._info_list(info)
 
     def run(self, n_steps: int, opts: Options = Options(), check: bool = True) -> List[dict]:
