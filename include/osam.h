@@ -64,7 +64,8 @@ typedef enum {
  * 2^-9 relative in that term). */
 typedef enum { OSAM_FP64 = 0, OSAM_FP32 = 1, OSAM_FP32_BF16H = 2 } osam_precision;
 typedef enum { OSAM_GUESS_HOLD = 0, OSAM_GUESS_PREDICTOR = 1 } osam_guess;
-typedef enum { OSAM_LINEAR = 0, OSAM_QUADRATIC = 1 } osam_form;
+typedef enum { OSAM_LINEAR = 0, OSAM_QUADRATIC = 1, OSAM_CUBIC = 2 } osam_form;
+typedef enum { OSAM_LINEAR_ELASTIC = 0, OSAM_SVK = 1 } osam_material;
 
 typedef struct osam_ctx osam_ctx;
 
@@ -92,9 +93,13 @@ const char *osam_last_error(const osam_ctx *ctx);
  * subdomain advances a controller step dt in n_sub Newmark steps of dt / n_sub
  * (Sec. 4.1, mixed time steps; its Schwarz data at the intermediate times come
  * from the source's trajectory through the temporal interpolant Xi, linear in
- * time).  All subdomains share dt.  Contexts whose subdomains are all explicit
- * with gamma = 1/2 and n_sub = 1 run the single-step path of run; any other
- * context runs the window engine (osam_set_engine). */
+ * time).  All subdomains share dt.  material = OSAM_SVK replaces the linear
+ * internal force K u by the Saint Venant-Kirchhoff force f(u) (App. A.2: Green-
+ * Lagrange strain, S = lam tr(E) I + 2 mu E, P = F S, total Lagrangian, the same
+ * 2x2x2 Gauss rule), a cubic polynomial of the nodal displacements.  Contexts
+ * whose subdomains are all linear elastic and explicit with gamma = 1/2 and
+ * n_sub = 1 run the single-step path of run; any other context runs the window
+ * engine (osam_set_engine). */
 typedef struct {
   int32_t nx, ny, nz;          /* global grid, elements per axis (>= 1)     */
   double Lx, Ly, Lz;           /* box size                                  */
@@ -109,6 +114,9 @@ typedef struct {
                                   1/2 <= gamma <= 1                         */
   int32_t n_sub;               /* Newmark steps per controller step (0 or 1:
                                   one; at most 64)                          */
+  int32_t material;            /* OSAM_LINEAR_ELASTIC (App. A.1) or OSAM_SVK:
+                                  Saint Venant-Kirchhoff (App. A.2), explicit
+                                  scheme only (beta = 0)                    */
 } osam_subdomain_desc;
 
 /* Append a FOM subdomain; *sd_id receives its index (0, 1, ...).  The
@@ -176,7 +184,10 @@ int32_t osam_set_record(osam_ctx *ctx, int32_t sd, const osam_record *rec);
  * (0 or 1: every step).  The fit is pointwise in time (Udd holds the Newmark
  * accelerations of the snapshot times); the Alg. 3 rollout takes `stride`
  * steps between snapshots with the boundary input interpolated linearly
- * between the two snapshots. */
+ * between the two snapshots.  form: OSAM_LINEAR, OSAM_QUADRATIC (q (x) q columns)
+ * or OSAM_CUBIC (also the q (x) q (x) q columns of COpInf, the ansatz of the Saint
+ * Venant-Kirchhoff model, App. A.2; the cubic operator is read back with
+ * osam_get_opinf_cubic). */
 typedef struct {
   int32_t form, with_c;
   int32_t r, r_s;
@@ -203,6 +214,16 @@ int32_t osam_set_opinf(osam_ctx *ctx, int32_t sd, int32_t r, int32_t r_s, const 
  * sizes above (any may be NULL). */
 int32_t osam_get_opinf(osam_ctx *ctx, int32_t sd, double *Phi, double *PhiS, double *A, double *H,
                        double *B, double *c);
+/* Cubic operator of an OpInf subdomain (COpInf, Eq. opinf_rom: the term
+ * C (q (x) q (x) q) of the Saint Venant-Kirchhoff ansatz), host float64
+ * column-major [r x r(r+1)(r+2)/6] over the compressed cubic power q_a q_b q_c,
+ * a <= b <= c in lexicographic order; NULL removes it.  Call after
+ * osam_set_opinf (or learn_opinf) and before osam_set_initial (the instances
+ * need their initial condition again).  OpInf subdomains with a cubic term run
+ * in the window engine.  OSAM_E_ORDER for a FOM subdomain. */
+int32_t osam_set_opinf_cubic(osam_ctx *ctx, int32_t sd, const double *C);
+/* Read back the cubic operator (zeros when there is none). */
+int32_t osam_get_opinf_cubic(osam_ctx *ctx, int32_t sd, double *C);
 
 /* Schwarz options (Eq. conv_criterion): converged when n >= min_iter and
  * sum_i ||du_i + dt_i dv_i||^2 < tol_abs^2 or that sum < tol_rel^2 sum_i

@@ -423,6 +423,13 @@ int32_t Ctx::rom_start(int i, int inst, const std::vector<double> &q, const std:
     for (int j = 0; j < d.r; ++j) s += d.oh.A[(size_t)j * d.r + i2] * q[j];
     if (d.oh.quadratic)
       for (int m = 0; m < r2; ++m) s += d.oh.H[(size_t)m * d.r + i2] * k2[m];
+    if (!d.oh.C3.empty()) {
+      // cubic term: q_a q_b q_c, a <= b <= c, lexicographic
+      size_t m = 0;
+      for (int a = 0; a < d.r; ++a)
+        for (int b = a; b < d.r; ++b)
+          for (int cc = b; cc < d.r; ++cc, ++m) s += d.oh.C3[m * d.r + i2] * q[a] * q[b] * q[cc];
+    }
     for (int l = 0; l < d.rs; ++l) s += d.oh.B[(size_t)l * d.r + i2] * gh[l];
     qdd[i2] = s;
   }

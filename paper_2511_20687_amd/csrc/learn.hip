@@ -38,13 +38,14 @@ hipError_t launch_trsv_block(const double *, long long, int, int, double *, long
 hipError_t launch_add_diag(double *, long long, int, double, hipStream_t);
 hipError_t launch_colnorm_max(const double *, int, long long, double *, hipStream_t);
 hipError_t launch_scale(double *, long long, double, double, hipStream_t);
-hipError_t launch_data_matrix(const double *, int, const double *, int, long long, int, int, double *, hipStream_t);
+hipError_t launch_data_matrix(const double *, int, const double *, int, long long, int, int, int, double *,
+                              hipStream_t);
 hipError_t launch_jacobi_round(const double *, double *, const double *, double *, int, int, hipStream_t);
 hipError_t launch_offnorm(const double *, long long, double *, int, hipStream_t);
 hipError_t launch_identity(double *, long long, hipStream_t);
 hipError_t launch_gather_cols(const double *, long long, const int *, int, double *, hipStream_t);
-hipError_t launch_rollout(const double *, int, int, int, int, int, const double *, const double *, const double *,
-                          const double *, long long, int, int, double, int, double *, hipStream_t);
+hipError_t launch_rollout(const double *, int, int, int, int, int, int, const double *, const double *,
+                          const double *, const double *, long long, int, int, double, int, double *, hipStream_t);
 
 namespace {
 
@@ -302,10 +303,12 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   if (NS > 0) {
     if (!L.pod<T>(S, NS, Tt, d.r_s, d.energy_bnd, PhiS, rs, sigS)) return ctx->fail(L.code, L.err);
   }
-  const int quad = d.form == OSAM_QUADRATIC;
+  const int quad = d.form == OSAM_QUADRATIC || d.form == OSAM_CUBIC;
+  const int cubic = d.form == OSAM_CUBIC;
   const int r2 = quad ? r * (r + 1) / 2 : 0;
+  const int r3 = cubic ? r * (r + 1) * (r + 2) / 6 : 0;
   const int with_c = d.with_c ? 1 : 0;
-  const int p = r + r2 + rs + with_c;
+  const int p = r + r2 + r3 + rs + with_c;
 
   // 2. reduced data Q = Phi^T U, Qdd = Phi^T U'', S^ = Phi_S^T S, q'0 = Phi^T v0
   double *Q = L.alloc((size_t)r * Tt), *Qdd = L.alloc((size_t)r * Tt), *Qd0 = L.alloc((size_t)r * ntraj);
@@ -333,7 +336,7 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   if (rs > 0) L.ok(launch_scale(Sh, (long long)rs * Tt, 1.0, alpha, L.s), "scale");
   double *D = L.alloc((size_t)Tt * p);
   if (L.code) return ctx->fail(L.code, L.err);
-  L.ok(launch_data_matrix(Q, r, Sh, rs, Tt, quad, with_c, D, L.s), "data matrix");
+  L.ok(launch_data_matrix(Q, r, Sh, rs, Tt, quad, cubic, with_c, D, L.s), "data matrix");
 
   // 3. normal equations (primal when p <= T, dual otherwise)
   const bool primal = p <= Tt;
@@ -385,7 +388,7 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   if (nlam > 1) {
     double *ro = L.alloc((size_t)nlam * ntraj * 5);
     if (L.code) return ctx->fail(L.code, L.err);
-    L.ok(launch_rollout(Xall, p, r, r2, rs, with_c, Q, Qd0, Qdd, Sh, Tn, ntraj, nlam, 1.0, std::max(1, d.stride), ro,
+    L.ok(launch_rollout(Xall, p, r, r2, r3, rs, with_c, Q, Qd0, Qdd, Sh, Tn, ntraj, nlam, 1.0, std::max(1, d.stride), ro,
                         L.s),
          "rollout");
     std::vector<double> h = L.down(ro, (size_t)nlam * ntraj * 5);
@@ -422,10 +425,17 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
     for (int i = 0; i < r; ++i)
       for (int m = 0; m < r2; ++m) oh.H[(size_t)i + (size_t)m * r] = X[(size_t)(r + m) + (size_t)i * p] / (dt2 * alpha);
   }
+  if (cubic) {
+    oh.C3.assign((size_t)r * r3, 0.0);
+    for (int i = 0; i < r; ++i)
+      for (int m = 0; m < r3; ++m)
+        oh.C3[(size_t)i + (size_t)m * r] = X[(size_t)(r + r2 + m) + (size_t)i * p] / (dt2 * alpha * alpha);
+  }
   if (rs > 0) {
     oh.B.assign((size_t)r * rs, 0.0);
     for (int i = 0; i < r; ++i)
-      for (int l2 = 0; l2 < rs; ++l2) oh.B[(size_t)i + (size_t)l2 * r] = X[(size_t)(r + r2 + l2) + (size_t)i * p] / dt2;
+      for (int l2 = 0; l2 < rs; ++l2)
+        oh.B[(size_t)i + (size_t)l2 * r] = X[(size_t)(r + r2 + r3 + l2) + (size_t)i * p] / dt2;
     oh.PhiS = L.down(PhiS, (size_t)NS * rs);
   }
   if (with_c) {
@@ -452,7 +462,7 @@ int32_t Ctx::learn(int sdi, const osam_opinf_desc &d) {
   if (sd.rom) return fail(OSAM_E_INVALID, "subdomain is already an OpInf model");
   if (d.n_traj < 1 || d.T < 2 || !d.U || !d.Udd || !d.V0 || (sd.nsch_nodes > 0 && !d.S))
     return fail(OSAM_E_INVALID, "bad snapshot description");
-  if (d.form != OSAM_LINEAR && d.form != OSAM_QUADRATIC) return fail(OSAM_E_INVALID, "bad form");
+  if (d.form != OSAM_LINEAR && d.form != OSAM_QUADRATIC && d.form != OSAM_CUBIC) return fail(OSAM_E_INVALID, "bad form");
   if (d.r <= 0 && !(d.energy > 0.0 && d.energy <= 1.0)) return fail(OSAM_E_INVALID, "bad energy threshold");
   if (d.n_lambda < 0 || (d.n_lambda > 0 && !d.lambdas)) return fail(OSAM_E_INVALID, "bad lambda grid");
   for (int l = 0; l < d.n_lambda; ++l)

@@ -646,9 +646,10 @@ hipError_t launch_scale(double *x, long long n, double mul, double div, hipStrea
 
 // ---------------------------------------------------------------------------
 // Data matrix of Eq. opinf_schwarz_inference, D (T x p, column-major):
-// columns [q_i | q_i q_j (i<=j, row by row) | s^_l | 1].
+// columns [q_i | q_i q_j (i<=j, row by row) | q_i q_j q_k (i<=j<=k, lexicographic;
+// the cubic ansatz of COpInf) | s^_l | 1].
 __global__ void data_matrix_kernel(const double *Q, int r, const double *Sh, int rs, long long T, int quad,
-                                   int with_c, double *D) {
+                                   int cubic, int with_c, double *D) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   int col = 0;
@@ -658,13 +659,19 @@ __global__ void data_matrix_kernel(const double *Q, int r, const double *Sh, int
       const double qi = Q[i + t * r];
       for (int j = i; j < r; ++j) D[t + (long long)(col++) * T] = qi * Q[j + t * r];
     }
+  if (cubic)
+    for (int i = 0; i < r; ++i)
+      for (int j = i; j < r; ++j) {
+        const double qij = Q[i + t * r] * Q[j + t * r];
+        for (int k = j; k < r; ++k) D[t + (long long)(col++) * T] = qij * Q[k + t * r];
+      }
   for (int l = 0; l < rs; ++l) D[t + (long long)(col++) * T] = Sh[l + t * rs];
   if (with_c) D[t + (long long)col * T] = 1.0;
 }
-hipError_t launch_data_matrix(const double *Q, int r, const double *Sh, int rs, long long T, int quad, int with_c,
-                              double *D, hipStream_t s) {
+hipError_t launch_data_matrix(const double *Q, int r, const double *Sh, int rs, long long T, int quad, int cubic,
+                              int with_c, double *D, hipStream_t s) {
   hipLaunchKernelGGL(data_matrix_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, Q, r, Sh, rs, T, quad,
-                     with_c, D);
+                     cubic, with_c, D);
   return hipGetLastError();
 }
 
@@ -674,7 +681,7 @@ hipError_t launch_data_matrix(const double *Q, int r, const double *Sh, int rs, 
 // Each workgroup runs the T-step explicit Newmark recursion with the Schwarz
 // input frozen to the training data, and accumulates ||q - q_train||^2,
 // ||q_train||^2, max ||q||, max ||q_train|| and a non-finite flag.
-__global__ void __launch_bounds__(256) rollout_kernel(const double *X, int p, int r, int r2, int rs, int with_c,
+__global__ void __launch_bounds__(256) rollout_kernel(const double *X, int p, int r, int r2, int r3, int rs, int with_c,
                                                       const double *Q, const double *Qd0, const double *Qdd,
                                                       const double *Sh, long long T, int ntraj, double dt,
                                                       int stride, double *out) {
@@ -721,9 +728,20 @@ __global__ void __launch_bounds__(256) rollout_kernel(const double *X, int p, in
           const int i = e / r, jj = e - i * r;
           if (jj >= i) z[r + i * r - (i * (i - 1)) / 2 + (jj - i)] = z[i] * z[jj];
         }
+      if (r3 > 0)
+        for (int e = tid; e < r * r; e += bs) {
+          // pair (i, jj), i <= jj: the run of columns q_i q_jj q_k, k = jj .. r-1
+          const int i = e / r, jj = e - i * r;
+          if (jj < i) continue;
+          int base = 0;
+          for (int a = 0; a < i; ++a) base += (r - a) * (r - a + 1) / 2;
+          for (int b = i; b < jj; ++b) base += r - b;
+          const double qij = z[i] * z[jj];
+          for (int k = jj; k < r; ++k) z[r + r2 + base + (k - jj)] = qij * z[k];
+        }
       const double w1 = (double)m / (double)stride;
       for (int e = tid; e < rs; e += bs)
-        z[r + r2 + e] = Sht[j * rs + e] + w1 * (Sht[(j + 1) * rs + e] - Sht[j * rs + e]);
+        z[r + r2 + r3 + e] = Sht[j * rs + e] + w1 * (Sht[(j + 1) * rs + e] - Sht[j * rs + e]);
       if (with_c && tid == 0) z[p - 1] = 1.0;
       __syncthreads();
       // q'' = X^T z : one wave per output
@@ -767,13 +785,13 @@ __global__ void __launch_bounds__(256) rollout_kernel(const double *X, int p, in
     o[4] = bad ? 1.0 : 0.0;
   }
 }
-hipError_t launch_rollout(const double *X, int p, int r, int r2, int rs, int with_c, const double *Q,
+hipError_t launch_rollout(const double *X, int p, int r, int r2, int r3, int rs, int with_c, const double *Q,
                           const double *Qd0, const double *Qdd, const double *Sh, long long T, int ntraj, int nlam,
                           double dt, int stride, double *out, hipStream_t s) {
   const size_t smem = sizeof(double) * (size_t)(p + 3 * r);
   if (smem > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rollout_kernel, dim3(nlam * ntraj), dim3(256), smem, s, X, p, r, r2, rs, with_c, Q, Qd0, Qdd,
-                     Sh, T, ntraj, dt, stride, out);
+  hipLaunchKernelGGL(rollout_kernel, dim3(nlam * ntraj), dim3(256), smem, s, X, p, r, r2, r3, rs, with_c, Q, Qd0,
+                     Qdd, Sh, T, ntraj, dt, stride, out);
   return hipGetLastError();
 }
 

@@ -328,6 +328,10 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   if (!(d->beta >= 0.0 && d->beta <= 0.5 && d->gamma >= 0.5 && d->gamma <= 1.0))
     return ctx->fail(OSAM_E_INVALID, "Newmark parameters outside 0 <= beta <= 1/2, 1/2 <= gamma <= 1");
   if (d->n_sub < 0 || d->n_sub > 64) return ctx->fail(OSAM_E_INVALID, "n_sub must be in 0..64");
+  if (d->material != OSAM_LINEAR_ELASTIC && d->material != OSAM_SVK)
+    return ctx->fail(OSAM_E_INVALID, "material must be OSAM_LINEAR_ELASTIC or OSAM_SVK");
+  if (d->material == OSAM_SVK && d->beta != 0.0)
+    return ctx->fail(OSAM_E_INVALID, "the Saint Venant-Kirchhoff material takes the explicit scheme (beta = 0)");
   const bool ext_lo = d->z_lo == 0, ext_hi = d->z_hi == d->nz;
   if ((ext_lo || ext_hi) && !d->clamp_ends)
     return ctx->fail(OSAM_E_INVALID, "traction-free exterior z-faces are not supported (clamp_ends = 1)");
@@ -532,6 +536,35 @@ int32_t osam_get_opinf(osam_ctx *c, int32_t sdi, double *Phi, double *PhiS, doub
   if (H && o.quadratic) std::copy(o.H.begin(), o.H.end(), H);
   if (B) std::copy(o.B.begin(), o.B.end(), B);
   if (cvec && !o.c.empty()) std::copy(o.c.begin(), o.c.end(), cvec);
+  return OSAM_OK;
+}
+
+int32_t osam_set_opinf_cubic(osam_ctx *c, int32_t sdi, const double *C3) {
+  if (!c) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  ctx->err.clear();
+  if (sdi < 0 || sdi >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  Subdomain &s = *ctx->sds[sdi];
+  if (!s.rom) return ctx->fail(OSAM_E_ORDER, "osam_set_opinf_cubic follows osam_set_opinf or learn_opinf");
+  const long long r = s.r, r3 = r * (r + 1) * (r + 2) / 6;
+  if (C3) s.oh.C3.assign(C3, C3 + (size_t)r * r3);
+  else s.oh.C3.clear();
+  // the initial states (q''0) and the window engine's buffers depend on it
+  ctx->win_ready = false;
+  std::fill(ctx->initialized.begin(), ctx->initialized.end(), 0);
+  return OSAM_OK;
+}
+
+int32_t osam_get_opinf_cubic(osam_ctx *c, int32_t sdi, double *C3) {
+  if (!c || !C3) return OSAM_E_INVALID;
+  Ctx *ctx = reinterpret_cast<Ctx *>(c);
+  ctx->err.clear();
+  if (sdi < 0 || sdi >= (int)ctx->sds.size()) return ctx->fail(OSAM_E_INVALID, "bad subdomain id");
+  const Subdomain &s = *ctx->sds[sdi];
+  if (!s.rom) return ctx->fail(OSAM_E_INVALID, "not an OpInf subdomain");
+  const long long r = s.r, r3 = r * (r + 1) * (r + 2) / 6;
+  if (s.oh.C3.empty()) std::fill(C3, C3 + (size_t)r * r3, 0.0);
+  else std::copy(s.oh.C3.begin(), s.oh.C3.end(), C3);
   return OSAM_OK;
 }
 

@@ -24,7 +24,9 @@ namespace osam {
 bool Ctx::window_mode() const {
   if (engine == 1) return true;
   for (const auto &s : sds)
-    if (s->desc.beta != 0.0 || s->desc.gamma != 0.5 || s->n_sub > 1 || !s->oh.C3.empty()) return true;
+    if (s->desc.beta != 0.0 || s->desc.gamma != 0.5 || s->n_sub > 1 || !s->oh.C3.empty() ||
+        (!s->rom && s->desc.material != OSAM_LINEAR_ELASTIC))
+      return true;
   return false;
 }
 
@@ -221,7 +223,7 @@ static int fill_exports(Ctx &c, int i, T *(&traj)[kWinMaxExp][2], int *layer, co
 }
 
 template <typename T>
-static int32_t launch_window_sd(Ctx &c, int i, int l, const Opts &o) {
+static int32_t launch_window_sd(Ctx &c, int i, int l, const Opts &o, bool svk_init = false) {
   Subdomain &d = *c.sds[i];
   const WinBufs &w = d.win;
   const bool implicit = d.desc.beta != 0.0;
@@ -230,6 +232,18 @@ static int32_t launch_window_sd(Ctx &c, int i, int l, const Opts &o) {
   if (!d.rom) {
     WinFomArgs<T> A;
     std::memset(&A, 0, sizeof(A));
+    A.material = d.desc.material;
+    const osam_subdomain_desc &g = d.desc;
+    A.lam = (T)(g.E * g.nu / ((1 + g.nu) * (1 - 2 * g.nu)));
+    A.mu = (T)(g.E / (2 * (1 + g.nu)));
+    A.hx = (T)(g.Lx / g.nx);
+    A.hy = (T)(g.Ly / g.ny);
+    A.hz = (T)(g.Lz / g.nz);
+    A.rho = (T)g.rho;
+    A.lateral_fix = g.lateral_fix;
+    A.nfree_nodes = d.nfree_nodes;
+    A.rec_ncols = d.rec.n_cols;
+    A.rec_a0 = d.rec.every > 0 && d.rec.n_cols > 0 ? (T *)d.rec.a : nullptr;
     A.nx = d.nx;
     A.ny = d.ny;
     A.nzs = d.nzs;
@@ -272,7 +286,7 @@ static int32_t launch_window_sd(Ctx &c, int i, int l, const Opts &o) {
     A.nsd = (int)c.sds.size();
     A.sums = c.win_sums;
     A.cg_iters = w.iters;
-    e = launch_win_fom<T>(A, c.batch, c.stream);
+    e = svk_init ? launch_win_svk_init<T>(A, c.batch, c.stream) : launch_win_fom<T>(A, c.batch, c.stream);
   } else {
     WinRomArgs<T> A;
     std::memset(&A, 0, sizeof(A));
@@ -373,6 +387,12 @@ int32_t Ctx::run_window(int64_t n_steps, const Opts &o, osam_instance_info *info
   int32_t st = window_setup();
   if (st) return st;
   const bool f64 = prec == OSAM_FP64;
+  // Saint Venant-Kirchhoff subdomains: the set-up's a0 used the linear stiffness
+  for (size_t i = 0; i < sds.size(); ++i)
+    if (!sds[i]->rom && sds[i]->desc.material == OSAM_SVK) {
+      st = f64 ? launch_window_sd<double>(*this, (int)i, 1, o, true) : launch_window_sd<float>(*this, (int)i, 1, o, true);
+      if (st) return st;
+    }
   for (int64_t k = 0; k < n_steps; ++k) {
     bool any = false;
     for (int b = 0; b < batch; ++b) {

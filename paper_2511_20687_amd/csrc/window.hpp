@@ -56,6 +56,13 @@ struct WinFomArgs {
   int sd, nsd;
   double *sums;                   // [batch][nsd][2]: Eq. conv_criterion sums of this iteration
   int *cg_iters;                  // [batch]: most CG iterations of any solve (statistics)
+  // Saint Venant-Kirchhoff material (App. A.2): the internal force of the box
+  // elements evaluated at the 2x2x2 Gauss points instead of the linear stencil
+  int material;                   // 0 linear elastic, 1 Saint Venant-Kirchhoff
+  T lam, mu, hx, hy, hz, rho;
+  int lateral_fix;                // components held at zero on the lateral faces
+  T *rec_a0;                      // SVK initial state: column 0 of the acceleration record, or null
+  long long rec_ncols, nfree_nodes;
 };
 
 template <typename T>
@@ -105,6 +112,8 @@ struct WinAcceptArgs {
 
 template <typename T>
 hipError_t launch_win_fom(const WinFomArgs<T> &A, int batch, hipStream_t s);
+template <typename T>
+hipError_t launch_win_svk_init(const WinFomArgs<T> &A, int batch, hipStream_t s);
 template <typename T>
 hipError_t launch_win_rom(const WinRomArgs<T> &A, int batch, hipStream_t s);
 hipError_t launch_win_decide(Status *st, const double *sums, const Opts &o, int batch, hipStream_t s);

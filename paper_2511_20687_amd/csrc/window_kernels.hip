@@ -130,6 +130,94 @@ __device__ __forceinline__ void node_force(const WinFomArgs<T> &A, const T *U, i
   }
 }
 
+// -M^-1 f(u) at free node (k, ix, iy) for the Saint Venant-Kirchhoff material
+// (App. A.2): f_a = sum over the node's elements and their 2x2x2 Gauss points of
+// w det(J) P grad N_a, with F = I + grad u, E = (F^T F - I)/2, S = lam tr(E) I +
+// 2 mu E, P = F S (total Lagrangian).  Box elements: dN_b/dX are products of
+// the 1D factors (1 +- xi)/2 and +-1/h; det(J) = hx hy hz / 8, unit weights.
+template <typename T>
+__device__ __forceinline__ void node_force_svk(const WinFomArgs<T> &A, const T *U, int k, int ix, int iy,
+                                               T (&acc)[3]) {
+  const int nx = A.nx, ny = A.ny, nxp = nx + 1, npl = A.npl;
+  const long long cs = A.cs;
+  const T g = T(0.57735026918962576451);   // 1/sqrt(3)
+  const T ih[3] = {T(1) / A.hx, T(1) / A.hy, T(1) / A.hz};
+  const T wdet = A.hx * A.hy * A.hz / T(8);
+  T f[3] = {T(0), T(0), T(0)};
+  int nel = 0;
+  for (int oz = 0; oz < 2; ++oz)
+    for (int oy = 0; oy < 2; ++oy)
+      for (int ox = 0; ox < 2; ++ox) {
+        // element with lower corner (ix - 1 + ox, iy - 1 + oy, k - 1 + oz); this node is its corner (1-ox, 1-oy, 1-oz)
+        const int ex = ix - 1 + ox, ey = iy - 1 + oy, ez = k - 1 + oz;
+        if (ex < 0 || ex >= nx || ey < 0 || ey >= ny) continue;
+        ++nel;
+        const int ca[3] = {1 - ox, 1 - oy, 1 - oz};
+        T ue[8][3];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const long long o = (long long)(ez + (b >> 2)) * npl + (ex + (b & 1)) + nxp * (ey + ((b >> 1) & 1));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) ue[b][c] = U[c * cs + o];
+        }
+#pragma unroll
+        for (int gp = 0; gp < 8; ++gp) {
+          const T xi[3] = {(gp & 1) ? g : -g, ((gp >> 1) & 1) ? g : -g, (gp >> 2) ? g : -g};
+          // 1D factors (1 + s xi)/2 per axis and corner coordinate d (s = 2d - 1)
+          T h1[3][2], dh[2] = {T(-0.5), T(0.5)};
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            h1[ax][0] = T(0.5) * (T(1) - xi[ax]);
+            h1[ax][1] = T(0.5) * (T(1) + xi[ax]);
+          }
+          T Gu[3][3] = {};
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int d0 = b & 1, d1 = (b >> 1) & 1, d2 = b >> 2;
+            const T dN[3] = {T(2) * dh[d0] * h1[1][d1] * h1[2][d2] * ih[0], T(2) * dh[d1] * h1[0][d0] * h1[2][d2] * ih[1],
+                             T(2) * dh[d2] * h1[0][d0] * h1[1][d1] * ih[2]};
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) Gu[i][j] += ue[b][i] * dN[j];
+          }
+          T F[3][3], E[3][3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) F[i][j] = Gu[i][j] + (i == j ? T(1) : T(0));
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+              T s = T(0);
+#pragma unroll
+              for (int m = 0; m < 3; ++m) s += F[m][i] * F[m][j];
+              E[i][j] = T(0.5) * (s - (i == j ? T(1) : T(0)));
+            }
+          const T tr = E[0][0] + E[1][1] + E[2][2];
+          const T dNa[3] = {T(2) * dh[ca[0]] * h1[1][ca[1]] * h1[2][ca[2]] * ih[0],
+                            T(2) * dh[ca[1]] * h1[0][ca[0]] * h1[2][ca[2]] * ih[1],
+                            T(2) * dh[ca[2]] * h1[0][ca[0]] * h1[1][ca[1]] * ih[2]};
+          // S dN_a, then f += w det(J) F (S dN_a)
+          T sd[3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            T s = T(0);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) s += (T(2) * A.mu * E[i][j] + (i == j ? A.lam * tr : T(0))) * dNa[j];
+            sd[i] = s;
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i) f[i] += wdet * (F[i][0] * sd[0] + F[i][1] * sd[1] + F[i][2] * sd[2]);
+        }
+      }
+  const T m = A.rho * wdet * T(nel);
+  const bool lateral = ix == 0 || ix == nx || iy == 0 || iy == ny;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = (lateral && (A.lateral_fix & (1 << c))) ? T(0) : -f[c] / m;
+}
+
 // Weight of a free node in the lumped-mass inner product (proportional to its
 // mass: the number of adjacent elements).
 __device__ __forceinline__ double mass_weight(int ix, int iy, int nx, int ny) {
@@ -215,7 +303,8 @@ __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A
     const int k = (int)(g / npl), nid = (int)(g - (long long)k * npl);
     const int ix = nid % nxp, iy = nid / nxp;
     T acc[3];
-    node_force<T>(A, uo, k, ix, iy, acc);
+    if (A.material) node_force_svk<T>(A, uo, k, ix, iy, acc);
+    else node_force<T>(A, uo, k, ix, iy, acc);
     if (!A.implicit) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -541,6 +630,32 @@ __global__ __launch_bounds__(kWinRomThreads) void win_rom_kernel(WinRomArgs<T> A
   }
 }
 
+// Initial acceleration a0 = -M^-1 f(u0) of a Saint Venant-Kirchhoff subdomain for the
+// instances that have not advanced yet (step 0), and column 0 of its acceleration record
+// (the set-up computed them with the linear stiffness).
+template <typename T>
+__global__ __launch_bounds__(kWinFomThreads) void win_svk_init_kernel(WinFomArgs<T> A) {
+  const int b = blockIdx.y;
+  const Status st = A.status[b];
+  if (st.step != 0 || (st.flags & kNonfinite)) return;
+  const long long ib = (long long)b * A.is;
+  const T *u = A.u[0] + ib;
+  T *a = A.a[0] + ib;
+  const int npl = A.npl, nxp = A.nx + 1;
+  const long long nfn = (long long)npl * (A.nzs - 1);
+  for (long long h = threadIdx.x; h < nfn; h += kWinFomThreads) {
+    const long long g = h + npl;
+    const int k = (int)(g / npl), nid = (int)(g - (long long)k * npl);
+    T acc[3];
+    node_force_svk<T>(A, u, k, nid % nxp, nid / nxp, acc);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a[c * A.cs + g] = acc[c];
+      if (A.rec_a0) A.rec_a0[(long long)b * A.rec_ncols * 3 * A.nfree_nodes + c * A.nfree_nodes + h] = acc[c];
+    }
+  }
+}
+
 // Eq. conv_criterion after the last subdomain of an iteration (one thread per instance).
 __global__ void win_decide_kernel(Status *status, const double *sums, Opts o, int batch) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -608,6 +723,11 @@ hipError_t launch_win_fom(const WinFomArgs<T> &A, int batch, hipStream_t s) {
   return hipGetLastError();
 }
 template <typename T>
+hipError_t launch_win_svk_init(const WinFomArgs<T> &A, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(win_svk_init_kernel<T>, dim3(1, batch), dim3(kWinFomThreads), 0, s, A);
+  return hipGetLastError();
+}
+template <typename T>
 hipError_t launch_win_rom(const WinRomArgs<T> &A, int batch, hipStream_t s) {
   const size_t smem = sizeof(T) * (3 * (size_t)A.r + A.rs);
   hipLaunchKernelGGL(win_rom_kernel<T>, dim3(1, batch), dim3(kWinRomThreads), smem, s, A);
@@ -626,6 +746,8 @@ hipError_t launch_win_accept(const WinAcceptArgs<T> &A, int batch, hipStream_t s
 
 template hipError_t launch_win_fom<double>(const WinFomArgs<double> &, int, hipStream_t);
 template hipError_t launch_win_fom<float>(const WinFomArgs<float> &, int, hipStream_t);
+template hipError_t launch_win_svk_init<double>(const WinFomArgs<double> &, int, hipStream_t);
+template hipError_t launch_win_svk_init<float>(const WinFomArgs<float> &, int, hipStream_t);
 template hipError_t launch_win_rom<double>(const WinRomArgs<double> &, int, hipStream_t);
 template hipError_t launch_win_rom<float>(const WinRomArgs<float> &, int, hipStream_t);
 template hipError_t launch_win_accept<double>(const WinAcceptArgs<double> &, int, hipStream_t);

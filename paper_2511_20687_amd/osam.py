@@ -29,7 +29,8 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_set_fe_launch", "osam_get_fe_launch", "osam_set_reduced", "run_adjoint",
             "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_set_fusion", "osam_set_fe_xshare",
             "osam_autotune",
-            "osam_sync", "osam_set_engine", "osam_get_solver_stats", "run_noalloc"]
+            "osam_sync", "osam_set_engine", "osam_get_solver_stats", "run_noalloc", "osam_set_opinf_cubic",
+            "osam_get_opinf_cubic"]
 
 
 class OsamError(RuntimeError):
@@ -44,7 +45,7 @@ class SubdomainDesc(C.Structure):
                 ("z_lo", C.c_int32), ("z_hi", C.c_int32),
                 ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
                 ("clamp_ends", C.c_int32), ("lateral_fix", C.c_int32), ("dt", C.c_double),
-                ("beta", C.c_double), ("gamma", C.c_double), ("n_sub", C.c_int32)]
+                ("beta", C.c_double), ("gamma", C.c_double), ("n_sub", C.c_int32), ("material", C.c_int32)]
 
 
 class Record(C.Structure):
@@ -165,6 +166,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_get_rom_path.restype = i32
     lib.osam_sync.argtypes = [vp]
     lib.osam_sync.restype = i32
+    lib.osam_set_opinf_cubic.argtypes = [vp, i32, dp]
+    lib.osam_set_opinf_cubic.restype = i32
+    lib.osam_get_opinf_cubic.argtypes = [vp, i32, dp]
+    lib.osam_get_opinf_cubic.restype = i32
     lib.run_noalloc.argtypes = [vp, i64, C.POINTER(SchwarzOpts), C.POINTER(InstanceInfo)]
     lib.run_noalloc.restype = i32
     lib.osam_set_engine.argtypes = [vp, i32]
@@ -270,14 +275,15 @@ class Context:
 
     # -- set-up ------------------------------------------------------------
     def create_subdomain(self, nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, dt,
-                         clamp_ends=True, beta=0.0, gamma=0.5, lateral_fix=(), n_sub=1) -> int:
+                         clamp_ends=True, beta=0.0, gamma=0.5, lateral_fix=(), n_sub=1, material="linear") -> int:
         """lateral_fix: components (0 = x, 1 = y, 2 = z) held at zero on the lateral faces;
-        dt: the controller step, taken in n_sub Newmark steps of dt / n_sub."""
+        dt: the controller step, taken in n_sub Newmark steps of dt / n_sub; material:
+        "linear" (linear elasticity) or "svk" (Saint Venant-Kirchhoff)."""
         mask = 0
         for c in lateral_fix:
             mask |= 1 << int(c)
         d = SubdomainDesc(nx, ny, nz, Lx, Ly, Lz, z_lo, z_hi, E, nu, rho, int(clamp_ends), mask, dt,
-                          beta, gamma, int(n_sub))
+                          beta, gamma, int(n_sub), {"linear": 0, "svk": 1}[material])
         sid = C.c_int32()
         self._check(self.lib.create_subdomain(self.h, C.byref(d), C.byref(sid)))
         self.n_sd += 1
@@ -359,6 +365,18 @@ class Context:
         self._check(self.lib.osam_set_opinf(self.h, sd, r, rs, p(Phi), p(PhiS_f), p(A_f), p(H_f),
                                             p(B_f), p(c_f)))
 
+    def set_opinf_cubic(self, sd: int, C3):
+        """Cubic operator [r x r(r+1)(r+2)/6] (compressed q_a q_b q_c, a <= b <= c), or None."""
+        Cf = None if C3 is None else np.asfortranarray(np.asarray(C3, dtype=np.float64))
+        self._check(self.lib.osam_set_opinf_cubic(self.h, sd, None if Cf is None else
+                                                  Cf.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def get_opinf_cubic(self, sd: int):
+        r = self.sizes(sd)["r"]
+        Cf = np.zeros((r, r * (r + 1) * (r + 2) // 6), order="F")
+        self._check(self.lib.osam_get_opinf_cubic(self.h, sd, Cf.ctypes.data_as(C.POINTER(C.c_double))))
+        return Cf
+
     def get_opinf(self, sd: int, quadratic: bool = False, with_c: bool = False):
         z = self.sizes(sd)
         r, rs, nf, ns = z["r"], z["r_s"], z["n_free"], z["n_sch"]
@@ -391,7 +409,7 @@ class Context:
         E = np.zeros(len(lam))
         ls = C.c_double()
         ro, rso = C.c_int32(), C.c_int32()
-        d = OpinfDesc(1 if form == "quadratic" else 0, int(with_c), r, r_s, energy, energy_bnd, len(lam),
+        d = OpinfDesc({"linear": 0, "quadratic": 1, "cubic": 2}[form], int(with_c), r, r_s, energy, energy_bnd, len(lam),
                       _dptr(lam), n_traj, T, _devptr(U), _devptr(Udd), _devptr(S), _devptr(V0),
                       _dptr(sig), _dptr(E), C.pointer(ls), C.pointer(ro), C.pointer(rso), stride)
         self._order_in()
@@ -567,15 +585,15 @@ def free_dof_map(nx: int, ny: int, nzs: int) -> np.ndarray:
 
 
 def add_bar_subdomains(ctx: Context, bar, layers, dt: float, lateral_fix=(), beta=0.0, gamma=0.5,
-                       n_sub=None) -> List[int]:
+                       n_sub=None, material="linear") -> List[int]:
     """Create one FOM subdomain per node-layer range of a bar (inputs.Bar); beta, gamma: one
     value or one per subdomain; n_sub: Newmark steps per controller step dt, per subdomain."""
     k = len(layers)
     per = lambda x: list(x) if isinstance(x, (list, tuple)) else [x] * k
-    betas, gammas, subs = per(beta), per(gamma), per(1 if n_sub is None else n_sub)
+    betas, gammas, subs, mats = per(beta), per(gamma), per(1 if n_sub is None else n_sub), per(material)
     return [ctx.create_subdomain(bar.nx, bar.ny, bar.nz, bar.Lx, bar.Ly, bar.Lz, lo, hi, bar.E, bar.nu,
-                                 bar.rho, dt, lateral_fix=lateral_fix, beta=b, gamma=g, n_sub=s)
-            for (lo, hi), b, g, s in zip(layers, betas, gammas, subs)]
+                                 bar.rho, dt, lateral_fix=lateral_fix, beta=b, gamma=g, n_sub=s, material=m)
+            for (lo, hi), b, g, s, m in zip(layers, betas, gammas, subs, mats)]
 
 
 def lib_dof_index(nx: int, ny: int, nzs: int, dofs: np.ndarray) -> np.ndarray:
