@@ -33,9 +33,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 algorithmic bytes per FE DOF-iteration-update of the explicit step kernel:
-# read P, V0, A0, V1(prev) and write V1, A1, P2 (7 x 4 B) on free DOFs.
-FE_BYTES_PER_DOF = 28.0
+# FP32 algorithmic bytes per FE DOF-iteration-update (the unit of work of the explicit
+# step): read u, v, a at t_{k-1} and the previous iterate's u, v; write u, v, a; the lumped
+# mass, 4 B per node (8 x 4 B + 4/3 B)
+FE_BYTES_PER_DOF = 32.0 + 4.0 / 3.0
+# what the step kernel itself moves per DOF: read P, V0, A0, V1(prev), write V1, A1, P2
+# (7 x 4 B; the mass is folded into the stencil coefficients, u(t_k) is the predictor P)
+FE_KERNEL_BYTES_PER_DOF = 28.0
 
 
 def _log(msg):
@@ -109,6 +113,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched OpInf-OpInf comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-large-fe", action="store_true", help="skip the 64x64x640 FE step timing")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the 4x4x40 legs (explicit, implicit, mixed steps, Saint Venant-Kirchhoff)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -206,8 +212,12 @@ def main():
         recs.append(t)
     ctx.set_initial(0, u0, v0)
     ctx.run(n, opts)
-    Phi = torch.tensor(ctx.get_opinf(1)["Phi"], dtype=torch.float64, device=dev)
+    learned_ops = ctx.get_opinf(1)
+    Phi = torch.tensor(learned_ops["Phi"], dtype=torch.float64, device=dev)
     hyb = [recs[0][0].double(), (Phi @ recs[1][0].double().T).T]
+    # the first recorded columns, for the comparison with the FP64 oracle
+    hyb_head = [recs[0][0, : args.cpu_steps // every + 1].double().cpu().numpy(),
+                recs[1][0, : args.cpu_steps // every + 1].double().cpu().numpy()]
     del recs
     ff = build_context(w, w.precision)
     frec = []
@@ -255,10 +265,25 @@ def main():
     if not args.no_large_fe:
         large_fe = large_fe_timing(_log)
 
-    # ---- CPU oracle on a bounded sample ----
+    # ---- latency-bound legs on the 4x4x40 bar (both engines) ----
+    latency = None
+    if not args.no_latency:
+        from paper_2511_20687_amd import window_case
+        latency = _guarded("latency legs", lambda: window_case.run(_log))
+
+    # ---- CPU oracle: timed on a bounded sample; every GPU result's error against it ----
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = _guarded("CPU baseline", lambda: cpu_baseline(w, pulse, args.cpu_steps, learned))
+        cpu = _guarded("CPU baseline",
+                       lambda: cpu_baseline(w, pulse, args.cpu_steps, every, learned_ops, hyb_head))
+        if latency and "error" not in latency:
+            oracle_legs = _guarded("oracle of the latency legs", lambda: oracle_latency_legs(latency))
+            for k, v in latency.items():
+                if k.startswith("_"):
+                    continue
+                v[0].update(oracle_legs.get(k, {}) if isinstance(oracle_legs, dict) else {})
+    if latency and "error" not in latency:
+        latency = {k: v[0] for k, v in latency.items() if not k.startswith("_")}
 
     line = {
         "metric": "coupled Schwarz steps/s (FOM-OpInf hybrid, <=1e-3 rel err target vs FOM-FOM)",
@@ -283,6 +308,7 @@ def main():
         "fom_fom_steps_per_s": fom_fom_value,
         "speedup_vs_fom_fom": value / fom_fom_value,
         "rel_err_vs_fom_fom": {"fom_subdomain": errs[0], "opinf_subdomain": errs[1]},
+        "rel_err_vs_fp64_oracle": (cpu or {}).get("rel_err_vs_fp64_oracle"),
         "fe_dof_updates_per_s": dof_updates_per_s,
         "fe_kernel_avg_us": fe_avg_us,
         "rom_kernel_avg_us": 1e3 * rom_ms / max(rom_launches, 1),
@@ -299,13 +325,15 @@ def main():
                                 if tuning["fe"][0][0] == 1024 else "fe_kernel<float, step>"),
                      "kernel_avg_us": k_avg_us,
                      "launch_shape": ([512, tuning["fusion_kc"]] if fused else tuning["fe"][0]),
-                     "bytes_per_dof": FE_BYTES_PER_DOF, "dofs_per_launch": fe_dofs,
+                     "bytes_per_dof": FE_BYTES_PER_DOF, "kernel_bytes_per_dof": FE_KERNEL_BYTES_PER_DOF,
+                     "dofs_per_launch": fe_dofs,
                      "algorithmic_bytes_per_launch": alg_bytes, "fe_bytes_per_launch": fe_alg,
                      "rom_bytes_per_launch": rom_alg if fused else None},
         "cpu_baseline": cpu,
         "batched_opinf_opinf": batched,
         "adjoint": adjoint,
         "large_fe": large_fe,
+        "latency_legs_bar_4x4x40": latency,
     }
     print(json.dumps(line), flush=True)
 
@@ -389,46 +417,109 @@ def adjoint_timing(log):
                 operators="seeded synthetic, learned sizes (r=60 quadratic, r_S=10)")
 
 
-def cpu_baseline(w, pulse, n_steps, learned):
-    """FP64 oracle, one thread, on the first n_steps controller steps of the same hybrid.
+def _oracle_index(model):
+    """Library free-DOF index of each oracle free DOF, and library Schwarz-DOF index of each
+    oracle Schwarz DOF, of a bar subdomain (argument marshalling between the two layouts)."""
+    from paper_2511_20687_amd.osam import lib_dof_index
+    bar = model.bar
+    nzs = model.z_hi - model.z_lo
+    free = lib_dof_index(bar.nx, bar.ny, nzs, model.free_dofs)
+    npl = (bar.nx + 1) * (bar.ny + 1)
+    node, comp = model.sch_dofs // 3, model.sch_dofs % 3
+    lo_face = model.z_lo > 0
+    nsch = npl * (int(lo_face) + int(model.z_hi < bar.nz))
+    pos = np.where(node < npl, node, node - nzs * npl + (npl if lo_face else 0))
+    return free, comp * nsch + pos
 
-    The oracle's ROM uses seeded synthetic operators of the learned sizes (the
-    per-step cost does not depend on their values)."""
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def cpu_baseline(w, pulse, n_steps, every, ops, hyb_head):
+    """FP64 oracle, one thread, on the first n_steps controller steps of the same hybrid with
+    the operators the GPU learned; the error of the GPU's FP32 run against it (Eq. mse over
+    the steps recorded every `every` steps, free DOFs / reduced coordinates)."""
     from threadpoolctl import threadpool_limits
     from oracle.newmark import FomModel, SubdomainGeometry
     from oracle.rom import OpInfModel
     from oracle.schwarz import Coupled, SchwarzOptions
-    from paper_2511_20687_amd.inputs import synthetic_rom
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         lo, hi = w.layers[0]
         fom = FomModel(w.bar, lo, hi, w.dt, lateral_fix=w.lateral_fix)
         g = SubdomainGeometry(w.bar, *w.layers[1], lateral_fix=w.lateral_fix)
-        R = synthetic_rom(7, g.n_free, g.n_sch, learned["r"], max(learned["r_s"], 1), w.dt)
-        rom = OpInfModel(g, R["Phi"], R["PhiS"], R["A"], None, R["B"], None, dt=w.dt)
+        free, sch = _oracle_index(g)
+        rom = OpInfModel(g, ops["Phi"][free], ops["PhiS"][sch] if ops["PhiS"].shape[1] else None, ops["A"], None,
+                         ops["B"] if ops["B"].shape[1] else None, None, dt=w.dt)
         cp = Coupled([fom, rom])
         u0 = pulse.u0(w.bar)
         st = cp.initial_states(u0, np.zeros_like(u0))
         t_setup = time.perf_counter() - t0
         opts = SchwarzOptions(tol_abs=w.tol_abs, tol_rel=w.tol_rel, guess="predictor" if w.guess else "hold")
+        rec = [[fom.free_u(st[0])], [st[1].q.copy()]]
         t0 = time.perf_counter()
         its = 0
-        for _ in range(n_steps):
+        for k in range(1, n_steps + 1):
             st, info = cp.step(st, opts)
             its += info.iters
+            if k % every == 0:
+                rec[0].append(fom.free_u(st[0]))
+                rec[1].append(st[1].q.copy())
         t = time.perf_counter() - t0
-    cpu_model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu_model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+    ffree, _ = _oracle_index(fom)
+    errs = {"fom_subdomain": _rel(hyb_head[0][:, ffree], np.array(rec[0])),
+            "opinf_subdomain": _rel(hyb_head[1], np.array(rec[1])),
+            "steps_compared": f"0..{n_steps} every {every} (FP32 GPU run vs this FP64 oracle run)"}
     return {"value": n_steps / t, "unit": "controller steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_steps} controller steps of the same FOM-OpInf hybrid (FP64 numpy/scipy, "
-                      f"one thread; setup {t_setup:.1f} s excluded; {its / n_steps:.2f} Schwarz iterations/step)",
-            "cpu_model": cpu_model, "host_cpus": os.cpu_count()}
+            "sample": f"first {n_steps} controller steps of the same FOM-OpInf hybrid with the operators the GPU "
+                      f"learned (FP64 numpy/scipy, one thread; setup {t_setup:.1f} s excluded; "
+                      f"{its / n_steps:.2f} Schwarz iterations/step)",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "rel_err_vs_fp64_oracle": errs}
+
+
+def oracle_latency_legs(legs):
+    """The FP64 oracle on each 4x4x40 leg (full length, one thread): its steps/s and the Eq. mse
+    error of the GPU's FP64 records against it."""
+    from threadpoolctl import threadpool_limits
+    from oracle.newmark import FomModel
+    from oracle.schwarz import Coupled, SchwarzOptions
+    from oracle.svk import SvkFomModel
+    inp = legs["_inputs"]
+    bar, layers = inp["bar"], inp["layers"]
+    out = {}
+    for name, leg in legs.items():
+        if name.startswith("_"):
+            continue
+        res, recs = leg
+        models = []
+        for (lo, hi), beta, ns in zip(layers, res["beta"], res["n_sub"]):
+            cls = SvkFomModel if res["material"] == "svk" else FomModel
+            m = cls(bar, lo, hi, res["dt"] / ns, lateral_fix=(0, 1)) if cls is SvkFomModel else \
+                cls(bar, lo, hi, res["dt"] / ns, beta=beta, lateral_fix=(0, 1))
+            m.n_sub = ns
+            models.append(m)
+        u0 = inp["u_svk"] if res["material"] == "svk" else inp["u0"]
+        n = res["controller_steps"]
+        every = n // (recs[0].shape[0] - 1)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            ref = Coupled(models).run(u0, np.zeros_like(u0), n, SchwarzOptions(), every=every, record=("u",))
+            t = time.perf_counter() - t0
+        errs = [_rel(recs[i][:, _oracle_index(m)[0]], ref["u"][i]) for i, m in enumerate(models)]
+        out[name] = {"rel_err_vs_fp64_oracle": errs, "oracle_steps_per_s": n / t,
+                     "oracle_iters_per_step": float(ref["iters"].mean()), "gpu_vs_oracle_speed": res["steps_per_s"] * t / n}
+    return out
 
 
 if __name__ == "__main__":

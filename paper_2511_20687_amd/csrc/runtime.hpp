@@ -176,6 +176,7 @@ struct Ctx {
   bool win_ready = false;
   std::vector<void *> win_allocs;
   double *win_sums = nullptr;      // [batch][nsd][2]
+  int win_iters_hint = 0;          // iterations the last controller step took (read-backs start there)
   bool window_mode() const;
   int32_t window_setup();
   int32_t run_window(int64_t n_steps, const Opts &o, osam_instance_info *info);

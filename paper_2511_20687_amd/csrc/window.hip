@@ -7,6 +7,7 @@
 // multiplicative (or additive) order, then the decision of Eq. conv_criterion;
 // after min_iter iterations the host reads the per-instance status back to stop
 // iterating once every instance has converged.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -273,7 +274,7 @@ static int32_t launch_window_sd(Ctx &c, int i, int l, const Opts &o, bool svk_in
     A.n_sub = d.n_sub;
     A.l = l;
     A.implicit = implicit;
-    const double tol = c.prec == OSAM_FP64 ? 1e-13 : 1e-6;
+    const double tol = c.prec == OSAM_FP64 ? 1e-14 : 1e-6;
     A.cg_tol2 = tol * tol;
     A.cg_max = 1000;
     A.additive = o.additive;
@@ -415,7 +416,9 @@ int32_t Ctx::run_window(int64_t n_steps, const Opts &o, osam_instance_info *info
         }
       const hipError_t e = launch_win_decide(d_status, win_sums, o, batch, stream);
       if (e != hipSuccess) return fail(OSAM_E_HIP, hipGetErrorString(e));
-      if (n >= o.min_iter || n == o.max_iter) {
+      // read the status back only from the iteration count the previous step needed on
+      // (iterations of instances that have converged are no-ops)
+      if (n >= std::max(o.min_iter, win_iters_hint) || n == o.max_iter) {
         if ((st = sync_status())) return st;
         bool done = true;
         for (int b = 0; b < batch; ++b)
@@ -423,6 +426,9 @@ int32_t Ctx::run_window(int64_t n_steps, const Opts &o, osam_instance_info *info
         if (done) break;
       }
     }
+    win_iters_hint = 0;
+    for (int b = 0; b < batch; ++b)
+      if (h_status[b].pad0 & 1) win_iters_hint = std::max(win_iters_hint, h_status[b].last_iters);
     for (size_t i = 0; i < sds.size(); ++i) {
       st = f64 ? launch_window_accept<double>(*this, (int)i) : launch_window_accept<float>(*this, (int)i);
       if (st) return st;

@@ -13,6 +13,7 @@ namespace osam {
 constexpr int kWinMaxExp = 4;   // faces of other subdomains one subdomain feeds
 constexpr int kWinFomThreads = 512;
 constexpr int kWinRomThreads = 256;
+constexpr size_t kWinLdsBytes = 144 * 1024;   // dynamic LDS of the FOM kernel's LDS-resident variant
 
 // The source of one Schwarz face.
 template <typename T>

@@ -92,12 +92,24 @@ __device__ __forceinline__ bool src_ready(int j, int sd, int n, int additive, in
 // cs): the 27-point stencil sum_d C_d (u_{i+d} - u_i); interior nodes use the
 // interior block's 27 distinct values, boundary columns their case block.
 template <typename T>
-__device__ __forceinline__ void node_force(const WinFomArgs<T> &A, const T *U, int k, int ix, int iy, T (&acc)[3]) {
+__device__ __forceinline__ void node_force(const WinFomArgs<T> &A, const T *coef, const T *U, int k, int ix, int iy,
+                                           T (&acc)[3]) {
   const int nx = A.nx, ny = A.ny, nxp = nx + 1, npl = A.npl;
   const long long cs = A.cs;
-  T w[27][3];
+  T ctr[3];
+  {
+    const long long o = (long long)k * npl + ix + nxp * iy;
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
+    for (int c = 0; c < 3; ++c) ctr[c] = U[c * cs + o];
+  }
+  acc[0] = acc[1] = acc[2] = T(0);
+  const int cx = ix == 0 ? 0 : (ix == nx ? 2 : 1), cy = iy == 0 ? 0 : (iy == ny ? 2 : 1);
+  const bool interior = cx == 1 && cy == 1;
+  const T *C = coef + (cx + 3 * cy) * 234;
+  // one z-slab (9 neighbours) at a time keeps the live values to a slab
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz) {
+    T w[9][3];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -105,28 +117,23 @@ __device__ __forceinline__ void node_force(const WinFomArgs<T> &A, const T *U, i
         const int jx = min(max(ix + dx - 1, 0), nx), jy = min(max(iy + dy - 1, 0), ny);
         const long long o = (long long)(k + dz - 1) * npl + jx + nxp * jy;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) w[dz * 9 + dy * 3 + dx][c] = U[c * cs + o];
+        for (int c = 0; c < 3; ++c) w[dy * 3 + dx][c] = U[c * cs + o];
       }
-  acc[0] = acc[1] = acc[2] = T(0);
-  const int cx = ix == 0 ? 0 : (ix == nx ? 2 : 1), cy = iy == 0 ? 0 : (iy == ny ? 2 : 1);
-  if (cx == 1 && cy == 1) {
 #pragma unroll
-    for (int d27 = 0; d27 < 27; ++d27) {
+    for (int n9 = 0; n9 < 9; ++n9) {
+      const int d27 = dz * 9 + n9;
       if (d27 == 13) continue;
-      const T d[3] = {w[d27][0] - w[13][0], w[d27][1] - w[13][1], w[d27][2] - w[13][2]};
-      xrow<T>(A.cb, d27, d, acc);
+      const T d[3] = {w[n9][0] - ctr[0], w[n9][1] - ctr[1], w[n9][2] - ctr[2]};
+      if (interior) {
+        xrow<T>(A.cb, d27, d, acc);
+      } else {
+        const int d26 = d27 < 13 ? d27 : d27 - 1;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) acc[p] += C[d26 * 9 + p * 3 + q] * d[q];
+      }
     }
-    return;
-  }
-  const T *C = A.coef + (cx + 3 * cy) * 234;
-#pragma unroll
-  for (int d27 = 0; d27 < 27; ++d27) {
-    if (d27 == 13) continue;
-    const int d26 = d27 < 13 ? d27 : d27 - 1;
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) acc[p] += C[d26 * 9 + p * 3 + q] * (w[d27][q] - w[13][q]);
   }
 }
 
@@ -233,10 +240,13 @@ __device__ __forceinline__ double mass_weight(int ix, int iy, int nx, int ny) {
 //   beta > 0: (M + beta dt^2 K_ff) a+ = -K [u~; u_c]  by conjugate gradients in the
 //             M inner product (M^-1 K is self-adjoint there), u+ = u~ + beta dt^2 a+;
 //   v+ = v + dt ((1 - gamma) a + gamma a+).
-template <typename T>
+// LDS: the displacement being formed and the CG vectors live in the workgroup's LDS
+// (subdomains small enough: the latency-bound sizes), the results are copied out once.
+template <typename T, bool LDS, bool SVK>
 __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A) {
   constexpr int NT = kWinFomThreads;
   __shared__ double red[NT / 64];
+  extern __shared__ unsigned char win_lds[];
   const int b = blockIdx.y, tid = threadIdx.x;
   const Status st = A.status[b];
   if (st.flags & kFinished) return;
@@ -265,13 +275,38 @@ __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A
     ao = A.ta[l & 1] + ib;
   }
   const T dt = A.dt, pc = (T(0.5) - A.beta) * dt * dt;
+  const bool implicit = !SVK && A.implicit;   // the SVK material takes the explicit scheme
   int par[2] = {0, 0};
   bool ready[2] = {false, false};
   for (int f = 0; f < 2; ++f)
     if (A.src[f].kind) ready[f] = src_ready(A.src[f].sd, A.sd, n, A.additive, par[f]);
+  // working vectors: the displacement U and the acceleration / CG iterate X, and the CG
+  // residual R, direction P and product Q ([3][cs] each)
+  const long long v3 = 3 * cs;
+  T *const ls = reinterpret_cast<T *>(win_lds);
+  T *const uo_g = uo, *const ao_g = ao;
+  if (LDS) {
+    uo = ls;
+    if (implicit) ao = ls + v3;
+  }
+  T *const Rw = LDS ? ls + 2 * v3 : A.cr + ib, *const Pw = LDS ? ls + 3 * v3 : A.cp + ib;
+  T *const Qw = LDS ? ls + 4 * v3 : A.cq + ib;
+  // the case blocks of the boundary columns (LDS: after the working vectors)
+  const T *coef = A.coef;
+  if (LDS) {
+    T *lc = ls + (implicit ? 5 : 1) * v3;
+    for (int i = tid; i < 9 * 234; i += NT) lc[i] = A.coef[i];
+    coef = lc;   // read after the barrier that ends the predictor phase
+  }
 
   // predictor on free layers, Schwarz data (or zero) on the two faces
   const long long nn = A.nnodes;
+  if (LDS && implicit)   // the faces of the CG direction stay zero
+    for (long long g = tid; g < 2 * npl; g += NT) {
+      const long long gg = g < npl ? g : g - npl + (long long)nzs * npl;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Pw[c * cs + gg] = T(0);
+    }
   for (long long g = tid; g < nn; g += NT) {
     const int k = (int)(g / npl), nid = (int)(g - (long long)k * npl);
     if (k == 0 || k == nzs) {
@@ -303,9 +338,9 @@ __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A
     const int k = (int)(g / npl), nid = (int)(g - (long long)k * npl);
     const int ix = nid % nxp, iy = nid / nxp;
     T acc[3];
-    if (A.material) node_force_svk<T>(A, uo, k, ix, iy, acc);
-    else node_force<T>(A, uo, k, ix, iy, acc);
-    if (!A.implicit) {
+    if constexpr (SVK) node_force_svk<T>(A, uo, k, ix, iy, acc);
+    else node_force<T>(A, coef, uo, k, ix, iy, acc);
+    if (!implicit) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const long long o = c * cs + g;
@@ -314,20 +349,23 @@ __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A
       }
     } else {
       const double wgt = mass_weight(ix, iy, nx, ny);
-      T *R = A.cr + ib;
+      T *R = Rw;
+      // first iterate: the previous Schwarz iterate's acceleration at the same time (one
+      // sub-step per controller step), else the acceleration of the state stepped from
+      const T *x0 = (n >= 2 && A.n_sub == 1) ? A.wa[(n - 1) & 1] + ib : ai;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const long long o = c * cs + g;
         R[o] = acc[c];   // right-hand side b
-        ao[o] = acc[c];  // first iterate x0 = b
+        ao[o] = x0[o];
         bb += wgt * (double)acc[c] * (double)acc[c];
       }
     }
   }
-  if (A.implicit) {
+  if (implicit) {
     // conjugate gradients on (I + c L) x = b, L = M^-1 K_ff (c = beta dt^2), in the
     // inner product weighted by the lumped mass; x lives in ao, r in cr, p in cp, q in cq
-    T *R = A.cr + ib, *P = A.cp + ib, *Q = A.cq + ib;
+    T *R = Rw, *P = Pw, *Q = Qw;
     const T cc = A.beta * dt * dt;
     bb = block_sum<NT>(bb, red);   // also orders the writes of x0 before the stencil reads
     // r0 = b - (I + c L) x0, p0 = r0
@@ -337,7 +375,7 @@ __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A
       const int k = (int)(g / npl), nid = (int)(g - (long long)k * npl);
       const int ix = nid % nxp, iy = nid / nxp;
       T acc[3];
-      node_force<T>(A, ao, k, ix, iy, acc);
+      node_force<T>(A, coef, ao, k, ix, iy, acc);
       const double wgt = mass_weight(ix, iy, nx, ny);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -361,7 +399,7 @@ __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A
         const int k = (int)(g / npl), nid = (int)(g - (long long)k * npl);
         const int ix = nid % nxp, iy = nid / nxp;
         T acc[3];
-        node_force<T>(A, P, k, ix, iy, acc);
+        node_force<T>(A, coef, P, k, ix, iy, acc);
         const double wgt = mass_weight(ix, iy, nx, ny);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -411,6 +449,15 @@ __global__ __launch_bounds__(kWinFomThreads) void win_fom_kernel(WinFomArgs<T> A
         vo[o] = vi[o] + dt * ((T(1) - A.gamma) * ai[o] + A.gamma * x);
       }
     }
+  }
+  if (LDS) {
+    __syncthreads();
+    for (long long g = tid; g < nn; g += NT)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uo_g[c * cs + g] = uo[c * cs + g];
+        if (implicit) ao_g[c * cs + g] = ao[c * cs + g];
+      }
   }
   __syncthreads();
 
@@ -719,7 +766,22 @@ __global__ void win_accept_kernel(WinAcceptArgs<T> A) {
 
 template <typename T>
 hipError_t launch_win_fom(const WinFomArgs<T> &A, int batch, hipStream_t s) {
-  hipLaunchKernelGGL(win_fom_kernel<T>, dim3(1, batch), dim3(kWinFomThreads), 0, s, A);
+  // small subdomains keep their working vectors in LDS (one vector explicit, five implicit)
+  const size_t lds = sizeof(T) * (3 * (size_t)A.cs * (A.implicit ? 5 : 1) + 9 * 234);
+  const bool svk = A.material != 0;
+  if (lds <= kWinLdsBytes) {
+    const void *f = svk ? (const void *)win_fom_kernel<T, true, true> : (const void *)win_fom_kernel<T, true, false>;
+    if (lds > 64 * 1024) {   // dynamic LDS beyond the default limit must be requested
+      const hipError_t ea = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (ea != hipSuccess) return ea;
+    }
+    if (svk) hipLaunchKernelGGL((win_fom_kernel<T, true, true>), dim3(1, batch), dim3(kWinFomThreads), lds, s, A);
+    else hipLaunchKernelGGL((win_fom_kernel<T, true, false>), dim3(1, batch), dim3(kWinFomThreads), lds, s, A);
+  } else if (svk) {
+    hipLaunchKernelGGL((win_fom_kernel<T, false, true>), dim3(1, batch), dim3(kWinFomThreads), 0, s, A);
+  } else {
+    hipLaunchKernelGGL((win_fom_kernel<T, false, false>), dim3(1, batch), dim3(kWinFomThreads), 0, s, A);
+  }
   return hipGetLastError();
 }
 template <typename T>

@@ -5,7 +5,7 @@ and the implicit Newmark scheme (beta = 1/4) on FOM (conjugate gradients) and Op
 
 Bar 3 x 3 x 30 (about 300 nodes per subdomain, several workgroup strides of the node loops),
 synthetic OpInf operators (seeded, r = 7).  Tolerances: FP64 1e-10 on the recorded
-trajectories (the implicit solves stop at a relative residual of 1e-13) and equal iteration
+trajectories (the implicit solves stop at a relative residual of 1e-14) and equal iteration
 counts; FP32 1e-4.  The convergence sums of every step are compared with the oracle's
 (relative 1e-8: they are differences of nearly equal iterates near convergence).
 """
@@ -124,8 +124,10 @@ def test_window_engine_explicit_single_step_matches_oracle(kinds, quadratic):
 @pytest.mark.parametrize("guess,additive", [("hold", False), ("predictor", False), ("hold", True)])
 def test_implicit_fom_fom_matches_oracle(guess, additive):
     """Implicit Newmark (beta = 1/4) at 16 times the explicit step with tight tolerances: a
-    genuinely geometric Schwarz iteration (6-7 sweeps per step in the oracle)."""
-    tight = dict(tol_abs=1e-14, tol_rel=1e-12, max_iter=64)
+    genuinely geometric Schwarz iteration (6 sweeps per step in the oracle).  The relative
+    tolerance 1e-10 stays well above the error of the GPU's iterative solves (relative
+    residual 1e-14, condition number about 50), so both sides stop at the same iterate."""
+    tight = dict(tol_abs=1e-14, tol_rel=1e-10, max_iter=64)
     bar, layers, ref, ctx, recs, info = _run_case(("fom", "fom"), [0.25, 0.25], [1, 1], 16.0, guess, additive,
                                                   "f64", n=40, opts=tight)
     _compare(bar, layers, ("fom", "fom"), recs, ref, 1e-10)
