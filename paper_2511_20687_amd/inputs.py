@@ -238,7 +238,7 @@ CFG2 = Workload("fom_opinf_bar_24x24x240_r40", Bar(24, 24, 240), 2, ("fom", "opi
                 "f32", form="linear", r=40, seed=2, train_steps=2000, tol_rel=1.0e-6, guess=1)
 CFG3 = Workload("opinf_opinf_bar_48x48x480_r100_b256", Bar(48, 48, 480), 2, ("opinf", "opinf"),
                 2000, "f32", form="quadratic", r=100, batch=256, seed=3, train_steps=2000,
-                train_runs=4, train_stride=4, tol_rel=1.0e-6, pulse_width=0.05, guess=1)
+                train_runs=16, train_stride=16, tol_rel=1.0e-6, pulse_width=0.05, guess=1)
 CFG4 = Workload("adjoint_fom_qopinf_bar_24x24x240_r60", Bar(24, 24, 240), 2, ("fom", "opinf"),
                 2000, "f32", form="quadratic", r=60, seed=4, train_steps=2000, checkpoint=100,
                 tol_rel=1.0e-6)
