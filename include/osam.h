@@ -147,6 +147,36 @@ int32_t osam_set_reduced(osam_ctx *ctx, int32_t sd, int32_t inst, const double *
  * fields Phi q, Phi q', Phi q'' (Sec. 4.2), lifted on the device, on free DOFs and
  * zero on Schwarz and Dirichlet DOFs. */
 int32_t osam_get_state(osam_ctx *ctx, int32_t sd, int32_t inst, double *u, double *v, double *a);
+/* Set the accepted state of subdomain sd, instance inst, at the instance's current
+ * step (restart from stored fields; Alg. 1 advances from the accepted state at
+ * t_{k-1}).  FOM: x, xd, xdd = u, v, a as host float64 [3][n_nodes] in the layout
+ * osam_get_state returns (the values on Schwarz faces are the data last imposed;
+ * held and clamped components must be zero).  OpInf: q, q', q'' host float64 [r]
+ * (osam_get_reduced).  Set every subdomain of the instance before the next step.
+ * The window engine advances from the accepted state alone, so a state saved with
+ * osam_get_state / osam_get_reduced continues bit for bit there.  The single-step
+ * path derives the next predictor and the values pushed to neighbours from it before
+ * the next step (the acceleration of a FOM subdomain is recomputed as M^-1(-K u),
+ * which is what the explicit step produced); the push of an OpInf subdomain into a
+ * FOM face is formed on the host in FP64 and may differ from the kernel's in the
+ * last bit (osam_save_checkpoint restores such contexts exactly).  The step counter
+ * is not changed.  OSAM_E_ORDER before osam_set_initial. */
+int32_t osam_set_state(osam_ctx *ctx, int32_t sd, int32_t inst, const double *x, const double *xd,
+                       const double *xdd);
+
+/* Raw checkpoint of one instance: every device range that carries state from one
+ * controller step to the next (the accepted state in all its buffer roles, the
+ * values pushed for the next step, OpInf predictors) and the instance's step
+ * counters.  osam_checkpoint_size gives the bytes of one instance (the same for
+ * every instance); osam_save_checkpoint copies instance inst into host memory of
+ * that size; osam_load_checkpoint restores it into instance inst of this or another
+ * context with the same subdomains, precision and engine, after which run continues
+ * bit for bit as the saved instance would have.  Records are not part of it.
+ * OSAM_E_ORDER before osam_set_initial. */
+int32_t osam_checkpoint_size(osam_ctx *ctx, int64_t *bytes);
+int32_t osam_save_checkpoint(osam_ctx *ctx, int32_t inst, void *host);
+int32_t osam_load_checkpoint(osam_ctx *ctx, int32_t inst, const void *host);
+
 /* Reduced state (q, q', q'') of an OpInf subdomain, host float64 [r] each. */
 int32_t osam_get_reduced(osam_ctx *ctx, int32_t sd, int32_t inst, double *q, double *qd,
                          double *qdd);

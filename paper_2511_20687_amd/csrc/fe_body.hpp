@@ -172,8 +172,8 @@ __device__ __forceinline__ void fe_xs_one(const FeArgs<T> &A, int b, int t, int 
   long long rcol = 0, rbase = 0;
   bool rec = false;
   if (A.rec_every > 0) {
-    rcol = (MODE == kModeInit) ? 0 : (step + 1) / A.rec_every;
-    rec = rcol < A.rec_ncols && (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
+    rcol = (MODE == kModeInit ? step : step + 1) / A.rec_every;   // the state this launch completes
+    rec = rcol < A.rec_ncols && ((MODE == kModeInit ? step : step + 1) % A.rec_every) == 0;
     rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
   }
   const unsigned voff = (unsigned)f * (unsigned)sizeof(T);   // (nid0 - nxp) bytes
@@ -260,8 +260,8 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   long long rcol = 0, rbase = 0;
   bool rec = false;
   if (A.rec_every > 0) {
-    rcol = (MODE == kModeInit) ? 0 : (step + 1) / A.rec_every;
-    rec = rcol < A.rec_ncols && (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
+    rcol = (MODE == kModeInit ? step : step + 1) / A.rec_every;   // the state this launch completes
+    rec = rcol < A.rec_ncols && ((MODE == kModeInit ? step : step + 1) % A.rec_every) == 0;
     rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
   }
 

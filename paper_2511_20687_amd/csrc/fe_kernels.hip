@@ -116,8 +116,8 @@ __global__ void __launch_bounds__(kLdsThreads) fe_lds_kernel(FeArgs<float> A) {
   long long rcol = 0, rbase = 0;
   bool rec = false;
   if (A.rec_every > 0) {
-    rcol = (MODE == kModeInit) ? 0 : (step + 1) / A.rec_every;
-    rec = rcol < A.rec_ncols && (MODE == kModeInit || ((step + 1) % A.rec_every) == 0);
+    rcol = (MODE == kModeInit ? step : step + 1) / A.rec_every;   // the state this launch completes
+    rec = rcol < A.rec_ncols && ((MODE == kModeInit ? step : step + 1) % A.rec_every) == 0;
     rbase = ((long long)b * A.rec_ncols + rcol) * 3 * A.nfree_nodes;
   }
 

@@ -30,7 +30,8 @@ EXPORTED = ["osam_version", "osam_ctx_create", "osam_ctx_destroy", "osam_last_er
             "osam_set_rom_path", "osam_get_rom_path", "osam_set_graph", "osam_set_fusion", "osam_set_fe_xshare",
             "osam_autotune",
             "osam_sync", "osam_set_engine", "osam_get_solver_stats", "run_noalloc", "osam_set_opinf_cubic",
-            "osam_get_opinf_cubic"]
+            "osam_get_opinf_cubic", "osam_set_state", "osam_checkpoint_size", "osam_save_checkpoint",
+            "osam_load_checkpoint"]
 
 
 class OsamError(RuntimeError):
@@ -166,6 +167,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.osam_get_rom_path.restype = i32
     lib.osam_sync.argtypes = [vp]
     lib.osam_sync.restype = i32
+    lib.osam_set_state.argtypes = [vp, i32, i32, dp, dp, dp]
+    lib.osam_set_state.restype = i32
+    lib.osam_checkpoint_size.argtypes = [vp, C.POINTER(i64)]
+    lib.osam_checkpoint_size.restype = i32
+    lib.osam_save_checkpoint.argtypes = [vp, i32, vp]
+    lib.osam_save_checkpoint.restype = i32
+    lib.osam_load_checkpoint.argtypes = [vp, i32, vp]
+    lib.osam_load_checkpoint.restype = i32
     lib.osam_set_opinf_cubic.argtypes = [vp, i32, dp]
     lib.osam_set_opinf_cubic.restype = i32
     lib.osam_get_opinf_cubic.argtypes = [vp, i32, dp]
@@ -308,6 +317,26 @@ class Context:
         u, v, a = (np.zeros((3, n)) for _ in range(3))
         self._check(self.lib.osam_get_state(self.h, sd, inst, _dptr(u), _dptr(v), _dptr(a)))
         return u, v, a
+
+    def set_state(self, sd: int, inst: int, x, xd, xdd):
+        """FOM: u, v, a [3][n_nodes] (osam_get_state layout); OpInf: q, q', q'' [r]."""
+        x, xd, xdd = _f64(x), _f64(xd), _f64(xdd)
+        self._check(self.lib.osam_set_state(self.h, sd, inst, _dptr(x), _dptr(xd), _dptr(xdd)))
+
+    def save_checkpoint(self, inst: int = 0) -> bytes:
+        n = C.c_int64()
+        self._check(self.lib.osam_checkpoint_size(self.h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self.lib.osam_save_checkpoint(self.h, inst, buf))
+        return buf.raw
+
+    def load_checkpoint(self, inst: int, blob: bytes):
+        n = C.c_int64()
+        self._check(self.lib.osam_checkpoint_size(self.h, C.byref(n)))
+        if len(blob) != n.value:
+            raise ValueError(f"checkpoint of {len(blob)} bytes, this context's instances take {n.value}")
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self.lib.osam_load_checkpoint(self.h, inst, buf))
 
     def get_reduced(self, sd: int, inst: int = 0):
         r = self.sizes(sd)["r"]
