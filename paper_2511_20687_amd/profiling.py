@@ -6,6 +6,8 @@ Used under rocprofv3 to produce the summaries in profiles/:
     python -m paper_2511_20687_amd.profiling workload [steps [fused]]  # coupled run, synthetic r=40 OpInf
     python -m paper_2511_20687_amd.profiling large [steps [block kc]]  # 64x64x640, OpInf-FOM-OpInf, B=16
     python -m paper_2511_20687_amd.profiling copy               # plain copy of 256 MiB (calibration)
+    python -m paper_2511_20687_amd.profiling rom [steps [bf16]]  # 48x48x480 OpInf-OpInf r=100 quadratic, B=256
+    python -m paper_2511_20687_amd.profiling learn [T [r]]      # learning on 268,125 x T seeded snapshots
     python -m paper_2511_20687_amd.profiling summarize OUTDIR [bar24|bar64|bar24_sweep]   # counters -> profiles/*.txt
 
 The workload runs exactly the FE kernel work of the bench (same subdomain, launch shape and
@@ -25,6 +27,9 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 256 << 20
+# algorithmic FP32 bytes per FE DOF-iteration-update (read u, v, a and the previous iterate's
+# u, v; write u, v, a; the lumped mass, 4 B per node)
+FE_ALG_BYTES = 32.0 + 4.0 / 3.0
 _CSRC = "paper_2511_20687_amd/csrc/"
 SOURCES = {   # the sources each profiled kernel is built from
     "fe": tuple(_CSRC + f for f in ("fe_kernels.hip", "fe_body.hpp", "stencil.hpp", "osam_device.hpp")),
@@ -105,10 +110,57 @@ def large(steps: int = 20, block: int = 0, kc: int = 0) -> None:
     torch.cuda.synchronize()
     ms, n = ctx.get_timing(fom)
     us = 1e3 * ms / max(n, 1)
-    alg = 28.0 * nf * w.batch
+    alg = FE_ALG_BYTES * nf * w.batch
     print(f"large done: {steps} steps, {info[0]['total_iters']} Schwarz iterations (instance 0), "
           f"FE launches {n}, FE avg {us:.1f} us, {nf} FE DOFs x {w.batch} instances, "
           f"algorithmic {alg / 1e6:.1f} MB per launch -> {alg / (us * 1e-6) / 1e9:.0f} GB/s", flush=True)
+
+
+def rom(steps: int = 50, bf16: bool = False) -> None:
+    """Batched OpInf-OpInf on the 48x48x480 bar: quadratic r = 100 on both subdomains (H 100 x
+    5050), 256 instances, the batched path (f0 on the matrix cores), PREDICTOR guess; seeded
+    synthetic operators of the learned sizes."""
+    import torch
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import CFG3, draw_pulses, synthetic_rom
+    w = CFG3
+    ctx = osam.Context(0, "f32_bf16h" if bf16 else "f32", w.batch)
+    osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
+    for sd in range(2):
+        z = ctx.sizes(sd)
+        R = synthetic_rom(w.seed + sd, z["n_free"], z["n_sch"], w.r, 1, w.dt, quadratic=True)
+        ctx.set_opinf(sd, R["Phi"], R["PhiS"], R["A"], R["H"], R["B"])
+        ctx.set_rom_path(sd, 2)
+    for b, p in enumerate(draw_pulses(w.seed, w.batch, s=w.pulse_width)):
+        u0 = p.u0(w.bar)
+        ctx.set_initial(b, u0, np.zeros_like(u0))
+    info = ctx.run(steps, osam.Options(tol_abs=w.tol_abs, tol_rel=w.tol_rel, guess=w.guess))
+    torch.cuda.synchronize()
+    print(f"rom done: {steps} steps x {w.batch} instances, {info[0]['total_iters']} iterations (instance 0)",
+          flush=True)
+
+
+def learn(T: int = 2000, r: int = 40) -> None:
+    """OpInf learning (POD by the FP64 Gram on the matrix cores, least squares, Alg. 3) on the
+    24x24x240 bar's OpInf subdomain (268,125 free DOFs) from seeded random snapshots (T
+    columns, FP32) with a decaying spectrum."""
+    import torch
+    from paper_2511_20687_amd import osam
+    from paper_2511_20687_amd.inputs import CFG2, lambda_grid_values
+    w = CFG2
+    ctx = osam.Context(0, "f32", 1)
+    osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
+    z = ctx.sizes(1)
+    g = torch.Generator(device="cuda:0").manual_seed(2)
+    modes = torch.randn((1, 64, z["n_free"]), generator=g, device="cuda:0")
+    coef = torch.randn((1, T, 64), generator=g, device="cuda:0") * torch.logspace(0, -6, 64, device="cuda:0")
+    U = torch.bmm(coef, modes).contiguous()
+    A = torch.bmm(coef.flip(2).contiguous(), modes).contiguous()
+    S = torch.randn((1, T, z["n_sch"]), generator=g, device="cuda:0") * 1e-3
+    V0 = torch.zeros((1, z["n_free"]), device="cuda:0")
+    out = ctx.learn_opinf(1, U, A, S, V0, 1, T, r=r, r_s=1, lambdas=lambda_grid_values(11))
+    torch.cuda.synchronize()
+    print(f"learn done: N={z['n_free']} T={T} r={out['r']} lambda*={out['lambda_star']}", flush=True)
 
 
 def copy() -> None:
@@ -138,14 +190,14 @@ def _mean_counter(rows, name_part, counter):
 
 # the fused sweep of the 24x24x240 workload: FE step of Omega_1 plus the OpInf step
 # (r = 40, r_S = 1, one FOM-fed face and one push face of 3 x 625 DOFs)
-_SWEEP24_BYTES = 28 * 268125 + rom_bytes_per_launch(40, 1, 1875, 1875)
+_SWEEP24_BYTES = FE_ALG_BYTES * 268125 + rom_bytes_per_launch(40, 1, 1875, 1875)
 
 CASES = {
     # name: (subdirectory prefix, kernel name filter, algorithmic bytes per launch, summary file,
     #        source set, title)
-    "bar24": ("", "fe_kernel<float, 0", 28 * 268125, "fe_kernel_bar24x24x240_traffic.txt", "fe",
+    "bar24": ("", "fe_kernel<float, 0", FE_ALG_BYTES * 268125, "fe_kernel_bar24x24x240_traffic.txt", "fe",
               "FE step kernel, 24x24x240 bar, Omega_1 268125 FE DOFs, FP32, launch 256 threads x 1 layer"),
-    "bar64": ("large_", "fe_kernel<float, 0", 28 * 16 * 4322175, "fe_kernel_bar64x64x640_b16_traffic.txt", "fe",
+    "bar64": ("large_", "fe_kernel<float, 0", FE_ALG_BYTES * 16 * 4322175, "fe_kernel_bar64x64x640_b16_traffic.txt", "fe",
               "FE step kernel, 64x64x640 bar, middle FOM subdomain 4322175 FE DOFs x 16 instances, FP32, "
               "launch 256 threads x 1 layer, x-shared interior rows"),
     "bar24_sweep": ("sweep_", "sweep_kernel<float, 1", _SWEEP24_BYTES, "sweep_kernel_bar24x24x240_traffic.txt",
@@ -231,6 +283,10 @@ if __name__ == "__main__":
         large(*a)
     elif cmd == "copy":
         copy()
+    elif cmd == "rom":
+        rom(int(sys.argv[2]) if len(sys.argv) > 2 else 50, len(sys.argv) > 3 and sys.argv[3] == "bf16")
+    elif cmd == "learn":
+        learn(*[int(x) for x in sys.argv[2:4]])
     elif cmd == "summarize":
         summarize(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "bar24")
     else:
