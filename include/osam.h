@@ -208,8 +208,11 @@ int32_t osam_set_record(osam_ctx *ctx, int32_t sd, const osam_record *rec);
  * when r_s <= 0); least squares in FP64 (normal or dual form) for each lambda
  * in `lambdas`; Alg. 3 picks lambda* (frozen-boundary rollout error, smallest
  * lambda on ties, non-finite = +inf) and the operators are refit with it.  On
- * success sd becomes an OpInf subdomain.  Outputs (host, may be NULL): sigma
- * (singular values of U, min(n_free, n_traj*T) entries), E_lambda [n_lambda],
+ * success sd becomes an OpInf subdomain.  The POD computes only the leading
+ * eigenpairs of the Gram (block subspace iteration with Rayleigh-Ritz; a full
+ * Jacobi eigen-decomposition when that does not converge).  Outputs (host, may
+ * be NULL): sigma (singular values of U, min(n_free, n_traj*T) entries: the
+ * leading max(r, 16) or more, the entries beyond those computed are 0), E_lambda [n_lambda],
  * lambda_star, r_out, rs_out.  stride: time steps between consecutive snapshots
  * (0 or 1: every step).  The fit is pointwise in time (Udd holds the Newmark
  * accelerations of the snapshot times); the Alg. 3 rollout takes `stride`

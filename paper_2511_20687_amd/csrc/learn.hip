@@ -19,6 +19,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <random>
 #include <vector>
 
 #include "runtime.hpp"
@@ -28,8 +29,9 @@ namespace osam {
 template <typename TA, typename TB>
 hipError_t gemm64(bool, bool, int, int, long long, double, const TA *, long long, const TB *, long long, double,
                   double *, long long, double *, long long, hipStream_t);
-hipError_t launch_chol_small(double *, int, long long, double, int *, hipStream_t);
-hipError_t launch_trsm_right_lt(double *, long long, int, const double *, hipStream_t);
+hipError_t launch_chol_lds(double *, int, long long, double, int *, hipStream_t);
+hipError_t launch_trtri_lower(const double *, int, double *, hipStream_t);
+hipError_t launch_ritz_resid(const double *, const double *, const double *, long long, int, double *, hipStream_t);
 hipError_t launch_colscale(double *, long long, int, const double *, int, hipStream_t);
 hipError_t launch_sign_fix(double *, long long, int, hipStream_t);
 hipError_t launch_potrf_diag(double *, long long, int, int, int *, hipStream_t);
@@ -44,6 +46,7 @@ hipError_t launch_jacobi_round(const double *, double *, const double *, double 
 hipError_t launch_offnorm(const double *, long long, double *, int, hipStream_t);
 hipError_t launch_identity(double *, long long, hipStream_t);
 hipError_t launch_gather_cols(const double *, long long, const int *, int, double *, hipStream_t);
+hipError_t launch_jacobi(double *, double *, double *, int, int *, double *, hipStream_t);
 hipError_t launch_rollout(const double *, int, int, int, int, int, int, const double *, const double *,
                           const double *, const double *, long long, int, int, double, int, double *, hipStream_t);
 
@@ -114,19 +117,41 @@ struct Learner {
     sync();
   }
 
+  // Workspace of Cholesky-QR on m x k blocks: the Gram / its factor (k x k), the inverse
+  // factor (k x k), the second block the products go to (m x k), the factorisation flag.
+  struct QrWork {
+    double *G = nullptr, *Li = nullptr, *Wt = nullptr;
+    int *info = nullptr;
+  };
+  bool qr_work(QrWork &w, long long m, int k) {
+    w.G = alloc((size_t)k * k);
+    w.Li = alloc((size_t)k * k);
+    w.Wt = alloc((size_t)m * k);
+    w.info = ar.i(1);
+    if (!w.info) return fail(OSAM_E_OOM, "out of device memory in learning");
+    return code == OSAM_OK;
+  }
+
+  // One Cholesky-QR pass: G = W^T W + shift I = L L^T, W <- W L^-T (the product with the
+  // explicit inverse factor, a GEMM; W and w.Wt swap).  Returns false (without recording an
+  // error) when the factorisation breaks down.
+  bool cholqr_pass(double *&W, long long m, int k, double shift, QrWork &w) {
+    if (!gemm<double, double>(true, false, k, k, m, 1.0, W, m, W, m, 0.0, w.G, k)) return false;
+    if (!ok(launch_chol_lds(w.G, k, k, shift, w.info, s), "chol")) return false;
+    int hinfo = 0;
+    ok(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    sync();
+    if (code || hinfo != 0) return false;
+    if (!ok(launch_trtri_lower(w.G, k, w.Li, s), "trtri")) return false;
+    if (!gemm<double, double>(false, true, (int)m, k, k, 1.0, W, m, w.Li, k, 0.0, w.Wt, m)) return false;
+    std::swap(W, w.Wt);
+    return code == OSAM_OK;
+  }
+
   // Cholesky-QR2: W (m x k) <- W R^-1 with orthonormal columns.  Returns false
   // (without recording an error) when the block is numerically rank deficient.
-  bool cholqr(double *W, long long m, int k, double *G, int *info) {
-    for (int pass = 0; pass < 2; ++pass) {
-      if (!gemm<double, double>(true, false, k, k, m, 1.0, W, m, W, m, 0.0, G, k)) return false;
-      if (!ok(launch_chol_small(G, k, k, 0.0, info, s), "chol")) return false;
-      int hinfo = 0;
-      ok(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
-      sync();
-      if (hinfo != 0) return false;
-      if (!ok(launch_trsm_right_lt(W, m, k, G, s), "trsm")) return false;
-    }
-    return code == OSAM_OK;
+  bool cholqr(double *&W, long long m, int k, QrWork &w) {
+    return cholqr_pass(W, m, k, 0.0, w) && cholqr_pass(W, m, k, 0.0, w);
   }
 
   // All eigenpairs of the symmetric matrix C (n x n, destroyed) by cyclic
@@ -159,9 +184,8 @@ struct Learner {
     }
     // eigenvalues = diagonal, sorted descending (stable on ties)
     std::vector<double> diag(n);
-    for (int i = 0; i < n; ++i) {
-      ok(hipMemcpyAsync(&diag[i], Ain + i + (size_t)i * n, 8, hipMemcpyDeviceToHost, s), "copy");
-    }
+    ok(hipMemcpy2DAsync(diag.data(), sizeof(double), Ain, (size_t)(n + 1) * sizeof(double), sizeof(double), n,
+                        hipMemcpyDeviceToHost, s), "diagonal");
     sync();
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
@@ -176,9 +200,112 @@ struct Learner {
     return code == OSAM_OK;
   }
 
-  // POD basis of X (nr x nc, column-major, ld nr, type T): Phi (device nr x r, FP64).
+  // Orthonormal basis of the column space of W (m x k) by shifted Cholesky-QR (Fukaya,
+  // Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020): Cholesky-QR passes on W^T W + s I with
+  // s = 11 (m k + k (k + 1)) u ||W||_F^2 of the current block until its Gram is within 0.1 of
+  // the identity entrywise, then one unshifted pass.  Blocks with kappa(W) up to 1/u take
+  // two shifted passes (the shifted Cholesky-QR3 of the paper cited).  Directions of W below
+  // that (columns that are numerically dependent: the part of the subspace iteration's
+  // block beyond the numerical rank of the Gram) grow by about 1/sqrt(s) per further
+  // shifted pass until the block is well conditioned, and come out as orthonormal directions
+  // of no significance.  Returns false (code OK) when 12 shifted passes do not get there.
+  bool orth(double *&W, long long m, int k, QrWork &w) {
+    std::vector<double> g((size_t)k * k);
+    for (int pass = 0; pass < 12; ++pass) {
+      if (!gemm<double, double>(true, false, k, k, m, 1.0, W, m, W, m, 0.0, w.G, k)) return false;
+      ok(hipMemcpyAsync(g.data(), w.G, g.size() * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+      sync();
+      if (code) return false;
+      double fro2 = 0.0, dev = 0.0;
+      for (int j = 0; j < k; ++j) {
+        fro2 += g[(size_t)j * (k + 1)];
+        for (int i = 0; i < k; ++i) dev = std::max(dev, std::fabs(g[i + (size_t)j * k] - (i == j ? 1.0 : 0.0)));
+      }
+      if (!(fro2 > 0.0) || !std::isfinite(fro2)) return false;
+      if (dev <= 0.1) return cholqr_pass(W, m, k, 0.0, w);
+      const double shift = 11.0 * ((double)m * k + (double)k * (k + 1)) * std::numeric_limits<double>::epsilon() * fro2;
+      if (!ok(launch_chol_lds(w.G, k, k, shift, w.info, s), "chol")) return false;
+      int hinfo = 0;
+      ok(hipMemcpyAsync(&hinfo, w.info, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+      sync();
+      if (code || hinfo != 0) return false;
+      if (!ok(launch_trtri_lower(w.G, k, w.Li, s), "trtri")) return false;
+      if (!gemm<double, double>(false, true, (int)m, k, k, 1.0, W, m, w.Li, k, 0.0, w.Wt, m)) return false;
+      std::swap(W, w.Wt);
+    }
+    return false;
+  }
+
+  // Rayleigh-Ritz on the n x b orthonormal block Y: H = Y^T (C Y), its eigenpairs by one
+  // workgroup's cyclic Jacobi, Y <- Y W (Ritz vectors), Z <- Z W (= C Y); w: the Ritz values
+  // (device, descending).
+  bool rayleigh_ritz(const double *C, int n, int b, double *&Y, double *&Z, double *&Y2, double *H, double *Wm,
+                     double *w, int *pws, double *cws) {
+    if (!gemm<double, double>(false, false, n, b, n, 1.0, C, n, Y, n, 0.0, Z, n)) return false;
+    if (!gemm<double, double>(true, false, b, b, n, 1.0, Y, n, Z, n, 0.0, H, b)) return false;
+    if (!ok(launch_jacobi(H, Wm, w, b, pws, cws, s), "jacobi")) return false;
+    if (!gemm<double, double>(false, false, n, b, b, 1.0, Y, n, Wm, b, 0.0, Y2, n)) return false;
+    std::swap(Y, Y2);
+    if (!gemm<double, double>(false, false, n, b, b, 1.0, Z, n, Wm, b, 0.0, Y2, n)) return false;
+    std::swap(Z, Y2);
+    return code == OSAM_OK;
+  }
+
+  // The k largest eigenpairs of the symmetric positive semidefinite C (n x n, kept):
+  // block subspace iteration Y <- orth(C Y) (shifted Cholesky-QR) with a Rayleigh-Ritz
+  // step every 4 iterations, block b = min(n, k + 32), from a seeded Gaussian start; for
+  // b == n the Rayleigh-Ritz step is the whole eigen-decomposition.  Converged when each of
+  // the k leading Ritz pairs has ||C y - theta y|| <= 1e-13 theta_1.  theta: the k leading
+  // Ritz values (host, descending); V: device n x k.  Returns false with code OK when it
+  // did not converge within 400 iterations or the block lost rank (the caller falls back
+  // to eig_all).
+  bool eig_top(const double *C, int n, int k, std::vector<double> &theta, double *&V) {
+    const int b = std::min(n, k + 32);
+    double *Y = alloc((size_t)n * b), *Z = alloc((size_t)n * b), *Y2 = alloc((size_t)n * b);
+    double *H = alloc((size_t)b * b), *Wm = alloc((size_t)b * b), *w = alloc(b), *res = alloc(k);
+    double *cws = alloc((size_t)b + 2);
+    int *pws = ar.i((size_t)b + 2);
+    QrWork qw;
+    if (!qr_work(qw, n, b) || code || !pws) return fail(OSAM_E_OOM, "out of device memory in learning");
+    if (b == n) {
+      ok(launch_identity(Y, n, s), "identity");
+    } else {
+      std::vector<double> y((size_t)n * b);
+      std::mt19937_64 gen(0x5eed0f00dULL);
+      std::normal_distribution<double> nd(0.0, 1.0);
+      for (double &v : y) v = nd(gen);
+      up(Y, y);
+      if (!orth(Y, n, b, qw)) return false;
+    }
+    std::vector<double> th;
+    for (int it = 0; it < 400; ++it) {
+      if (b < n) {   // Y <- orth(C Y)
+        if (!gemm<double, double>(false, false, n, b, n, 1.0, C, n, Y, n, 0.0, Z, n)) return false;
+        std::swap(Y, Z);
+        if (!orth(Y, n, b, qw)) return false;
+      }
+      if (b < n && it % 4 != 3) continue;
+      if (!rayleigh_ritz(C, n, b, Y, Z, Y2, H, Wm, w, pws, cws)) return false;
+      th = down(w, (size_t)k);
+      if (b == n) break;
+      // residuals of the k leading Ritz pairs: Z - Y diag(theta) (Z = C Y after the rotation)
+      if (!ok(launch_ritz_resid(Z, Y, w, n, k, res, s), "residual")) return false;
+      const std::vector<double> r2 = down(res, (size_t)k);
+      if (code) return false;
+      double worst = 0.0;
+      for (double v : r2) worst = std::max(worst, std::sqrt(v));
+      if (!(worst > 1e-13 * std::max(th[0], 0.0))) break;
+      if (it == 399) return false;
+    }
+    theta = th;
+    V = Y;
+    return code == OSAM_OK;
+  }
+
+  // POD basis of X (nr x nc, column-major, ld nr, type T): Phi (device nr x r, FP64); sigma:
+  // the leading singular values computed (at least min_k of them when r is fixed).
   template <typename T>
-  bool pod(const T *X, long long nr, long long nc, int r_fixed, double energy, double *&Phi, int &r,
+  bool pod(const T *X, long long nr, long long nc, int r_fixed, double energy, int min_k, double *&Phi, int &r,
            std::vector<double> &sigma) {
     const bool snap = nr >= nc;
     const int n = (int)(snap ? nc : nr);
@@ -191,22 +318,49 @@ struct Learner {
     }
     std::vector<double> theta;
     double *V = nullptr;
-    const int kmax = std::min(n, 128);
-    if (!eig_all(C, n, kmax, theta, V)) return false;
+    const int kmax = std::min(n, 128);   // POD bases hold at most 128 modes
+    if (r_fixed > 128) return fail(OSAM_E_INVALID, "POD basis larger than 128 modes");
+    // the total energy is the trace of the Gram (the sum of all its eigenvalues)
+    std::vector<double> dg(n);
+    ok(hipMemcpy2DAsync(dg.data(), sizeof(double), C, (size_t)(n + 1) * sizeof(double), sizeof(double), n,
+                        hipMemcpyDeviceToHost, s), "diagonal");
+    sync();
+    double trace = 0.0;
+    for (double v : dg) trace += v;
+    if (code) return false;
+    // energy criterion (Eq. pod_energy): smallest r with E_r >= energy, over the leading
+    // eigenvalues at hand (0 when they do not reach it)
+    const double tot = std::max(trace, 0.0);
+    auto energy_r = [&](const std::vector<double> &th) {
+      double cum = 0.0;
+      for (size_t i = 0; i < th.size(); ++i) {
+        cum += std::max(th[i], 0.0);
+        if (tot > 0.0 && cum >= energy * tot) return (int)i + 1;
+      }
+      return 0;
+    };
+    // the leading eigenpairs only: the r asked for (at least min_k, the singular values
+    // reported), or for the energy criterion 16, 64, then 128 of them until the criterion is
+    // met; the full cyclic Jacobi when the subspace iteration does not converge
+    bool top = false;
+    if (r_fixed > 0) {
+      top = eig_top(C, n, std::min(n, std::max(r_fixed, min_k)), theta, V);
+    } else {
+      for (int kk : {16, 64, 128}) {
+        kk = std::min(kk, kmax);
+        top = eig_top(C, n, kk, theta, V);
+        if (!top || energy_r(theta) > 0 || kk == kmax) break;
+      }
+    }
+    if (!top) {
+      if (code) return false;
+      if (!eig_all(C, n, kmax, theta, V)) return false;
+    }
     if (r_fixed > 0) {
       r = std::min(r_fixed, n);
     } else {
-      // energy criterion (Eq. pod_energy): smallest r with E_r >= energy
-      double cum = 0.0, tot = 0.0;
-      for (int i = 0; i < n; ++i) tot += std::max(theta[i], 0.0);
-      r = n;
-      for (int i = 0; i < n; ++i) {
-        cum += std::max(theta[i], 0.0);
-        if (tot > 0.0 && cum >= energy * tot) {
-          r = i + 1;
-          break;
-        }
-      }
+      r = energy_r(theta);
+      if (r == 0) r = (int)theta.size() < n ? kmax + 1 : n;   // not met within the leading kmax
     }
     if (r < 1) return fail(OSAM_E_INVALID, "empty POD basis");
     if (r > 128) return fail(OSAM_E_INVALID, "POD basis larger than 128 modes");
@@ -223,9 +377,12 @@ struct Learner {
       double *f = alloc(r);
       up(f, sv);
       ok(launch_colscale(Phi, nr, r, f, 0, s), "colscale");
-      double *G = alloc((size_t)r * r);
-      int *info = ar.i(1);
-      if (!cholqr(Phi, nr, r, G, info)) return fail(OSAM_E_SINGULAR, "POD basis is not of full rank");
+      QrWork qw;
+      if (!qr_work(qw, nr, r)) return false;
+      if (!cholqr(Phi, nr, r, qw)) {
+        if (code) return false;
+        return fail(OSAM_E_SINGULAR, "POD basis is not of full rank");
+      }
     } else {
       ok(hipMemcpyAsync(Phi, V, (size_t)nr * r * 8, hipMemcpyDeviceToDevice, s), "copy");
     }
@@ -299,9 +456,9 @@ static int32_t learn_impl(Ctx *ctx, int sdi, const osam_opinf_desc &d) {
   double *Phi = nullptr, *PhiS = nullptr;
   int r = 0, rs = 0;
   std::vector<double> sig, sigS;
-  if (!L.pod<T>(U, N, Tt, d.r, d.energy, Phi, r, sig)) return ctx->fail(L.code, L.err);
+  if (!L.pod<T>(U, N, Tt, d.r, d.energy, 16, Phi, r, sig)) return ctx->fail(L.code, L.err);
   if (NS > 0) {
-    if (!L.pod<T>(S, NS, Tt, d.r_s, d.energy_bnd, PhiS, rs, sigS)) return ctx->fail(L.code, L.err);
+    if (!L.pod<T>(S, NS, Tt, d.r_s, d.energy_bnd, 1, PhiS, rs, sigS)) return ctx->fail(L.code, L.err);
   }
   const int quad = d.form == OSAM_QUADRATIC || d.form == OSAM_CUBIC;
   const int cubic = d.form == OSAM_CUBIC;

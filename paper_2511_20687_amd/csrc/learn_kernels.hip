@@ -4,9 +4,11 @@
 //    the FP64 matrix cores (v_mfma_f64_16x16x4); A/B may be FP32 (snapshots are
 //    stored in the run precision and widened on load).  64x64 tile per
 //    workgroup, 4 waves of 32x32, optional split-K with a fixed-order reduction.
-//  * symmetric eigensolver for the snapshot Gram (cyclic Jacobi, one launch per
-//    round), small and blocked Cholesky, triangular solves: the pieces of the
-//    POD and of the regularised normal equations.
+//  * symmetric eigensolvers for the snapshot Gram (a one-workgroup cyclic Jacobi
+//    for the Rayleigh-Ritz blocks of the subspace iteration, a cyclic Jacobi with
+//    one launch per round for whole Grams), small (LDS) and blocked Cholesky,
+//    triangular solves and inverses: the pieces of the POD and of the regularised
+//    normal equations.
 //  * data matrix D = [Q^T | (Q (x) Q)^T | S^^T | 1] and the batched FP64
 //    frozen-boundary rollouts of Alg. 3 (one workgroup per lambda x trajectory).
 #include <hip/hip_runtime.h>
@@ -14,6 +16,10 @@
 namespace osam {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// dynamic LDS of one workgroup: gfx950's 160 KB less room for a kernel's static LDS
+constexpr size_t kLdsDyn = 159 * 1024;
+constexpr int kCholLdsMaxN = 200;        // n (n + 1) / 2 doubles <= kLdsDyn
 
 __device__ __forceinline__ double wsum(double x) {
 #pragma unroll
@@ -166,15 +172,23 @@ template hipError_t gemm64<float, double>(bool, bool, int, int, long long, doubl
 // ---------------------------------------------------------------------------
 // Cyclic Jacobi for a small symmetric matrix A (k x k, column-major, destroyed),
 // one workgroup.  Round-robin ordering: k/2 disjoint rotations per round.
-// Eigenvalues (descending) in w, eigenvectors in the columns of V.
-__global__ void __launch_bounds__(1024) jacobi_eig_kernel(double *A, double *V, double *w, int k, int max_sweeps,
+// Eigenvalues (descending) in w, eigenvectors in the columns of V.  LDS: A and V
+// are worked on in LDS (2 k^2 doubles of dynamic LDS) and V is written back at the end.
+template <bool LDS>
+__global__ void __launch_bounds__(1024) jacobi_eig_kernel(double *Ag, double *Vg, double *w, int k, int max_sweeps,
                                                          int *pairs_ws, double *cs_ws) {
+  extern __shared__ double jlds[];
   __shared__ double sh[16];
   __shared__ int done;
+  double *A = LDS ? jlds : Ag;
+  double *V = LDS ? jlds + (size_t)k * k : Vg;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int kk = k + (k & 1);          // even number of players (a dummy when k is odd)
   const int np = kk / 2;
-  for (long long i = tid; i < (long long)k * k; i += bs) V[i] = ((i % k) == (i / k)) ? 1.0 : 0.0;
+  for (long long i = tid; i < (long long)k * k; i += bs) {
+    V[i] = ((i % k) == (i / k)) ? 1.0 : 0.0;
+    if (LDS) A[i] = Ag[i];
+  }
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // convergence test: off-diagonal vs total Frobenius norm
@@ -259,17 +273,52 @@ __global__ void __launch_bounds__(1024) jacobi_eig_kernel(double *A, double *V, 
     for (int i = 0; i < k; ++i) w[i] = A[pairs_ws[i] + (long long)pairs_ws[i] * k];
   }
   __syncthreads();
-  // permuted copy of V into A (A is scratch now), then back
+  // permuted copy of V into A (A is scratch now), then into the output
   for (long long e = tid; e < (long long)k * k; e += bs) {
     const int i = (int)(e % k), j = (int)(e / k);
     A[e] = V[i + (long long)pairs_ws[j] * k];
   }
   __syncthreads();
-  for (long long e = tid; e < (long long)k * k; e += bs) V[e] = A[e];
+  for (long long e = tid; e < (long long)k * k; e += bs) Vg[e] = A[e];
 }
 
 hipError_t launch_jacobi(double *A, double *V, double *w, int k, int *pairs_ws, double *cs_ws, hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(1), dim3(1024), 0, s, A, V, w, k, 60, pairs_ws, cs_ws);
+  const size_t lds = (size_t)2 * k * k * sizeof(double);
+  if (lds <= kLdsDyn) {
+    static bool attr = false;
+    if (!attr && lds > 65536) {
+      const hipError_t e = hipFuncSetAttribute((const void *)jacobi_eig_kernel<true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDyn);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    hipLaunchKernelGGL(jacobi_eig_kernel<true>, dim3(1), dim3(1024), lds, s, A, V, w, k, 60, pairs_ws, cs_ws);
+  } else {
+    hipLaunchKernelGGL(jacobi_eig_kernel<false>, dim3(1), dim3(1024), 0, s, A, V, w, k, 60, pairs_ws, cs_ws);
+  }
+  return hipGetLastError();
+}
+
+// out[j] = || Z[:, j] - theta[j] Y[:, j] ||^2 for the k leading columns of the n-row blocks
+// Z and Y (ld n): the residuals of Ritz pairs.  One workgroup per column.
+__global__ void __launch_bounds__(256) ritz_resid_kernel(const double *Z, const double *Y, const double *theta,
+                                                        long long n, double *out) {
+  __shared__ double sh[16];
+  const int j = blockIdx.x;
+  const double th = theta[j];
+  const double *z = Z + (size_t)j * n, *y = Y + (size_t)j * n;
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = z[i] - th * y[i];
+    acc += d * d;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[j] = acc;
+}
+
+hipError_t launch_ritz_resid(const double *Z, const double *Y, const double *theta, long long n, int k, double *out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(ritz_resid_kernel, dim3(k), dim3(256), 0, s, Z, Y, theta, n, out);
   return hipGetLastError();
 }
 
@@ -440,20 +489,102 @@ hipError_t launch_chol_small(double *A, int n, long long lda, double shift, int 
   return hipGetLastError();
 }
 
-// W (m x k, column-major, ld m) <- W L^-T, L lower (k x k, ld k): each row
-// solves x L^T = w by forward substitution.
-__global__ void trsm_right_lt_kernel(double *W, long long m, int k, const double *L) {
-  const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= m) return;
-  for (int j = 0; j < k; ++j) {
-    double s = W[row + j * m];
-    for (int l = 0; l < j; ++l) s -= W[row + l * m] * L[j + (long long)l * k];
-    W[row + j * m] = s / L[j + (long long)j * k];
+// The same factorisation with the lower triangle packed in LDS (column-major packed
+// storage, n (n + 1) / 2 doubles): for the Gram blocks of Cholesky-QR, n <= kCholLdsMaxN.
+__global__ void __launch_bounds__(1024) chol_lds_kernel(double *A, int n, long long lda, double shift, int *info) {
+  extern __shared__ double P[];
+  __shared__ double piv;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  // packed offset of (i, l), i >= l: the columns before l hold n + (n - 1) + ... entries
+  auto at = [&](int i, int l) -> double & { return P[(long long)l * n - (long long)l * (l - 1) / 2 + (i - l)]; };
+  if (tid == 0) *info = 0;
+  for (long long e = tid; e < (long long)n * n; e += bs) {
+    const int i = (int)(e % n), l = (int)(e / n);
+    if (i >= l) at(i, l) = A[i + l * lda] + (i == l ? shift : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      const double d = at(j, j);
+      if (!(d > 0.0)) {
+        *info = j + 1;
+        piv = 0.0;
+      } else {
+        piv = sqrt(d);
+        at(j, j) = piv;
+      }
+    }
+    __syncthreads();
+    if (!(piv > 0.0)) return;
+    for (int i = j + 1 + tid; i < n; i += bs) at(i, j) /= piv;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int e = tid; e < m * m; e += bs) {
+      const int i = j + 1 + e % m, l = j + 1 + e / m;
+      if (i >= l) at(i, l) -= at(i, j) * at(l, j);
+    }
+    __syncthreads();
+  }
+  for (long long e = tid; e < (long long)n * n; e += bs) {
+    const int i = (int)(e % n), l = (int)(e / n);
+    A[i + l * lda] = i >= l ? at(i, l) : 0.0;
   }
 }
 
-hipError_t launch_trsm_right_lt(double *W, long long m, int k, const double *L, hipStream_t s) {
-  hipLaunchKernelGGL(trsm_right_lt_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, W, m, k, L);
+hipError_t launch_chol_lds(double *A, int n, long long lda, double shift, int *info, hipStream_t s) {
+  if (n > kCholLdsMaxN) return launch_chol_small(A, n, lda, shift, info, s);
+  const size_t lds = (size_t)n * (n + 1) / 2 * sizeof(double);
+  static bool attr = false;
+  if (!attr && lds > 65536) {
+    const hipError_t e =
+        hipFuncSetAttribute((const void *)chol_lds_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsDyn);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(chol_lds_kernel, dim3(1), dim3(1024), lds, s, A, n, lda, shift, info);
+  return hipGetLastError();
+}
+
+// Li <- L^-1 for a lower-triangular L (k x k, ld k, k <= 192).  One wavefront per column j
+// of the inverse: forward substitution L x = e_j, each lane holding the entries x_l with
+// l = lane (mod 64) and the dot products reduced across the wave.
+__global__ void __launch_bounds__(256) trtri_lower_kernel(const double *L, int k, double *Li) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= k) return;
+  double x0 = 0.0, x1 = 0.0, x2 = 0.0;   // x_lane, x_{lane+64}, x_{lane+128}
+  const double xj = 1.0 / L[j + (long long)j * k];
+  if (lane == (j & 63)) {
+    if ((j >> 6) == 0) x0 = xj;
+    else if ((j >> 6) == 1) x1 = xj;
+    else x2 = xj;
+  }
+  double *col = Li + (long long)j * k;
+  for (int i = lane; i < j; i += 64) col[i] = 0.0;
+  if (lane == 0) col[j] = xj;
+  for (int i = j + 1; i < k; ++i) {
+    const double *row = L + i;
+    double acc = 0.0;
+    int l = lane;
+    if (l >= j && l < i) acc += row[(long long)l * k] * x0;
+    l += 64;
+    if (l >= j && l < i) acc += row[(long long)l * k] * x1;
+    l += 64;
+    if (l >= j && l < i) acc += row[(long long)l * k] * x2;
+    acc = wsum(acc);
+    const double xi = -acc / L[i + (long long)i * k];
+    if (lane == (i & 63)) {
+      if ((i >> 6) == 0) x0 = xi;
+      else if ((i >> 6) == 1) x1 = xi;
+      else x2 = xi;
+    }
+    if (lane == 0) col[i] = xi;
+  }
+}
+
+hipError_t launch_trtri_lower(const double *L, int k, double *Li, hipStream_t s) {
+  if (k > 192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(trtri_lower_kernel, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, s, L, k, Li);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ import pytest
 from paper_2511_20687_amd.inputs import Bar, gaussian_pulse_u, random_normal, slab_layers
 from oracle.newmark import FomModel, SubdomainGeometry
 from oracle.opinf import lambda_grid, select_lambda
-from oracle.pod import pod
+from oracle.pod import energy_rank, pod
 from oracle.rom import OpInfModel
 from oracle.schwarz import Coupled, SchwarzOptions
 from tests._gpu import (lib_free_index, lib_index_of, lib_sch_index, rel_err, restrict_free_lib, synthetic_rom,
@@ -139,6 +139,47 @@ def test_pod_of_prescribed_spectrum_matches_oracle():
     _, sig = pod(U)
     e = np.cumsum(sig ** 2) / np.sum(sig ** 2)
     assert out2["r"] == int(np.searchsorted(e, 1 - 1e-6) + 1)
+
+
+@pytest.mark.parametrize("r,energy", [(40, None), (0, 1 - 1e-6)])
+def test_pod_leading_modes_by_subspace_iteration(r, energy):
+    """Gram larger than the block of the subspace iteration (T = 300 snapshots): a fixed
+    r = 40 (block 72), and the energy criterion, met only after the block widens from 16
+    to 64 leading modes (r = 60).  The boundary basis sees a flat random (Marchenko-Pastur)
+    spectrum, the slow case of the iteration.  sigma, Phi and PhiS against the oracle's SVD."""
+    import torch
+    from paper_2511_20687_amd import osam
+    bar = Bar(4, 4, 40)
+    dt = bar.explicit_dt()
+    layers = slab_layers(bar.nz, 2)
+    ctx = osam.Context(0, "f64", 1)
+    osam.add_bar_subdomains(ctx, bar, layers, dt)
+    z = ctx.sizes(1)
+    N, NS, T = z["n_free"], z["n_sch"], 300
+    L = np.linalg.qr(random_normal(41, (N, T)))[0]
+    R = np.linalg.qr(random_normal(42, (T, T)))[0]
+    s = 10.0 ** (-np.arange(T) / 20.0)
+    U = L @ np.diag(s) @ R.T
+    S = random_normal(43, (NS, T)) * 1e-3
+    Udd = random_normal(44, (N, T))
+    dev = "cuda:0"
+    Ut = torch.tensor(U.T[None].copy(), device=dev)
+    Uddt = torch.tensor(Udd.T[None].copy(), device=dev)
+    St = torch.tensor(S.T[None].copy(), device=dev)
+    V0 = torch.zeros((1, N), dtype=torch.float64, device=dev)
+    print(f"[pod subspace r={r} energy={energy} N={N} NS={NS} T={T}]", flush=True)
+    out = ctx.learn_opinf(1, Ut, Uddt, St, V0, 1, T, r=r, r_s=4, energy=energy or 1 - 1e-6, lambdas=[1e-8])
+    r_o = r or energy_rank(s, energy)
+    assert out["r"] == r_o and out["r_s"] == 4
+    assert np.allclose(out["sigma"][:r_o], s[:r_o], rtol=1e-9)
+    ops = ctx.get_opinf(1)
+    Phi_o, _ = pod(U, r=r_o)
+    assert np.abs(ops["Phi"].T @ ops["Phi"] - np.eye(r_o)).max() <= 1e-12
+    assert np.abs(ops["Phi"] - Phi_o).max() <= 1e-9
+    PhiS_o, _ = pod(S, r=4)
+    err_s = np.abs(ops["PhiS"] - PhiS_o).max()
+    print(f"  max |Phi - Phi_o| {np.abs(ops['Phi'] - Phi_o).max():.2e}, max |PhiS - PhiS_o| {err_s:.2e}")
+    assert err_s <= 1e-8
 
 
 def _train_oracle_and_gpu(bar, layers, dt, u0, v0, T, precision, lateral_fix=()):
