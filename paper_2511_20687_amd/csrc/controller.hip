@@ -959,11 +959,22 @@ std::string Ctx::fusion_unsupported() const {
   return "";
 }
 
+// fold: take the previous sweep's decision in this sweep's workgroups (its partials and
+// OpInf sums in parity 1 - par); par: the parity of the buffers this sweep writes them to.
+// sums: the OpInf steps leave their sums in rom_sums (parity par) rather than in the output
+// status (the sweeps of a graph with folded decisions).
 template <typename T>
-static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1) {
+static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1, bool fold, int par, bool sums) {
   SweepArgs<T> S;
   std::memset(&S, 0, sizeof(S));
   S.n = (int)c.sds.size();
+  S.opts = o;
+  if (fold) {
+    S.fold = 1;
+    S.prev = c.fused_finish_args(1 - par);
+    S.st_prev = c.d_status;
+    S.st_cur = c.d_status_alt;
+  }
   int nfe = 0, nrom = 0;
   bool one = true;
   size_t smem = 0;
@@ -986,6 +997,7 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
       A.nblocks = d.fz_nblocks;
       A.part_stride = d.fz_nblocks;
       A.part_off = 0;
+      A.partials = d.partials_of(par, c.batch);
       one = one && d.fz_kc == 1;
       S.nblk[slot] = d.fz_nblocks;
       S.fe_idx[slot] = nfe++;
@@ -994,6 +1006,7 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
       RomArgs<T> &A = S.rom[nrom];
       fill_rom_args<T>(c, d, i, o, A);
       A.defer = 1;
+      if (sums) A.sums_out = c.rom_sums + (size_t)par * c.batch * kMaxSd * 2;
       // an OpInf source runs side by side with this step: take its predictor
       // from its accepted state (the value it writes in this sweep)
       for (int f = 0; f < A.nfaces; ++f)
@@ -1015,7 +1028,21 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
 // finisher.  Sources push into the next step's roles and write their sums to
 // their own slots, so the subdomains' steps are independent within the sweep
 // (an OpInf source's displacement is formed from its accepted state).
-int32_t Ctx::launch_round_fused(const Opts &o) {
+// The finisher's arguments for the partials and OpInf sums a fused sweep wrote to the
+// buffers of parity par (graph mode with folded decisions).
+FinishArgs Ctx::fused_finish_args(int par) {
+  FinishArgs F = finish_args(*this, true, true);
+  for (int k = 0; k < F.nfom; ++k) F.part[k] = sds[F.sd[k]]->partials_of(par, batch);
+  F.rom_sums = rom_sums + (size_t)par * batch * kMaxSd * 2;
+  return F;
+}
+
+// r, n: the sweep's place in a sequence of n sweeps launched back to back (a captured
+// graph, or a chunk of eager launches).  Without batched OpInf parts, every sweep but the
+// first takes the previous sweep's decision itself (SweepArgs), the buffers alternating by
+// round parity, and only the last sweep is followed by the finisher.  Otherwise (and for
+// n = 0) every sweep has its finisher.
+int32_t Ctx::launch_round_fused(const Opts &o, long long r, long long n) {
   const std::string why = fusion_unsupported();
   if (!why.empty()) return fail(OSAM_E_INVALID, why);
   RomPreArgs pre[kSweepRom];
@@ -1038,9 +1065,16 @@ int32_t Ctx::launch_round_fused(const Opts &o) {
     if (!e0 || !e1) return fail(OSAM_E_HIP, "event create");
     for (size_t i = 0; i < sds.size(); ++i) ev_used.push_back({(int)i, {a, b}});
   }
-  int32_t st = prec == OSAM_FP64 ? fused_sweep<double>(*this, o, e0, e1) : fused_sweep<float>(*this, o, e0, e1);
+  const bool folding = n > 0 && npre == 0;
+  const bool fold = folding && r > 0;
+  const int par = folding ? (int)(r & 1) : 0;
+  int32_t st = prec == OSAM_FP64 ? fused_sweep<double>(*this, o, e0, e1, fold, par, folding)
+                                 : fused_sweep<float>(*this, o, e0, e1, fold, par, folding);
   if (st) return st;
-  const hipError_t e = launch_finish(d_status, d_status_alt, finish_args(*this, true, true), o, batch, stream);
+  if (fold) std::swap(d_status, d_status_alt);   // the sweep stored the status it started from
+  if (folding && r < n - 1) return OSAM_OK;
+  const FinishArgs F = folding ? fused_finish_args(par) : finish_args(*this, true, true);
+  const hipError_t e = launch_finish(d_status, d_status_alt, F, o, batch, stream);
   if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("finish kernel: ") + hipGetErrorString(e));
   std::swap(d_status, d_status_alt);
   return OSAM_OK;
@@ -1100,7 +1134,8 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     for (int r = 0; r < graph_rounds && !st; ++r)
-      st = fuse ? launch_round_fused(o) : (graph_streams == 2 ? launch_round_concurrent(o) : launch_round(o));
+      st = fuse ? launch_round_fused(o, r, graph_rounds)
+                : (graph_streams == 2 ? launch_round_concurrent(o) : launch_round(o));
     const hipError_t ec = hipStreamEndCapture(stream, &g);
     if (st) {
       if (g) (void)hipGraphDestroy(g);
@@ -1131,7 +1166,7 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
       if (graph) {
         const hipError_t e = hipGraphLaunch(gexec, stream);
         if (e != hipSuccess) return fail(OSAM_E_HIP, std::string("graph launch: ") + hipGetErrorString(e));
-      } else if ((st = fuse ? launch_round_fused(o) : launch_round(o))) {
+      } else if ((st = fuse ? launch_round_fused(o, k, rounds) : launch_round(o))) {
         return st;
       }
     }

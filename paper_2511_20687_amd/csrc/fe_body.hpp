@@ -383,15 +383,17 @@ __device__ __forceinline__ void store_partials(const FeArgs<T> &A, int b, int bx
 // sweeps); otherwise every wave has one layer chunk and one wave-uniform layer.
 // XSOK: the x-shared interior layout (A.xs) is compiled in (not in the fused
 // sweep kernel, where its shuffles push the register budget into spills).
+// st (optional): flags, step and iteration of the status this step starts from, when the
+// caller holds them (folded decisions of fused sweeps); else read from A.status[b].
 template <typename T, int MODE, bool ONE, bool PACKB = false, bool XSOK = true>
-__device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk) {
+__device__ __forceinline__ void fe_body(const FeArgs<T> &A, int xblk, const StepState *st = nullptr) {
   const int b = blockIdx.y;
   const Status *stp = A.status + b;
-  const int flags = stp->flags;
+  const int flags = st ? st->flags : stp->flags;
   if (MODE == kModeStep && (flags & kFinished)) return;
   if (MODE == kModeInit && !(flags & kNeedInit)) return;
-  const long long step = stp->step;
-  const int iter = stp->iter;
+  const long long step = st ? st->step : stp->step;
+  const int iter = st ? st->iter : stp->iter;
 
   double acc_abs = 0.0, acc_den = 0.0;
   const int bx = xcd_block(xblk, A.nblocks);

@@ -45,6 +45,7 @@ hipError_t launch_data_matrix(const double *, int, const double *, int, long lon
 hipError_t launch_jacobi_round(const double *, double *, const double *, double *, int, int, hipStream_t);
 hipError_t launch_offnorm(const double *, long long, double *, int, hipStream_t);
 hipError_t launch_identity(double *, long long, hipStream_t);
+hipError_t launch_diag(const double *, long long, double *, hipStream_t);
 hipError_t launch_gather_cols(const double *, long long, const int *, int, double *, hipStream_t);
 hipError_t launch_jacobi(double *, double *, double *, int, int *, double *, hipStream_t);
 hipError_t launch_rollout(const double *, int, int, int, int, int, int, const double *, const double *,
@@ -111,6 +112,13 @@ struct Learner {
     ok(hipMemcpyAsync(h.data(), p, n * 8, hipMemcpyDeviceToHost, s), "copy");
     sync();
     return h;
+  }
+  // the diagonal of the n x n device matrix A (ld n), on the host
+  std::vector<double> diagonal(const double *A, int n) {
+    double *d = alloc(n);
+    if (!d) return std::vector<double>(n, 0.0);
+    ok(launch_diag(A, n, d, s), "diagonal");
+    return down(d, (size_t)n);
   }
   void up(double *p, const std::vector<double> &h) {
     ok(hipMemcpyAsync(p, h.data(), h.size() * 8, hipMemcpyHostToDevice, s), "copy");
@@ -183,10 +191,7 @@ struct Learner {
       }
     }
     // eigenvalues = diagonal, sorted descending (stable on ties)
-    std::vector<double> diag(n);
-    ok(hipMemcpy2DAsync(diag.data(), sizeof(double), Ain, (size_t)(n + 1) * sizeof(double), sizeof(double), n,
-                        hipMemcpyDeviceToHost, s), "diagonal");
-    sync();
+    const std::vector<double> diag = diagonal(Ain, n);
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return diag[a] > diag[b]; });
@@ -321,10 +326,7 @@ struct Learner {
     const int kmax = std::min(n, 128);   // POD bases hold at most 128 modes
     if (r_fixed > 128) return fail(OSAM_E_INVALID, "POD basis larger than 128 modes");
     // the total energy is the trace of the Gram (the sum of all its eigenvalues)
-    std::vector<double> dg(n);
-    ok(hipMemcpy2DAsync(dg.data(), sizeof(double), C, (size_t)(n + 1) * sizeof(double), sizeof(double), n,
-                        hipMemcpyDeviceToHost, s), "diagonal");
-    sync();
+    const std::vector<double> dg = diagonal(C, n);
     double trace = 0.0;
     for (double v : dg) trace += v;
     if (code) return false;

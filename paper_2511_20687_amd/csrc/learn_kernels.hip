@@ -441,6 +441,17 @@ hipError_t launch_identity(double *V, long long n, hipStream_t s) {
   hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, V, n);
   return hipGetLastError();
 }
+
+// d[i] = A[i, i] for the n x n matrix A (ld n).
+__global__ void diag_kernel(const double *A, long long n, double *d) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = A[i + i * n];
+}
+
+hipError_t launch_diag(const double *A, long long n, double *d, hipStream_t s) {
+  hipLaunchKernelGGL(diag_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, n, d);
+  return hipGetLastError();
+}
 hipError_t launch_gather_cols(const double *V, long long n, const int *order, int k, double *out, hipStream_t s) {
   hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)((n * k + 255) / 256)), dim3(256), 0, s, V, n, order, k, out);
   return hipGetLastError();

@@ -64,7 +64,7 @@ extern "C" int32_t run_noalloc(osam_ctx *c, int64_t n_steps, const osam_schwarz_
     const Subdomain &d = *ctx->sds[i];
     if (d.rom || win) continue;
     off[i] = need;
-    need += round(sizeof(double) * 2 * (size_t)ctx->batch * d.max_nblocks);
+    need += round(sizeof(double) * 4 * (size_t)ctx->batch * d.max_nblocks);   // two sweep parities
   }
   const size_t win_off = need;
   if (win) need += round(sizeof(double) * 2 * (size_t)ctx->batch * ctx->sds.size());

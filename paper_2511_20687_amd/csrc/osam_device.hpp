@@ -24,6 +24,11 @@ struct Status {
   double sd_abs2[kMaxSd];  // this iteration's per-subdomain sums
   double sd_den2[kMaxSd];
 };
+// What a step body needs of the status it starts from.
+struct StepState {
+  long long step;
+  int iter, flags;
+};
 constexpr int kFinished = 1;
 constexpr int kNonfinite = 2;
 constexpr int kNeedInit = 4;
@@ -89,6 +94,7 @@ struct FinishArgs {
   int nblocks[kMaxSd];
   const double *part[kMaxSd];   // [batch][nblocks][2]
   int rom_sd[kMaxSd];           // OpInf subdomains whose sums are in `out` already
+  const double *rom_sums;       // or, when not null, in this [batch][kMaxSd][2] array
 };
 
 // Sum over the 64 lanes of a wave (every lane active), returned to every lane.
@@ -157,47 +163,63 @@ __device__ inline double2 fom_sums(const FinishArgs &F, int k, int b, int lane) 
   return make_double2(wave_sum64(sa), wave_sum64(sd));
 }
 
-// The decider: called by one whole wave (lane 0 writes `out`).  own_sd >= 0
-// with own_abs2/own_den2: the calling OpInf kernel's own sums.
+// The sums of a sweep gathered into the status s it started from, and the decision of
+// Eq. conv_criterion taken: by one whole wave, every lane ends with the same s.
+// rom_src: the status holding the OpInf subdomains' sums (when F.rom_sums is null).
+// own_sd >= 0 with own_abs2/own_den2: the calling OpInf kernel's own sums.
 // pre (optional): the FOM sums already reduced by the caller, [abs2, den2] per FOM subdomain.
 // U: partial-sum loads in flight per lane (registers: 4 U).
+template <int U>
+__device__ inline void gather_decide(Status &s, const Status *rom_src, const FinishArgs &F, const Opts &o, int b,
+                                     int own_sd, double own_abs2, double own_den2, const double *pre) {
+  const int lane = threadIdx.x & 63;
+  if (s.flags & kFinished) return;
+  // per-subdomain sums, written with compile-time indices only (no private-memory indexing)
+  for (int k = 0; k < F.nfom; ++k) {
+    const double2 t = pre ? make_double2(pre[2 * k], pre[2 * k + 1]) : fom_sums<U>(F, k, b, lane);
+    const int j = F.sd[k];
+#pragma unroll
+    for (int i = 0; i < kMaxSd; ++i)
+      if (i == j) {
+        s.sd_abs2[i] = t.x;
+        s.sd_den2[i] = t.y;
+      }
+  }
+  for (int k = 0; k < F.nrom; ++k) {
+    const int j = F.rom_sd[k];
+    double ta, td;
+    if (F.rom_sums) {
+      const double2 v = reinterpret_cast<const double2 *>(F.rom_sums)[(long long)b * kMaxSd + j];
+      ta = v.x;
+      td = v.y;
+    } else {
+      ta = rom_src[b].sd_abs2[j];
+      td = rom_src[b].sd_den2[j];
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxSd; ++i)
+      if (i == j) {
+        s.sd_abs2[i] = ta;
+        s.sd_den2[i] = td;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxSd; ++i)
+    if (i == own_sd) {
+      s.sd_abs2[i] = own_abs2;
+      s.sd_den2[i] = own_den2;
+    }
+  decide(s, o.nsd - 1, o);
+}
+
+// The decider: called by one whole wave (lane 0 writes `out`).  Arguments as gather_decide.
 template <int U = 16>
 __device__ inline void finish_sweep(const Status *in, Status *out, const FinishArgs &F, const Opts &o, int b,
                                     int own_sd = -1, double own_abs2 = 0.0, double own_den2 = 0.0,
                                     const double *pre = nullptr) {
-  const int lane = threadIdx.x & 63;
   Status s = in[b];
-  if (!(s.flags & kFinished)) {
-    // per-subdomain sums, written with compile-time indices only (no private-memory indexing)
-    for (int k = 0; k < F.nfom; ++k) {
-      const double2 t = pre ? make_double2(pre[2 * k], pre[2 * k + 1]) : fom_sums<U>(F, k, b, lane);
-      const int j = F.sd[k];
-#pragma unroll
-      for (int i = 0; i < kMaxSd; ++i)
-        if (i == j) {
-          s.sd_abs2[i] = t.x;
-          s.sd_den2[i] = t.y;
-        }
-    }
-    for (int k = 0; k < F.nrom; ++k) {
-      const int j = F.rom_sd[k];
-      const double ta = out[b].sd_abs2[j], td = out[b].sd_den2[j];
-#pragma unroll
-      for (int i = 0; i < kMaxSd; ++i)
-        if (i == j) {
-          s.sd_abs2[i] = ta;
-          s.sd_den2[i] = td;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < kMaxSd; ++i)
-      if (i == own_sd) {
-        s.sd_abs2[i] = own_abs2;
-        s.sd_den2[i] = own_den2;
-      }
-    decide(s, o.nsd - 1, o);
-  }
-  if (lane == 0) out[b] = s;
+  gather_decide<U>(s, out, F, o, b, own_sd, own_abs2, own_den2, pre);
+  if ((threadIdx.x & 63) == 0) out[b] = s;
 }
 
 // Faces and pushes.  All subdomains share one global grid, so a Schwarz face of
@@ -309,6 +331,7 @@ struct RomArgs {
   // batched path: f0 = A q + H (q (x) q) + c and g^ of the FOM-fed faces come
   // precomputed as partial sums (A, H, c and FOM faces are then absent above)
   int defer;               // 1: never decide, leave the sums for the finisher kernel
+  double *sums_out;        // deferred sums: [batch][kMaxSd][2] when not null, else status_out
   const T *f0part;         // [f0_ks][batch][r] or null
   int f0_ks;
   const double *gpart;     // [g_gs][batch][rs] or null
@@ -346,10 +369,22 @@ hipError_t launch_rom_pre_multi(const RomPreArgs *P, int n, hipStream_t s);
 // nblk[i] workgroups of the grid (x), instances along y; fe_idx / rom_idx pick
 // its arguments (rom_idx < 0: a FOM step).  Kernel arguments stay below 4 KB.
 constexpr int kSweepMax = 4, kSweepFe = 3, kSweepRom = 2;
+//
+// Folded decisions (graph mode): with fold = 1 the previous sweep had no finisher.  Wave 0
+// of every workgroup then reduces that sweep's partial sums (`prev`, double-buffered by
+// sweep parity) in the finisher's fixed order and takes the same decision on st_prev, so
+// every workgroup starts from the same status, the one the finisher would have written;
+// workgroup 0 of each instance stores it in st_cur for the sweep after.  The bodies read
+// the status from the workgroup's copy and ignore their own status pointers.
 template <typename T>
 struct SweepArgs {
   int n;
   int nblk[kSweepMax], fe_idx[kSweepMax], rom_idx[kSweepMax];
+  int fold;
+  FinishArgs prev;
+  const Status *st_prev;
+  Status *st_cur;
+  Opts opts;
   FeArgs<T> fe[kSweepFe];
   RomArgs<T> rom[kSweepRom];
 };

@@ -59,8 +59,10 @@ __host__ __device__ inline int rom_variant(const RomArgs<T> &A) {
   return (A.f0part ? kRomPre : 0) | (A.nexp == 0 ? kRomNoPushRegs : 0);
 }
 
+// st (optional): flags, step and iteration of the status this step starts from, when the
+// caller holds them (folded decisions of fused sweeps); else read from A.status[b].
 template <typename T, int V>
-__device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
+__device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, const StepState *st = nullptr) {
   constexpr bool PRE = (V & kRomPre) != 0, PUSHREG = (V & kRomNoPushRegs) == 0;
   const int b = blockIdx.y;
   const Status *stp = A.status + b;
@@ -81,9 +83,9 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
   __shared__ double nsum[2];
 
   // ---- 1. loads independent of this step's results
-  const int flags = stp->flags;
-  const long long step = stp->step;
-  const int iter = stp->iter;
+  const int flags = st ? st->flags : stp->flags;
+  const long long step = st ? st->step : stp->step;
+  const int iter = st ? st->iter : stp->iter;
   const int tq = min(tid, r - 1);
   T xq[2], xqd[2], xqdd[2], x_c = T(0);
 #pragma unroll
@@ -363,8 +365,13 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g) {
     if (wid == 0)
       finish_sweep<4>(A.status, A.status_out, F, A.opts, b, A.sd, nsum[0], nsum[1], small_part ? tot + 8 : nullptr);
   } else if (tid == 0) {
-    A.status_out[b].sd_abs2[A.sd] = nsum[0];
-    A.status_out[b].sd_den2[A.sd] = nsum[1];
+    if (A.sums_out) {
+      A.sums_out[((long long)b * kMaxSd + A.sd) * 2] = nsum[0];
+      A.sums_out[((long long)b * kMaxSd + A.sd) * 2 + 1] = nsum[1];
+    } else {
+      A.status_out[b].sd_abs2[A.sd] = nsum[0];
+      A.status_out[b].sd_den2[A.sd] = nsum[1];
+    }
   }
 }
 

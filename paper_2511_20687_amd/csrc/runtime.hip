@@ -274,6 +274,7 @@ int32_t osam_ctx_create(osam_ctx **out, int32_t device, int32_t precision, int32
   int32_t st = OSAM_OK;
   ctx->d_status = dalloc<Status>(ctx, batch, &st);
   if (st == OSAM_OK) ctx->d_status_alt = dalloc<Status>(ctx, batch, &st);
+  if (st == OSAM_OK) ctx->rom_sums = dalloc<double>(ctx, (size_t)2 * batch * kMaxSd * 2, &st);
   if (st != OSAM_OK) {
     osam_ctx_destroy(reinterpret_cast<osam_ctx *>(ctx));
     return st;
@@ -405,7 +406,7 @@ int32_t create_subdomain(osam_ctx *c, const osam_subdomain_desc *d, int32_t *sd_
   if (st) return ctx->fail(st, "out of device memory");
   HIPCHK(hipMemcpy(sd->bnd_cols, bnd.data(), bnd.size() * sizeof(int), hipMemcpyHostToDevice));
   ctx->choose_fe_launch(*sd, 0, 0);
-  sd->partials = dalloc<double>(ctx, (size_t)ctx->batch * sd->max_nblocks * 2, &st);
+  sd->partials = dalloc<double>(ctx, (size_t)ctx->batch * sd->max_nblocks * 4, &st);
   if (st) return ctx->fail(st, "out of device memory");
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (sd_id) *sd_id = (int32_t)ctx->sds.size();

@@ -56,7 +56,10 @@ struct Subdomain {
   int n_int = 0, n_bnd = 0;
   int nbg = 0, bg_start[8] = {}, bg_n[8] = {};   // the case groups of bnd_cols
   bool fe_xs = true;               // interior waves share x-neighbours across lanes
-  double *partials = nullptr;
+  double *partials = nullptr;        // two halves of [batch][max_nblocks][2], by sweep parity
+  double *partials_of(int par, int batch) const {
+    return partials + (size_t)par * batch * max_nblocks * 2;
+  }
   // FE launch shape: fe_block 64/128/256 = column kernel; 1024 = layer-staged kernel for the
   // interior (fe_chunks workgroups of fe_kc layers) plus the column kernel (64 threads, one
   // layer per thread) for the boundary columns; fe_nblocks = workgroup partials per instance
@@ -103,6 +106,7 @@ struct Ctx {
   std::vector<std::unique_ptr<Subdomain>> sds;
   Status *d_status = nullptr;       // status every kernel of the next round reads
   Status *d_status_alt = nullptr;   // written by that round's decider; swapped after each round
+  double *rom_sums = nullptr;       // [2][batch][kMaxSd][2]: OpInf sums of fused sweeps by parity
   Status *h_status = nullptr;   // pinned mirror
   std::vector<void *> allocs;   // hipMalloc'ed arena blocks (freed at destroy)
   struct Chunk {
@@ -160,7 +164,8 @@ struct Ctx {
   int fuse_kc = 1;
   std::string fusion_unsupported() const;
   void fuse_layout(Subdomain &s);
-  int32_t launch_round_fused(const Opts &o);
+  int32_t launch_round_fused(const Opts &o, long long r = 0, long long n = 0);
+  FinishArgs fused_finish_args(int par);
   int32_t autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out);
   int32_t apply_tuning(const osam_tuning &t);
   hipEvent_t next_event();
