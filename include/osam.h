@@ -419,9 +419,12 @@ int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds, int32_t streams);
 
 /* Fused sweeps (enable = 1): each Schwarz sweep of Alg. 1 runs as one kernel
  * launch in which every subdomain's step (FOM explicit step, or OpInf step of
- * Eq. opinf_model_schwarz) takes its own range of workgroups, followed by the
- * finisher kernel that takes the decision of Eq. conv_criterion (the batched
- * OpInf parts of osam_set_rom_path 2 are launched before).  Within a sweep no
+ * Eq. opinf_model_schwarz) takes its own range of workgroups.  The decision of
+ * Eq. conv_criterion on a sweep's sums is taken by every workgroup of the next
+ * sweep (the same fixed-order reduction in each), and a finisher kernel takes it
+ * after the last sweep of each chunk of launches; with the batched OpInf parts of
+ * osam_set_rom_path 2 (launched before each sweep) the finisher follows every
+ * sweep.  Within a sweep no
  * step reads what another writes: sources push the displacement of the next
  * step into buffers the sweep does not read, and an OpInf face fed by another
  * OpInf subdomain forms the source's displacement at t_k (its explicit
@@ -481,7 +484,14 @@ int32_t osam_sync(osam_ctx *ctx);
  * rounding order).  The launch settings (osam_set_fe_launch, osam_set_fusion,
  * osam_set_graph, osam_set_rom_path) do not apply to it; osam_autotune and
  * run_adjoint return OSAM_E_INVALID for contexts it runs.  OSAM_E_INVALID for
- * other values. */
+ * other values.  engine = 2: the persistent OpInf engine, for contexts whose
+ * subdomains are all explicit single-step OpInf models (at most 4, r <= 128,
+ * multiplicative Schwarz): one kernel launch runs every controller step of a run
+ * call, one workgroup per instance holding every subdomain's reduced state in LDS
+ * (the operators too, where they fit; else they are read from global memory); no
+ * workgroup waits for another.  Its iterates, sums, iteration counts and records
+ * are those of the single-step path with osam_set_rom_path 1, bit for bit.  run
+ * returns OSAM_E_INVALID for other contexts. */
 int32_t osam_set_engine(osam_ctx *ctx, int32_t engine);
 
 /* Iteration statistics of the window engine's solves for subdomain sd: iters

@@ -8,7 +8,8 @@ Training set (a reading: the configuration leaves it open): FOM-FOM runs of 2000
 pulses of draws 257, 258, ... of the same seed stream (w.train_runs of them), snapshots every
 w.train_stride steps, so T = 2000 per subdomain over all runs.  Learning per subdomain (Alg. 2):
 POD with the energy criterion for the boundary basis, the quadratic fit, Alg. 3 over the
-11-value grid.  Online: draws 1-256, 2000 steps, in FP32 and in the BF16-H precision.
+11-value grid.  Online: draws 1-256, 2000 steps, in FP32 and in the BF16-H precision, on the
+single-step path and on the persistent OpInf engine.
 Reported: batched OpInf-OpInf steps/s (x 256 instances); FOM-FOM steps/s for the same 256
 instances on the same GPU, timed over its whole 2000-step run (recording every `every` steps);
 and the Eq. mse error of the OpInf-OpInf displacement against that FOM-FOM run for every
@@ -92,15 +93,22 @@ def run(w=None, every=400, log=print) -> dict:
                   train_runs=w.train_runs, train_stride=w.train_stride, train_s=t_train, learn_s=t_learn,
                   learned={form: {str(k): v for k, v in lf.items()} for form, lf in learned.items()})
     qrec = {}
-    variants = {"f32": (w.form, "f32"), "f32_bf16h": (w.form, "f32_bf16h"), "linear_f32": ("linear", "f32")}
-    for key, (form, prec) in variants.items():
+    # engine 0: the single-step path (batched f0 on the matrix cores, fused sweeps, graphs;
+    # autotuned); engine 2: the persistent OpInf engine (all steps in one launch)
+    variants = {"f32": (w.form, "f32", 0), "f32_bf16h": (w.form, "f32_bf16h", 0), "linear_f32": ("linear", "f32", 0),
+                "f32_persistent": (w.form, "f32", 2), "linear_f32_persistent": ("linear", "f32", 2)}
+    for key, (form, prec, engine) in variants.items():
         ctx = osam.Context(0, prec, B)
         sds = osam.add_bar_subdomains(ctx, w.bar, w.layers, w.dt, lateral_fix=w.lateral_fix)
         for sd in sds:
             o = ops[form][sd]
             ctx.set_opinf(sd, o["Phi"], o["PhiS"], o["A"], o["H"], o["B"], o["c"])
         _initial(ctx, w, B)
-        tune = ctx.autotune(trial_steps=50, opts=opts)
+        if engine == 0:
+            tune = ctx.autotune(trial_steps=50, opts=opts)
+        else:
+            ctx.set_engine(engine)
+            tune = "persistent OpInf engine (one launch, one workgroup per instance)"
         recs = [torch.zeros((B, ncol, learned[form][sd]["r"]), device=dev) for sd in sds]
         for sd in sds:
             ctx.set_record(sd, every, ncol, u=recs[sd])
@@ -111,8 +119,8 @@ def run(w=None, every=400, log=print) -> dict:
         torch.cuda.synchronize()
         dt_run = time.perf_counter() - t0
         iters = float(np.mean([i["total_iters"] for i in info])) / n
-        result[key] = dict(form=form, precision=prec, steps_per_s=n / dt_run, instance_steps_per_s=B * n / dt_run,
-                           schwarz_iters_per_step=iters, launch=tune)
+        result[key] = dict(form=form, precision=prec, engine=engine, steps_per_s=n / dt_run,
+                           instance_steps_per_s=B * n / dt_run, schwarz_iters_per_step=iters, launch=tune)
         log(f"OpInf-OpInf {key}: {n / dt_run:.0f} steps/s x {B} instances, {iters:.2f} iterations/step")
         qrec[key] = recs
         del ctx
@@ -140,7 +148,7 @@ def run(w=None, every=400, log=print) -> dict:
     # accuracy of every instance (the lift Phi q one instance at a time)
     from paper_2511_20687_amd.inputs import draw_pulses
     pulses = draw_pulses(w.seed, B, s=w.pulse_width)
-    for key, (form, prec) in variants.items():
+    for key, (form, prec, _) in variants.items():
         Phis = [torch.tensor(np.ascontiguousarray(ops[form][sd]["Phi"].T), dtype=torch.float32, device=dev)
                 for sd in sds]
         errs = []

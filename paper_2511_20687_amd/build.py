@@ -12,7 +12,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libosam.so")
 SOURCES = ["fe_kernels.hip", "rom_kernels.hip", "learn_kernels.hip", "runtime.hip", "controller.hip",
            "learn.hip", "adjoint_kernels.hip", "adjoint.hip", "rom_pre_kernels.hip", "tune.hip",
-           "sweep_kernels.hip", "window_kernels.hip", "window.hip", "noalloc.hip", "state.hip"]
+           "sweep_kernels.hip", "window_kernels.hip", "window.hip", "noalloc.hip", "state.hip", "persist_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions are kept out of the generated code

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <vector>
 
+#include "persist.hpp"
 #include "runtime.hpp"
 
 namespace osam {
@@ -1080,6 +1081,114 @@ int32_t Ctx::launch_round_fused(const Opts &o, long long r, long long n) {
   return OSAM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent OpInf engine (engine 2): every step of the call in one launch of
+// rom_persist_kernel, one workgroup per instance (persist_kernels.hip).
+std::string Ctx::persist_unsupported(const Opts &o) const {
+  if ((int)sds.size() > kPersistMax) return "at most 4 subdomains";
+  for (const auto &dp : sds) {
+    const Subdomain &d = *dp;
+    if (!d.rom) return "every subdomain must be an OpInf model";
+    if (d.desc.beta != 0.0 || d.desc.gamma != 0.5 || d.n_sub > 1 || !d.oh.C3.empty())
+      return "explicit single-step OpInf subdomains only (beta = 0, gamma = 1/2, n_sub = 1, no cubic term)";
+    if (d.r > 128) return "r above 128";   // the OpInf step's rows: 8 waves x 16 rows
+  }
+  if (o.additive) return "the multiplicative variant only";
+  return "";
+}
+
+template <typename T>
+static int32_t persist_launch(Ctx &c, const Opts &o) {
+  PersistArgs<T> P;
+  std::memset(&P, 0, sizeof(P));
+  P.nsd = (int)c.sds.size();
+  P.status = c.d_status;
+  P.opts = o;
+  for (int i = 0; i < kMaxSd; ++i) P.slot[i] = 0;
+  // state blocks, then the scratch shared by the subdomains, then operators while they fit
+  long long off = 0;
+  int max_rs = 1, max_r2 = 1, max_r = 1;
+  for (int i = 0; i < P.nsd; ++i) {
+    Subdomain &d = *c.sds[i];
+    RomArgs<T> &A = P.sd[i];
+    fill_rom_args<T>(c, d, i, o, A);
+    // the whole step here: operators, not the batched parts
+    A.A = (const T *)d.d_A;
+    A.H = (const T *)d.d_H;
+    A.c = (const T *)d.d_c;
+    A.r2 = d.oh.quadratic ? d.r * (d.r + 1) / 2 : 0;
+    A.f0part = nullptr;
+    A.gpart = nullptr;
+    P.slot[i] = i;
+    PersistLayout &Y = P.lay[i];
+    for (int p = 0; p < 2; ++p) {
+      Y.q[p] = (int)off;
+      off += d.r;
+      Y.v[p] = (int)off;
+      off += d.r;
+      Y.a[p] = (int)off;
+      off += d.r;
+    }
+    Y.q1 = (int)off;
+    off += d.r;
+    Y.qp = (int)off;
+    off += d.r;
+    Y.am = Y.h = Y.bm = Y.c = Y.tm[0] = Y.tm[1] = Y.pre = -1;
+    max_rs = std::max(max_rs, d.rs);
+    max_r2 = std::max(max_r2, A.r2);
+    max_r = std::max(max_r, d.r);
+  }
+  P.sh_off = (int)off;
+  off += max_rs;
+  P.k2_off = (int)off;
+  off += max_r2;
+  P.rows_off = (int)off;
+  off += max_r;
+  const long long cap = (long long)(kPersistLds / sizeof(T));
+  if (off > cap) return c.fail(OSAM_E_INVALID, "persistent OpInf engine: the reduced states exceed the LDS");
+  auto place = [&](int &slot, long long n) {
+    if (n > 0 && off + n <= cap) {
+      slot = (int)off;
+      off += n;
+    }
+  };
+  // the row terms that do not change over a step's sweeps first, then the operators
+  for (int i = 0; i < P.nsd; ++i) place(P.lay[i].pre, (long long)P.sd[i].r * 64);
+  for (int i = 0; i < P.nsd; ++i) place(P.lay[i].am, (long long)P.sd[i].r * P.sd[i].r);
+  for (int i = 0; i < P.nsd; ++i)
+    for (int f = 0; f < P.sd[i].nfaces; ++f) place(P.lay[i].tm[f], (long long)P.sd[i].rs * P.sd[i].fin[f].src_r);
+  for (int i = 0; i < P.nsd; ++i) {
+    if (P.sd[i].B) place(P.lay[i].bm, (long long)P.sd[i].r * P.sd[i].rs);
+    if (P.sd[i].c) place(P.lay[i].c, P.sd[i].r);
+  }
+  for (int i = 0; i < P.nsd; ++i)
+    if (P.sd[i].r2 > 0) place(P.lay[i].h, (long long)P.sd[i].r * P.sd[i].r2);
+  const hipError_t e = launch_rom_persist<T>(P, c.batch, (size_t)off * sizeof(T), c.stream);
+  if (e != hipSuccess) return c.fail(OSAM_E_HIP, std::string("persistent OpInf kernel: ") + hipGetErrorString(e));
+  return OSAM_OK;
+}
+
+int32_t Ctx::run_persist(int64_t n_steps, const Opts &o, osam_instance_info *info) {
+  const std::string why = persist_unsupported(o);
+  if (!why.empty()) return fail(OSAM_E_INVALID, "persistent OpInf engine: " + why);
+  bool any = false;
+  for (int b = 0; b < batch; ++b) {
+    Status &S = h_status[b];
+    if (S.flags & kNonfinite) continue;
+    S.target = S.step + n_steps;
+    S.flags &= ~kFinished;
+    if (n_steps == 0) S.flags |= kFinished;
+    S.iter = 0;
+    any |= n_steps > 0;
+  }
+  HIPCHK(hipMemcpyAsync(d_status, h_status, sizeof(Status) * batch, hipMemcpyHostToDevice, stream));
+  int32_t st = OSAM_OK;
+  if (any) st = prec == OSAM_FP64 ? persist_launch<double>(*this, o) : persist_launch<float>(*this, o);
+  if (st) return st;
+  if ((st = sync_status())) return st;
+  return instance_info(info);
+}
+
 int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_info *info, bool host_sweeps) {
   if (!(op.tol_abs >= 0) || !(op.tol_rel >= 0) || op.min_iter < 1 || op.max_iter < op.min_iter ||
       op.max_iter > 1000000 || (op.guess != OSAM_GUESS_HOLD && op.guess != OSAM_GUESS_PREDICTOR) ||
@@ -1100,6 +1209,7 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
   o.guess = op.guess;
   o.additive = op.additive;
   o.nsd = (int)sds.size();
+  if (engine == 2) return run_persist(n_steps, o, info);
   if (window_mode()) return run_window(n_steps, o, info);
   bool any = false;
   for (int b = 0; b < batch; ++b) {
@@ -1176,6 +1286,12 @@ int32_t Ctx::run(int64_t n_steps, const osam_schwarz_opts &op, osam_instance_inf
     for (int b = 0; b < batch; ++b) any |= !(h_status[b].flags & kFinished);
   }
   if ((st = sync_status())) return st;
+  return instance_info(info);
+}
+
+// The host copy of the statuses into info (may be null); OSAM_E_NONFINITE if any instance
+// went non-finite.
+int32_t Ctx::instance_info(osam_instance_info *info) {
   bool nonfinite = false;
   for (int b = 0; b < batch; ++b) {
     const Status &S = h_status[b];

@@ -177,7 +177,7 @@ struct Ctx {
                         hipStream_t st = nullptr, bool defer = false);
   int32_t learn(int sd, const osam_opinf_desc &d);
   // window engine (window.hip): sub-stepped or implicit subdomains, or on request
-  int engine = 0;                  // 0 automatic, 1 window engine for every run
+  int engine = 0;                  // 0 automatic, 1 window engine for every run, 2 persistent OpInf
   bool win_ready = false;
   std::vector<void *> win_allocs;
   double *win_sums = nullptr;      // [batch][nsd][2]
@@ -185,6 +185,9 @@ struct Ctx {
   bool window_mode() const;
   int32_t window_setup();
   int32_t run_window(int64_t n_steps, const Opts &o, osam_instance_info *info);
+  int32_t run_persist(int64_t n_steps, const Opts &o, osam_instance_info *info);
+  std::string persist_unsupported(const Opts &o) const;
+  int32_t instance_info(osam_instance_info *info);
   // device address of the static scratch array on this context's device (noalloc.hip)
   void *static_scratch = nullptr;
 };

@@ -464,7 +464,7 @@ extern "C" int32_t osam_set_engine(osam_ctx *c, int32_t engine) {
   if (!c) return OSAM_E_INVALID;
   Ctx *ctx = reinterpret_cast<Ctx *>(c);
   ctx->err.clear();
-  if (engine != 0 && engine != 1) return ctx->fail(OSAM_E_INVALID, "engine must be 0 or 1");
+  if (engine < 0 || engine > 2) return ctx->fail(OSAM_E_INVALID, "engine must be 0, 1 or 2");
   ctx->engine = engine;
   return OSAM_OK;
 }

@@ -588,7 +588,8 @@ class Context:
         return p.value
 
     def set_engine(self, engine: int):
-        """0: automatic (the single-step explicit path where it applies), 1: the window engine."""
+        """0: automatic (the single-step explicit path where it applies), 1: the window engine,
+        2: the persistent OpInf engine (contexts of explicit OpInf subdomains only)."""
         self._check(self.lib.osam_set_engine(self.h, int(engine)))
 
     def solver_stats(self, sd: int) -> List[int]:
