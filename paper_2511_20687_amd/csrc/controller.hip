@@ -1133,7 +1133,9 @@ static int32_t persist_launch(Ctx &c, const Opts &o) {
     off += d.r;
     Y.qp = (int)off;
     off += d.r;
-    Y.am = Y.h = Y.bm = Y.c = Y.tm[0] = Y.tm[1] = Y.pre = -1;
+    Y.f0 = (int)off;
+    off += d.r;
+    Y.am = Y.h = Y.bm = Y.c = Y.tm[0] = Y.tm[1] = -1;
     max_rs = std::max(max_rs, d.rs);
     max_r2 = std::max(max_r2, A.r2);
     max_r = std::max(max_r, d.r);
@@ -1152,15 +1154,26 @@ static int32_t persist_launch(Ctx &c, const Opts &o) {
       off += n;
     }
   };
-  // the row terms that do not change over a step's sweeps first, then the operators
-  for (int i = 0; i < P.nsd; ++i) place(P.lay[i].pre, (long long)P.sd[i].r * 64);
-  for (int i = 0; i < P.nsd; ++i) place(P.lay[i].am, (long long)P.sd[i].r * P.sd[i].r);
-  for (int i = 0; i < P.nsd; ++i)
-    for (int f = 0; f < P.sd[i].nfaces; ++f) place(P.lay[i].tm[f], (long long)P.sd[i].rs * P.sd[i].fin[f].src_r);
+  // what every sweep reads (B, c and the transfer blocks, small) always goes to LDS, then A
+  // and H (read once per step) while they fit
   for (int i = 0; i < P.nsd; ++i) {
-    if (P.sd[i].B) place(P.lay[i].bm, (long long)P.sd[i].r * P.sd[i].rs);
-    if (P.sd[i].c) place(P.lay[i].c, P.sd[i].r);
+    PersistLayout &Y = P.lay[i];
+    const RomArgs<T> &A = P.sd[i];
+    for (int f = 0; f < A.nfaces; ++f) {
+      Y.tm[f] = (int)off;
+      off += (long long)A.rs * A.fin[f].src_r;
+    }
+    if (A.B) {
+      Y.bm = (int)off;
+      off += (long long)A.r * A.rs;
+    }
+    if (A.c) {
+      Y.c = (int)off;
+      off += A.r;
+    }
   }
+  if (off > cap) return c.fail(OSAM_E_INVALID, "persistent OpInf engine: the reduced states exceed the LDS");
+  for (int i = 0; i < P.nsd; ++i) place(P.lay[i].am, (long long)P.sd[i].r * P.sd[i].r);
   for (int i = 0; i < P.nsd; ++i)
     if (P.sd[i].r2 > 0) place(P.lay[i].h, (long long)P.sd[i].r * P.sd[i].r2);
   const hipError_t e = launch_rom_persist<T>(P, c.batch, (size_t)off * sizeof(T), c.stream);

@@ -13,9 +13,9 @@ constexpr size_t kPersistLds = 159 * 1024;      // dynamic LDS of the workgroup
 struct PersistLayout {
   int q[2], v[2], a[2];   // state by step parity (accepted: step % 2; iterates: the other)
   int q1, qp;             // predictor q(t_k) of the step; predictor of the latest iterate
-  int am, h, bm, c;       // A [r][r], H [r][r2], B [r][rs], c [r] (row-major)
-  int tm[2];              // Phi_S,face^T Pi Phi_src [rs][r_src] per face
-  int pre;                // [r][64]: each lane's A and H terms of each row, kept over a step
+  int f0;                 // the (A q + H (q (x) q)) rows of the step
+  int am, h, bm, c;       // A [r][r], H [r][r2] (or -1: global), B [r][rs], c [r] (row-major)
+  int tm[2];              // Phi_S,face^T Pi Phi_src [rs][r_src] per face (B, c, tm: always in LDS)
 };
 
 template <typename T>

@@ -10,6 +10,17 @@ namespace osam {
 
 __device__ __forceinline__ double wave_sum_d(double x) { return wave_total(x); }
 
+// The value lane l (wave-uniform) holds.
+__device__ __forceinline__ float lane_value(float x, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 constexpr int kRomThreads = 512;
 constexpr int kRomWaves = kRomThreads / 64;   // 8
 constexpr int kRowsPerWave = 16;              // rows i = wave + 8 j: r <= 128
@@ -284,7 +295,8 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, const StepS
     __syncthreads();
   }
 
-  // ---- 5. q''(t_k) rows: A q + H k2 + B g^ (+ c below), one wave per row
+  // ---- 5. q''(t_k) rows: (A q + H k2) + B g^ (+ c below), one wave per row: the first
+  // term by the wave's reduction, the second serially over the modes of g^
 #pragma unroll
   for (int j = 0; j < kRowsPerWave; ++j) {
     const int i = wid + kRomWaves * j;
@@ -295,10 +307,12 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, const StepS
 #pragma unroll 4
       for (int m = lane; m < r2; m += 64) s += Hr[m] * k2[m];
     }
-    if (lane < rs) s += brow[j] * sh[lane];
-    for (int l = 64 + lane; l < rs; l += 64) s += A.B[(long long)i * rs + l] * sh[l];
-    s = wave_total(s);
-    if (lane == 0) qdd1s[i] += s;
+    if (!PRE) s = wave_total(s);   // the row of A q + H (q (x) q): fixed over a step's sweeps
+    // B g^, serial over the modes of g^ (every lane the same value; lane l holds B[i, l])
+    T bs = T(0);
+    for (int l = 0; l < rs && l < 64; ++l) bs += lane_value(brow[j], l) * sh[l];
+    for (int l = 64; l < rs; ++l) bs += A.B[(long long)i * rs + l] * sh[l];
+    if (lane == 0) qdd1s[i] += s + bs;
   }
   __syncthreads();
 
