@@ -320,7 +320,8 @@ def main():
                      "frac": k_gbs / HBM_PEAK_GBS, "traffic": traffic_bytes,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
-                     "kernel": ("sweep_kernel<float, 1, 0> (FE step + OpInf step in one launch)" if fused
+                     "kernel": ("sweep_kernel<float, 1, 0, true> (FE step + OpInf step in one launch; every "
+                                "workgroup first takes the previous sweep's convergence decision)" if fused
                                 else "fe_lds_kernel<step> + boundary fe_kernel<float, step>"
                                 if tuning["fe"][0][0] == 1024 else "fe_kernel<float, step>"),
                      "kernel_avg_us": k_avg_us,
