@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched OpInf-OpInf comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-large-fe", action="store_true", help="skip the 64x64x640 FE step timing")
+    ap.add_argument("--no-survey", action="store_true",
+                    help="skip the 24x24x240 hybrid under traction-free lateral faces and s = 0.05")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the 4x4x40 legs (explicit, implicit, mixed steps, Saint Venant-Kirchhoff)")
     args = ap.parse_args()
@@ -265,6 +267,12 @@ def main():
     if not args.no_large_fe:
         large_fe = large_fe_timing(_log)
 
+    # ---- the same hybrid under traction-free lateral faces and s = 0.05 (errors, energy ranks) ----
+    survey = None
+    if not args.no_survey:
+        from paper_2511_20687_amd import survey_case
+        survey = _guarded("hybrid under other input readings", lambda: survey_case.run(_log))
+
     # ---- latency-bound legs on the 4x4x40 bar (both engines) ----
     latency = None
     if not args.no_latency:
@@ -335,6 +343,7 @@ def main():
         "adjoint": adjoint,
         "large_fe": large_fe,
         "latency_legs_bar_4x4x40": latency,
+        "hybrid_bar_24x24x240_other_readings": survey,
     }
     print(json.dumps(line), flush=True)
 
