@@ -291,3 +291,46 @@ def synthetic_rom(seed, n_free, n_sch, r, rs, dt, quadratic=False, with_c=False,
     H = 1e-3 * (1.0 / dt) ** 2 * random_normal(seed + 4, (r, r * (r + 1) // 2)) if quadratic else None
     c = 1e-6 * (1.0 / dt) ** 2 * random_normal(seed + 5, (r,)) if with_c else None
     return dict(Phi=Phi, PhiS=PhiS, A=A, B=B, H=H, c=c)
+
+
+@dataclass
+class ModalSnapshots:
+    """Snapshots with a known singular value decomposition (for learning at full size).
+
+    Column j (time t_j = j dt, j < T) of the displacement snapshots is
+    sum_k Phi[:, k] sigma_k v_k(j) with v_k(j) = sqrt(2 / T) cos(2 pi f_k j / T), distinct
+    integer frequencies 0 < f_k < T / 2: the v_k are orthonormal over the T samples, so
+    Phi diag(sigma) V^T is the thin SVD (Phi orthonormal).  Each mode is a free oscillation of
+    the explicit central-difference step: its acceleration is -w_k^2 times it with
+    w_k^2 = (4 / dt^2) sin^2(pi f_k / T), the second difference of the samples, so that step
+    started from the first sample with zero velocity reproduces every sample exactly."""
+    Phi: np.ndarray          # [n][m] orthonormal
+    sigma: np.ndarray        # [m] descending
+    freq: np.ndarray         # [m] integer frequencies
+    T: int
+    dt: float
+
+    def coefficients(self) -> np.ndarray:
+        """[m][T]: sigma_k v_k(j)."""
+        j = np.arange(self.T)
+        return (self.sigma[:, None] * math.sqrt(2.0 / self.T)
+                * np.cos(2.0 * math.pi * self.freq[:, None] * j[None, :] / self.T))
+
+    def omega2(self) -> np.ndarray:
+        return (4.0 / self.dt ** 2) * np.sin(math.pi * self.freq / self.T) ** 2
+
+    def snapshots(self) -> Tuple[np.ndarray, np.ndarray]:
+        """(U, Udd), each [n][T]."""
+        C = self.coefficients()
+        return self.Phi @ C, self.Phi @ (-self.omega2()[:, None] * C)
+
+
+def modal_snapshots(seed: int, n: int, T: int, m: int, dt: float, decades: float) -> ModalSnapshots:
+    """Seeded ModalSnapshots: sigma log-spaced over `decades` decades from 1, frequencies a
+    seeded draw of m distinct integers in [1, T/8) (slow modes: resolved by the time step)."""
+    Phi = np.linalg.qr(random_normal(seed, (n, m)))[0]
+    g = np.random.Generator(np.random.PCG64(SplitMix64(seed + 1).next_u64()))
+    freq = np.sort(g.choice(np.arange(1, T // 8), size=m, replace=False)).astype(np.int64)
+    g.shuffle(freq)
+    sigma = np.logspace(0.0, -decades, m)
+    return ModalSnapshots(Phi=Phi, sigma=sigma, freq=freq, T=T, dt=dt)
