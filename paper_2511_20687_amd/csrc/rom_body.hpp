@@ -53,6 +53,28 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double (*red)[kRom
   __syncthreads();
 }
 
+// block_reduce restricted to the entries whose bit is set in `used` (wave-uniform): the
+// others are zero on every thread and give 0 without their wave reductions.
+template <int NV, typename T>
+__device__ __forceinline__ void block_reduce_used(double (&v)[NV], unsigned used, double (*red)[kRomWaves],
+                                                  T *out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    if ((used >> k) & 1u) v[k] = wave_sum_d(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k][wid] = ((used >> k) & 1u) ? v[k] : 0.0;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    double t = 0.0;
+    for (int w = 0; w < kRomWaves; ++w) t += red[threadIdx.x][w];
+    out[threadIdx.x] = (T)t;
+  }
+  __syncthreads();
+}
+
 // Grid (G, batch): the G workgroups of an instance each take one slice of the
 // push rows and recompute the (small) reduced step redundantly, so the push
 // streams through G CUs instead of one; workgroup 0 alone stores the state and
@@ -230,7 +252,9 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, const StepS
             part[9 + 2 * k] += pa[k][d].y;
           }
     }
-    block_reduce<12>(part, red, tot);
+    const unsigned used = (small_face ? (1u << rs) - 1u : 0u) |
+                          (small_part ? ((1u << (2 * min(F.nfom, 2))) - 1u) << 8 : 0u);
+    block_reduce_used<12>(part, used, red, tot);
     if (small_face && tid < rs) sh[tid] = (T)tot[tid];
   }
   for (int fi = small_face ? 1 : 0; fi < A.nfaces; ++fi) {
