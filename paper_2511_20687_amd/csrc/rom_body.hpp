@@ -92,13 +92,27 @@ __host__ __device__ inline int rom_variant(const RomArgs<T> &A) {
   return (A.f0part ? kRomPre : 0) | (A.nexp == 0 ? kRomNoPushRegs : 0);
 }
 
-// st (optional): flags, step and iteration of the status this step starts from, when the
-// caller holds them (folded decisions of fused sweeps); else read from A.status[b].
-template <typename T, int V>
-__device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, const StepState *st = nullptr) {
+// The status a step starts from, read from A.status[b] (flags, step, iteration).
+template <typename T>
+struct StatusOf {
+  const RomArgs<T> &A;
+  __device__ __forceinline__ StepState operator()() const {
+    const Status *p = A.status + blockIdx.y;
+    StepState s;
+    s.step = p->step;
+    s.iter = p->iter;
+    s.flags = p->flags;
+    return s;
+  }
+};
+
+// state(): the status this step starts from (StatusOf, or the folded decision of a fused
+// sweep); every thread of the workgroup calls it once, after the loads of phase 1 are
+// issued, so that those loads (which do not depend on it) go out first.
+template <typename T, int V, typename State>
+__device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state) {
   constexpr bool PRE = (V & kRomPre) != 0, PUSHREG = (V & kRomNoPushRegs) == 0;
   const int b = blockIdx.y;
-  const Status *stp = A.status + b;
   const int r = A.r, rs = A.rs, r2 = A.r2;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const long long qo = (long long)b * r;
@@ -115,10 +129,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, const StepS
   __shared__ double tot[12];
   __shared__ double nsum[2];
 
-  // ---- 1. loads independent of this step's results
-  const int flags = st ? st->flags : stp->flags;
-  const long long step = st ? st->step : stp->step;
-  const int iter = st ? st->iter : stp->iter;
+  // ---- 1. loads independent of this step's results (and of its status)
   const int tq = min(tid, r - 1);
   T xq[2], xqd[2], xqdd[2], x_c = T(0);
 #pragma unroll
@@ -199,6 +210,10 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, const StepS
       for (int d = 0; d < kFaceDofs; ++d) pa[k][d] = pp[min(tid + kRomThreads * d, F.nblocks[kk] - 1)];
     }
   }
+  const StepState ss = state();
+  const int flags = ss.flags;
+  const long long step = ss.step;
+  const int iter = ss.iter;
   if (flags & kFinished) {
     if (last && g == 0 && wid == 0) finish_sweep<4>(A.status, A.status_out, F, A.opts, b);   // carries the status over
     return;

@@ -23,7 +23,7 @@ namespace osam {
 
 template <typename T, int V>
 __global__ void __launch_bounds__(kRomThreads) rom_kernel(RomArgs<T> A) {
-  rom_body<T, V>(A, blockIdx.x);
+  rom_body<T, V>(A, blockIdx.x, StatusOf<T>{A});
 }
 
 template <typename T>

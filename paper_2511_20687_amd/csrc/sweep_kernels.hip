@@ -58,23 +58,34 @@ __device__ inline void fold_decision(const Status *prev, Status *next, const Fin
 template <typename T, int FE, int V, bool FOLD>
 __global__ void __launch_bounds__(kRomThreads) sweep_kernel(SweepArgs<T> S) {
   __shared__ Status cur;
-  StepState ss;
-  const StepState *st = nullptr;
-  if (FOLD) {
+  int x = blockIdx.x, i = 0;
+  while (i + 1 < S.n && x >= S.nblk[i]) x -= S.nblk[i++];
+  // the folded decision's result in scalar registers (workgroup-uniform values)
+  auto folded = [&]() {
     fold_decision(S.st_prev, S.st_cur, S.prev, S.opts, cur);
-    // workgroup-uniform values: scalar registers, as the status loads of the bodies
+    StepState ss;
     const unsigned long long su = (unsigned long long)cur.step;
     const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)su);
     const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(su >> 32));
     ss.step = (long long)(((unsigned long long)hi << 32) | lo);
     ss.iter = __builtin_amdgcn_readfirstlane(cur.iter);
     ss.flags = __builtin_amdgcn_readfirstlane(cur.flags);
-    st = &ss;
+    return ss;
+  };
+  if (FE == 0 || S.rom_idx[i] >= 0) {
+    // an OpInf step issues its operand loads before it takes the decision
+    const RomArgs<T> &A = S.rom[S.rom_idx[i]];
+    if (FOLD) rom_body<T, V>(A, x, folded);
+    else rom_body<T, V>(A, x, StatusOf<T>{A});
+  } else {
+    StepState ss;
+    const StepState *st = nullptr;
+    if (FOLD) {
+      ss = folded();
+      st = &ss;
+    }
+    fe_body<T, kModeStep, FE == 1, true, false>(S.fe[S.fe_idx[i]], x, st);
   }
-  int x = blockIdx.x, i = 0;
-  while (i + 1 < S.n && x >= S.nblk[i]) x -= S.nblk[i++];
-  if (FE == 0 || S.rom_idx[i] >= 0) rom_body<T, V>(S.rom[S.rom_idx[i]], x, st);
-  else fe_body<T, kModeStep, FE == 1, true, false>(S.fe[S.fe_idx[i]], x, st);
 }
 
 // FP64: one FE layer per thread only (fe != 2).
