@@ -661,6 +661,7 @@ static void fill_fe_args(Ctx &c, Subdomain &s, int sdi, const Opts &o, FeArgs<T>
   A.status = c.d_status;
   A.sd = sdi;
   A.opts = o;
+  A.skip_rows = s.desc.lateral_fix & 7;
   A.partials = s.partials;
   A.kc = s.fe_kc;
   A.n_chunks = s.fe_chunks;

@@ -285,9 +285,9 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
 #pragma unroll
       for (int p = 0; p < 3; ++p) acc[p] = x_combine(s0[p], sm[p], sp[p], kx_diag(A.cb, p), w1[3][p], ctr[p], w1[5][p]);
     } else {
-      slab<T, -1>(C, w0, ctr, acc);
-      slab<T, 0>(C, w1, ctr, acc);
-      slab<T, 1>(C, w2, ctr, acc);
+      slab<T, -1>(C, w0, ctr, acc, A.skip_rows);
+      slab<T, 0>(C, w1, ctr, acc, A.skip_rows);
+      slab<T, 1>(C, w2, ctr, acc, A.skip_rows);
     }
     if (!act) return;
     update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
@@ -313,8 +313,8 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
     xslab<T>(A.cb, 0, nxt, cur, sm, s0, sp);
     xslab<T>(A.cb, 1, cur, cur, sm, s0, sp);
   } else {
-    slab<T, -1>(C, nxt, ctr, acc);
-    slab<T, 0>(C, cur, ctr, acc);
+    slab<T, -1>(C, nxt, ctr, acc, A.skip_rows);
+    slab<T, 0>(C, cur, ctr, acc, A.skip_rows);
   }
   if (act && rec && A.rec_s && k0 == 1 && A.face_src[0] >= 0) record_face<T>(A, b, 0, nid0, nxt, rcol);
 
@@ -327,7 +327,7 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
 #pragma unroll
       for (int p = 0; p < 3; ++p) acc[p] = x_combine(s0[p], sm[p], sp[p], kx_diag(A.cb, p), cur[3][p], ctr[p], cur[5][p]);
     } else {
-      slab<T, 1>(C, nxt, ctr, acc);
+      slab<T, 1>(C, nxt, ctr, acc, A.skip_rows);
     }
     if (act)
       update_node<T, MODE, UK>(A, R, b, k, nid0, ctr, acc, v0, a0, old, n_iter, rec, rbase, acc_abs, acc_den);
@@ -342,8 +342,8 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
         xslab<T>(A.cb, 0, cur, nxt, sm, s0, sp);
         xslab<T>(A.cb, 1, nxt, nxt, sm, s0, sp);
       } else {
-        slab<T, -1>(C, cur, ctr, acc);
-        slab<T, 0>(C, nxt, ctr, acc);
+        slab<T, -1>(C, cur, ctr, acc, A.skip_rows);
+        slab<T, 0>(C, nxt, ctr, acc, A.skip_rows);
       }
 #pragma unroll
       for (int n = 0; n < 9; ++n)

@@ -251,6 +251,7 @@ struct FeArgs {
   T *v[2];
   T *a[2];
   const T *coef;           // [9 cases][26 offsets][3][3]: -K_d / m
+  int skip_rows;           // components held on the lateral faces (zero rows of the boundary cases)
   T cb[27];                // the interior block's 27 distinct values (box_index)
   T dt, half_dt, half_dt2;
   int face_src[2];         // source subdomain of the low / high face, -1 if clamped

@@ -227,17 +227,21 @@ __device__ __forceinline__ T x_combine(T s0, T sm, T sp, T kx, T um, T u, T up) 
 // the boundary columns (interior nodes: xslab) whose own value is ctr:
 // acc += sum_n C_(dx,dy,DZ) (w[n] - ctr), C the node's case block (memory).
 template <typename T, int DZ>
-__device__ __forceinline__ void slab(const T *C, const T (&w)[9][3], const T (&ctr)[3], T (&acc)[3]) {
+__device__ __forceinline__ void slab(const T *C, const T (&w)[9][3], const T (&ctr)[3], T (&acc)[3],
+                                     int skip = 0) {
+  // skip (wave-uniform): components whose coefficient rows are zero (held lateral
+  // components of the boundary cases); each acc[p] sums over n, q in the same order
 #pragma unroll
-  for (int n = 0; n < 9; ++n) {
-    const int d27 = (DZ + 1) * 9 + n;
-    if (d27 == 13) continue;
-    const int d26 = d27 < 13 ? d27 : d27 - 1;
-    const T du[3] = {w[n][0] - ctr[0], w[n][1] - ctr[1], w[n][2] - ctr[2]};
+  for (int p = 0; p < 3; ++p) {
+    if ((skip >> p) & 1) continue;
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int n = 0; n < 9; ++n) {
+      const int d27 = (DZ + 1) * 9 + n;
+      if (d27 == 13) continue;
+      const int d26 = d27 < 13 ? d27 : d27 - 1;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) acc[p] += C[d26 * 9 + p * 3 + q] * du[q];
+      for (int q = 0; q < 3; ++q) acc[p] += C[d26 * 9 + p * 3 + q] * (w[n][q] - ctr[q]);
+    }
   }
 }
 
