@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--no-large-fe", action="store_true", help="skip the 64x64x640 FE step timing")
     ap.add_argument("--no-survey", action="store_true",
                     help="skip the 24x24x240 hybrid under traction-free lateral faces and s = 0.05")
+    ap.add_argument("--fixed-launch", action="store_true",
+                    help="skip the hybrid's autotuner and run fused sweeps (one layer per FE thread) in graphs of "
+                         "128 sweeps, the choice it makes for this workload on MI355X without a profiler: under "
+                         "rocprofv3 the per-launch overhead changes the tuner's timings and so its choice")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the 4x4x40 legs (explicit, implicit, mixed steps, Saint Venant-Kirchhoff)")
     args = ap.parse_args()
@@ -142,7 +146,12 @@ def main():
     # ---- launch configuration by the library's autotuner (untimed set-up) ----
     ctx.set_initial(0, u0, v0)
     t0 = time.perf_counter()
-    tuning = ctx.autotune(trial_steps=200, opts=opts)
+    if args.fixed_launch:
+        ctx.set_fusion(True, 1)
+        ctx.set_graph(128, 1)
+        tuning = {"fixed": True, "fusion_kc": 1, "graph": (128, 1)}
+    else:
+        tuning = ctx.autotune(trial_steps=200, opts=opts)
     t_tune = time.perf_counter() - t0
     _log(f"autotune {t_tune:.2f} s: {tuning}")
 

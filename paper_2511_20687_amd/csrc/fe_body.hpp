@@ -145,12 +145,15 @@ __device__ __forceinline__ void state_loads(const Roles<T> &R, const Strides &B,
 // One layer's 3x3 neighbourhood: interior columns through wave-uniform row bases,
 // boundary columns (clamped indices) through per-lane addresses.
 // XS: interior rows shared across lanes (load_layer_xshare).
+// xf (boundary, wave-uniform): the columns are on an x-face (load_layer_xface, FP32).
 template <typename T, bool INTERIOR, bool XS = false>
 __device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B, long long cs, int L, int npl,
-                                      int nxp, int ix, int iy, int nx, int ny, int nid0) {
+                                      int nxp, int ix, int iy, int nx, int ny, int nid0, bool xf = false) {
   if (INTERIOR && XS) load_layer_xshare<T>(w, P, B, L, (unsigned)(nid0 - nxp) * (unsigned)sizeof(T));
   else if (INTERIOR) load_layer_uniform<T>(w, P, B, L, (unsigned)(nid0 - nxp - 1) * (unsigned)sizeof(T));
-  else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
+  else if (sizeof(T) == 4 && xf) {
+    if constexpr (sizeof(T) == 4) load_layer_xface(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
+  } else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
 }
 
 // One layer k of the x-shared interior layout in x-resolved form (xrow): lane j
@@ -251,6 +254,7 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
     cse = __builtin_amdgcn_readfirstlane((ix == 0 ? 0 : (ix == nx ? 2 : 1)) + 3 * (iy == 0 ? 0 : (iy == ny ? 2 : 1)));
   }
   const T *C = A.coef + cse * 234;
+  const bool xf = !INTERIOR && cse % 3 != 1;   // x-face columns (wave-uniform)
   const Roles<T> R = roles<T, MODE>(A, b, step, n_iter);
   const int k1 = ONE ? k0 + 1 : min(k0 + A.kc, nzs);
   const int nid0 = ix + nxp * iy;
@@ -268,9 +272,9 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   if (ONE) {
     const int k = k0;
     T w0[9][3], w1[9][3], w2[9][3], v0[3], a0[3], old[3], acc[3], ctr[3];
-    layer<T, INTERIOR, XS>(w0, k == 1 ? R.Flo : R.Pin, B, cs, k - 1, npl, nxp, ix, iy, nx, ny, nid0);
-    layer<T, INTERIOR, XS>(w1, R.Pin, B, cs, k, npl, nxp, ix, iy, nx, ny, nid0);
-    layer<T, INTERIOR, XS>(w2, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR, XS>(w0, k == 1 ? R.Flo : R.Pin, B, cs, k - 1, npl, nxp, ix, iy, nx, ny, nid0, xf);
+    layer<T, INTERIOR, XS>(w1, R.Pin, B, cs, k, npl, nxp, ix, iy, nx, ny, nid0, xf);
+    layer<T, INTERIOR, XS>(w2, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0, xf);
     state_loads<T, MODE, UK>(R, B, k, nid0, n_iter, v0, a0, old);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -302,8 +306,8 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   // of layer k from layers k-1 and k until layer k+1 arrives.
   // (interior: the x-resolved sums sm, s0, sp instead of acc until layer k+1 arrives)
   T cur[9][3], nxt[9][3], acc[3], ctr[3], sm[3], s0[3], sp[3];
-  layer<T, INTERIOR, XS>(nxt, k0 == 1 ? R.Flo : R.Pin, B, cs, k0 - 1, npl, nxp, ix, iy, nx, ny, nid0);
-  layer<T, INTERIOR, XS>(cur, R.Pin, B, cs, k0, npl, nxp, ix, iy, nx, ny, nid0);
+  layer<T, INTERIOR, XS>(nxt, k0 == 1 ? R.Flo : R.Pin, B, cs, k0 - 1, npl, nxp, ix, iy, nx, ny, nid0, xf);
+  layer<T, INTERIOR, XS>(cur, R.Pin, B, cs, k0, npl, nxp, ix, iy, nx, ny, nid0, xf);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     ctr[c] = cur[4][c];
@@ -321,7 +325,7 @@ __device__ __forceinline__ void fe_columns(const FeArgs<T> &A, int b, int t, int
   for (int k = k0; k < k1; ++k) {
     T v0[3], a0[3], old[3];
     state_loads<T, MODE, UK>(R, B, k, nid0, n_iter, v0, a0, old);
-    layer<T, INTERIOR, XS>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0);
+    layer<T, INTERIOR, XS>(nxt, k + 1 == nzs ? R.Fhi : R.Pin, B, cs, k + 1, npl, nxp, ix, iy, nx, ny, nid0, xf);
     if (INTERIOR) {
       xslab<T>(A.cb, 2, nxt, cur, sm, s0, sp);
 #pragma unroll

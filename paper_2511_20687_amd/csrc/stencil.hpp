@@ -93,6 +93,32 @@ __device__ __forceinline__ void load_layer(T (&w)[9][3], const T *P, long long c
   }
 }
 
+// load_layer of a boundary column on an x-face (ix = 0 or nx; FP32): the row's two
+// x-positions of the node's own x-cell in one 8-byte load (4-byte alignment suffices),
+// the clamped third position a copy of the face value, as load_layer would read it.
+// Lanes of an x-face wave sit a row apart, so each lane's loads touch lines of their
+// own: a third of the load instructions.  The 8 bytes are split by shifts (the FP32
+// pair taken as the two elements of a vector load compiled to one 4-byte load).
+typedef unsigned long long osam_u64_a4 __attribute__((aligned(4)));
+__device__ __forceinline__ void load_layer_xface(float (&w)[9][3], const float *P, long long cs, int L, int npl,
+                                                 int nxp, int ix, int iy, int nx, int ny) {
+  const int j0 = ix == 0 ? 0 : nx - 1;   // x-positions j0, j0 + 1
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    int jy = iy + r - 1;
+    jy = jy < 0 ? 0 : (jy > ny ? ny : jy);
+    const float *p = P + (long long)L * npl + (j0 + nxp * jy);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const unsigned long long v = *reinterpret_cast<const osam_u64_a4 *>(p + c * cs);
+      const float x0 = __builtin_bit_cast(float, (unsigned)v), x1 = __builtin_bit_cast(float, (unsigned)(v >> 32));
+      w[3 * r][c] = x0;                      // x - 1 (clamped to 0 on the low face)
+      w[3 * r + 1][c] = ix == 0 ? x0 : x1;   // the face
+      w[3 * r + 2][c] = x1;                  // x + 1 (clamped to nx on the high face)
+    }
+  }
+}
+
 // Raw buffer access to one instance's [3][cs] field (gfx9-family resource,
 // word 3 = 0x00020000): the resource and the byte offset soff are wave-uniform,
 // only the per-lane byte offset voff lives in a vector register, so the
