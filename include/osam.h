@@ -431,7 +431,7 @@ int32_t osam_set_graph(osam_ctx *ctx, int32_t rounds, int32_t streams);
  * predictor) from the source's accepted state.  Results and iteration counts
  * equal those of the sequential launches.  FOM steps run the column kernel
  * with 512 threads per workgroup and kc (>= 1; 0 means 1) node layers per
- * thread (FP64 contexts: always one), whatever osam_set_fe_launch chose (that
+ * thread, whatever osam_set_fe_launch chose (that
  * choice still serves the initial acceleration).  Combines with osam_set_graph (its streams setting is
  * then unused).  At most 4 subdomains, 3 FOM and 2 OpInf: OSAM_E_INVALID here
  * when the context already has more, and from run when a sweep does not fit

@@ -688,8 +688,7 @@ int32_t osam_set_fusion(osam_ctx *c, int32_t enable, int32_t kc) {
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->fuse = enable != 0;
-  // FP64 sweeps take one layer per FE thread (the multi-layer FP64 variant is not built)
-  ctx->fuse_kc = (kc > 0 && ctx->prec != OSAM_FP64) ? kc : 1;
+  ctx->fuse_kc = kc > 0 ? kc : 1;
   return OSAM_OK;
 }
 

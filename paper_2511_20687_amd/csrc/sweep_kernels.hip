@@ -88,16 +88,13 @@ __global__ void __launch_bounds__(kRomThreads) sweep_kernel(SweepArgs<T> S) {
   }
 }
 
-// FP64: one FE layer per thread only (fe != 2).
 template <typename T, int V, bool FOLD>
 static bool launch_sweep_f(const SweepArgs<T> &S, dim3 grid, int fe, size_t smem, hipStream_t s, hipEvent_t ev0,
                            hipEvent_t ev1) {
   const dim3 block(kRomThreads);
   if (fe == 0) hipExtLaunchKernelGGL((sweep_kernel<T, 0, V, FOLD>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
   else if (fe == 1) hipExtLaunchKernelGGL((sweep_kernel<T, 1, V, FOLD>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
-  else if constexpr (sizeof(T) == 4)
-    hipExtLaunchKernelGGL((sweep_kernel<T, 2, V, FOLD>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
-  else return false;
+  else hipExtLaunchKernelGGL((sweep_kernel<T, 2, V, FOLD>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, S);
   return true;
 }
 template <typename T, int V>

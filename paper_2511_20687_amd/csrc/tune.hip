@@ -56,7 +56,7 @@ int32_t Ctx::apply_tuning(const osam_tuning &t) {
   graph_rounds = t.graph_rounds;
   graph_streams = t.graph_streams;
   fuse = t.fusion_kc > 0;
-  fuse_kc = fuse && prec != OSAM_FP64 ? t.fusion_kc : 1;
+  fuse_kc = fuse ? t.fusion_kc : 1;
   return OSAM_OK;
 }
 
@@ -170,7 +170,6 @@ int32_t Ctx::autotune(int64_t n, const osam_schwarz_opts &op, osam_tuning *out) 
   if (fusion_unsupported().empty()) {
     const int fmodes[][2] = {{1, 0}, {1, 32}, {1, 128}, {2, 32}, {4, 32}};
     for (const auto &m : fmodes) {
-      if (prec == OSAM_FP64 && m[0] > 1) continue;   // FP64 sweeps take one layer per FE thread
       fuse = true;
       fuse_kc = m[0];
       graph_rounds = m[1];

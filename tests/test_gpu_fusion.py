@@ -6,7 +6,8 @@ iteration counts, with host launches and with graph replays (eager work between 
 for FOM-FOM, FOM-OpInf, OpInf-FOM-OpInf (batch 20, fused and batched OpInf paths) and
 OpInf-OpInf (the OpInf source's predictor formed from its accepted state; batched path with
 both f0 contractions in one launch), in FP64 and FP32, with one and three node layers per FE
-thread (FP64 only with one: the cases with three are skipped, see _FP64_KC_SKIP).  FP64 FOM-FOM is also checked
+thread (FP64 too: its sweep kernel with an OpInf body and three layers per FE thread spills
+heavily, and these cases guard it).  FP64 FOM-FOM is also checked
 against the oracle.
 """
 import numpy as np
@@ -17,9 +18,6 @@ from tests._gpu import lib_index_of, oracle_fom_coupled, rel_err
 from tests.test_gpu_graph import _context, _run
 
 pytestmark = pytest.mark.gpu
-_FP64_KC_SKIP = ("FP64 fused sweeps with several FE layers per thread are not built: that variant gave "
-                 "non-finite states after the x-resolved stencil change and no cause was found; FP64 "
-                 "contexts fuse with one layer per thread (the kc = 1 cases)")
 
 
 @pytest.mark.parametrize("kc", [1, 3])
@@ -35,8 +33,6 @@ _FP64_KC_SKIP = ("FP64 fused sweeps with several FE layers per thread are not bu
     (("fom", "opinf", "fom"), "f64", 2, 70, 0),
 ])
 def test_fused_sweeps_equal_sequential_launches(kinds, precision, batch, n, rom_path, kc):
-    if precision == "f64" and kc > 1:
-        pytest.skip(_FP64_KC_SKIP)
     bar = Bar(3, 3, 36)
     ctx, sds, layers = _context(kinds, precision, batch, bar)
     if rom_path:
