@@ -25,7 +25,10 @@ constexpr int kRomThreads = 512;
 constexpr int kRomWaves = kRomThreads / 64;   // 8
 constexpr int kRowsPerWave = 16;              // rows i = wave + 8 j: r <= 128
 constexpr int kFaceDofs = 4;                  // face DOFs per thread on the fast g^ path
-constexpr int kPushK = 64;                    // modes of the push row held in registers
+// modes of the push row held in registers: 40 (models with r <= 40), else 64 (the rest
+// streams at the push); every push adds the held modes in one order, so both widths give
+// the same bits where they apply
+constexpr int kPushNarrow = 40, kPushWide = 64;
 
 // 16-byte vectors (push rows are read a row per thread, 16 bytes per load)
 template <typename T>
@@ -84,12 +87,24 @@ __device__ __forceinline__ void block_reduce_used(double (&v)[NV], unsigned used
 // for both state parities and all three face roles.
 // Variants (register budget): kRomPre = f0 and the FOM-fed g^ arrive as
 // partial sums (no A rows, no quadratic term, no FOM face here);
-// kRomNoPushRegs = no push row held in registers (no FOM neighbour).
-constexpr int kRomPre = 1, kRomNoPushRegs = 2;
+// kRomNoPushRegs = no push row held in registers (no FOM neighbour);
+// kRomWidePush = kPushWide modes of the push row held (r > kPushNarrow), else kPushNarrow.
+// Registers held for modes a model does not have are spent for nothing: with 64 held
+// modes at r = 40 the fused sweep kernel spilled 40 VGPRs (132 bytes of scratch per lane),
+// with 40 it spills 7 (32 bytes), and a Schwarz sweep of the 24x24x240 FOM-OpInf bar
+// takes 14.5 instead of 15.5 us.
+constexpr int kRomPre = 1, kRomNoPushRegs = 2, kRomWidePush = 4;
 
 template <typename T>
 __host__ __device__ inline int rom_variant(const RomArgs<T> &A) {
-  return (A.f0part ? kRomPre : 0) | (A.nexp == 0 ? kRomNoPushRegs : 0);
+  return (A.f0part ? kRomPre : 0) |
+         (A.nexp == 0 ? kRomNoPushRegs : (A.r > kPushNarrow ? kRomWidePush : 0));
+}
+// The variant of a kernel holding several OpInf subdomains: the batched parts and no push
+// registers only if every subdomain has them, the wide push row if any needs it.
+__host__ __device__ inline int rom_variant_join(int a, int b) {
+  const int v = (a & b & (kRomPre | kRomNoPushRegs)) | ((a | b) & kRomWidePush);
+  return (v & kRomNoPushRegs) ? (v & ~kRomWidePush) : v;
 }
 
 // The status a step starts from, read from A.status[b] (flags, step, iteration).
@@ -112,6 +127,7 @@ struct StatusOf {
 template <typename T, int V, typename State>
 __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state) {
   constexpr bool PRE = (V & kRomPre) != 0, PUSHREG = (V & kRomNoPushRegs) == 0;
+  constexpr int kPushK = (V & kRomWidePush) ? kPushWide : kPushNarrow;
   const int b = blockIdx.y;
   const int r = A.r, rs = A.rs, r2 = A.r2;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;

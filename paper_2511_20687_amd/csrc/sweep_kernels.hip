@@ -110,7 +110,7 @@ hipError_t launch_sweep(const SweepArgs<T> &S, int batch, bool one, size_t smem,
   int total = 0, v = kRomPre | kRomNoPushRegs, nfe = 0;
   for (int i = 0; i < S.n; ++i) {
     total += S.nblk[i];
-    if (S.rom_idx[i] >= 0) v &= rom_variant(S.rom[S.rom_idx[i]]);
+    if (S.rom_idx[i] >= 0) v = rom_variant_join(v, rom_variant(S.rom[S.rom_idx[i]]));
     else ++nfe;
   }
   const int fe = nfe == 0 ? 0 : (one ? 1 : 2);
@@ -119,9 +119,12 @@ hipError_t launch_sweep(const SweepArgs<T> &S, int batch, bool one, size_t smem,
   bool ok;
   if constexpr (sizeof(T) == 8) {   // the batched parts are FP32 only
     if (v & kRomNoPushRegs) ok = launch_sweep_v<T, kRomNoPushRegs>(S, grid, fe, smem, s, ev0, ev1);
+    else if (v & kRomWidePush) ok = launch_sweep_v<T, kRomWidePush>(S, grid, fe, smem, s, ev0, ev1);
     else ok = launch_sweep_v<T, 0>(S, grid, fe, smem, s, ev0, ev1);
   } else {
-    if (v == 3) ok = launch_sweep_v<T, 3>(S, grid, fe, smem, s, ev0, ev1);
+    if (v == 5) ok = launch_sweep_v<T, 5>(S, grid, fe, smem, s, ev0, ev1);
+    else if (v == 4) ok = launch_sweep_v<T, 4>(S, grid, fe, smem, s, ev0, ev1);
+    else if (v == 3) ok = launch_sweep_v<T, 3>(S, grid, fe, smem, s, ev0, ev1);
     else if (v == 2) ok = launch_sweep_v<T, 2>(S, grid, fe, smem, s, ev0, ev1);
     else if (v == 1) ok = launch_sweep_v<T, 1>(S, grid, fe, smem, s, ev0, ev1);
     else ok = launch_sweep_v<T, 0>(S, grid, fe, smem, s, ev0, ev1);
