@@ -25,10 +25,11 @@ constexpr int kRomThreads = 512;
 constexpr int kRomWaves = kRomThreads / 64;   // 8
 constexpr int kRowsPerWave = 16;              // rows i = wave + 8 j: r <= 128
 constexpr int kFaceDofs = 4;                  // face DOFs per thread on the fast g^ path
-// modes of the push row held in registers: 40 (models with r <= 40), else 64 (the rest
-// streams at the push); every push adds the held modes in one order, so both widths give
-// the same bits where they apply
-constexpr int kPushNarrow = 40, kPushWide = 64;
+// Register widths of the two variants: modes of the push row held (the rest streams at
+// the push) and reduced face modes of the first FOM face held (more take the general
+// loop); narrow for models with r <= 40 and r_S <= 2.  The held entries are added in one
+// order either way, so both widths give the same bits where they apply.
+constexpr int kPushNarrow = 40, kPushWide = 64, kFaceNarrow = 2, kFaceWide = 8;
 
 // 16-byte vectors (push rows are read a row per thread, 16 bytes per load)
 template <typename T>
@@ -88,23 +89,23 @@ __device__ __forceinline__ void block_reduce_used(double (&v)[NV], unsigned used
 // Variants (register budget): kRomPre = f0 and the FOM-fed g^ arrive as
 // partial sums (no A rows, no quadratic term, no FOM face here);
 // kRomNoPushRegs = no push row held in registers (no FOM neighbour);
-// kRomWidePush = kPushWide modes of the push row held (r > kPushNarrow), else kPushNarrow.
-// Registers held for modes a model does not have are spent for nothing: with 64 held
-// modes at r = 40 the fused sweep kernel spilled 40 VGPRs (132 bytes of scratch per lane),
-// with 40 it spills 7 (32 bytes), and a Schwarz sweep of the 24x24x240 FOM-OpInf bar
-// takes 14.5 instead of 15.5 us.
-constexpr int kRomPre = 1, kRomNoPushRegs = 2, kRomWidePush = 4;
+// kRomWide = the wide register widths (r > kPushNarrow or r_S > kFaceNarrow), else narrow.
+// Registers held for modes a model does not have are spent for nothing: with the wide
+// widths at r = 40, r_S = 1 the fused sweep kernel spilled 40 VGPRs (132 bytes of scratch
+// per lane); with the narrow ones it needs 247 VGPRs and spills none, and a Schwarz sweep
+// of the 24x24x240 FOM-OpInf bar takes 14.5 instead of 15.5 us.
+constexpr int kRomPre = 1, kRomNoPushRegs = 2, kRomWide = 4;
 
 template <typename T>
 __host__ __device__ inline int rom_variant(const RomArgs<T> &A) {
   return (A.f0part ? kRomPre : 0) |
-         (A.nexp == 0 ? kRomNoPushRegs : (A.r > kPushNarrow ? kRomWidePush : 0));
+         (A.nexp == 0 ? kRomNoPushRegs : (A.r > kPushNarrow || A.rs > kFaceNarrow ? kRomWide : 0));
 }
 // The variant of a kernel holding several OpInf subdomains: the batched parts and no push
 // registers only if every subdomain has them, the wide push row if any needs it.
 __host__ __device__ inline int rom_variant_join(int a, int b) {
-  const int v = (a & b & (kRomPre | kRomNoPushRegs)) | ((a | b) & kRomWidePush);
-  return (v & kRomNoPushRegs) ? (v & ~kRomWidePush) : v;
+  const int v = (a & b & (kRomPre | kRomNoPushRegs)) | ((a | b) & kRomWide);
+  return (v & kRomNoPushRegs) ? (v & ~kRomWide) : v;
 }
 
 // The status a step starts from, read from A.status[b] (flags, step, iteration).
@@ -127,7 +128,8 @@ struct StatusOf {
 template <typename T, int V, typename State>
 __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state) {
   constexpr bool PRE = (V & kRomPre) != 0, PUSHREG = (V & kRomNoPushRegs) == 0;
-  constexpr int kPushK = (V & kRomWidePush) ? kPushWide : kPushNarrow;
+  constexpr int kPushK = (V & kRomWide) ? kPushWide : kPushNarrow;
+  constexpr int FR = (V & kRomWide) ? kFaceWide : kFaceNarrow;   // face modes held
   const int b = blockIdx.y;
   const int r = A.r, rs = A.rs, r2 = A.r2;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -185,8 +187,8 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
   }
   // first face when fed by a FOM: values of all three roles and up to 8 modes
   const bool small_face = !PRE && A.nfaces > 0 && A.fin[0].type == kFaceFom &&
-                          A.fin[0].n <= kFaceDofs * kRomThreads && rs <= 8;
-  T fv[3][kFaceDofs], fph[kFaceDofs][8];
+                          A.fin[0].n <= kFaceDofs * kRomThreads && rs <= FR;
+  T fv[3][kFaceDofs], fph[kFaceDofs][FR];
   if (small_face) {
     const RomFaceIn<T> &f = A.fin[0];
 #pragma unroll
@@ -195,7 +197,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
 #pragma unroll
       for (int ro = 0; ro < 3; ++ro) fv[ro][d] = f.sface[ro][(long long)b * f.n + m];
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) fph[d][kk] = kk < rs ? f.phis[(long long)kk * f.n + m] : T(0);
+      for (int kk = 0; kk < FR; ++kk) fph[d][kk] = kk < rs ? f.phis[(long long)kk * f.n + m] : T(0);
     }
   }
   // this thread's push row (export 0): (Pi Phi)[m, 0..r)
@@ -257,9 +259,9 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
   if (PRE) {
     __syncthreads();   // sh is complete
   } else {
-    double part[12];
+    double part[FR + 4];   // face modes, then the FOM partial sums
 #pragma unroll
-    for (int kk = 0; kk < 12; ++kk) part[kk] = 0.0;
+    for (int kk = 0; kk < FR + 4; ++kk) part[kk] = 0.0;
     if (small_face) {
       const RomFaceIn<T> &f = A.fin[0];
       const bool hold = n_iter == 1 && (f.src_sd > A.sd || A.opts.additive) && A.opts.guess == 0;
@@ -269,7 +271,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
         const bool ok = tid + kRomThreads * d < f.n;
         const T sv = ok ? (ro == 0 ? fv[0][d] : (ro == 1 ? fv[1][d] : fv[2][d])) : T(0);
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk)
+        for (int kk = 0; kk < FR; ++kk)
           if (kk < rs) part[kk] += (double)(fph[d][kk] * sv);
       }
     }
@@ -279,13 +281,13 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
 #pragma unroll
         for (int d = 0; d < kFaceDofs; ++d)
           if (k < F.nfom && tid + kRomThreads * d < F.nblocks[k]) {
-            part[8 + 2 * k] += pa[k][d].x;
-            part[9 + 2 * k] += pa[k][d].y;
+            part[FR + 2 * k] += pa[k][d].x;
+            part[FR + 1 + 2 * k] += pa[k][d].y;
           }
     }
     const unsigned used = (small_face ? (1u << rs) - 1u : 0u) |
-                          (small_part ? ((1u << (2 * min(F.nfom, 2))) - 1u) << 8 : 0u);
-    block_reduce_used<12>(part, used, red, tot);
+                          (small_part ? ((1u << (2 * min(F.nfom, 2))) - 1u) << FR : 0u);
+    block_reduce_used<FR + 4>(part, used, red, tot);
     if (small_face && tid < rs) sh[tid] = (T)tot[tid];
   }
   for (int fi = small_face ? 1 : 0; fi < A.nfaces; ++fi) {
@@ -432,7 +434,7 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
   if (g != 0) return;
   if (last) {
     if (wid == 0)
-      finish_sweep<4>(A.status, A.status_out, F, A.opts, b, A.sd, nsum[0], nsum[1], small_part ? tot + 8 : nullptr);
+      finish_sweep<4>(A.status, A.status_out, F, A.opts, b, A.sd, nsum[0], nsum[1], small_part ? tot + FR : nullptr);
   } else if (tid == 0) {
     if (A.sums_out) {
       A.sums_out[((long long)b * kMaxSd + A.sd) * 2] = nsum[0];

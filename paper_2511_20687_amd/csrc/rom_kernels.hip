@@ -43,7 +43,7 @@ hipError_t launch_rom(const RomArgs<T> &A, int batch, hipStream_t s, hipEvent_t 
   if constexpr (sizeof(T) == 8) {   // the batched parts are FP32 only
     if (v & kRomPre) return hipErrorInvalidValue;
     if (v == kRomNoPushRegs) hipExtLaunchKernelGGL((rom_kernel<T, kRomNoPushRegs>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
-    else if (v == kRomWidePush) hipExtLaunchKernelGGL((rom_kernel<T, kRomWidePush>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
+    else if (v == kRomWide) hipExtLaunchKernelGGL((rom_kernel<T, kRomWide>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
     else hipExtLaunchKernelGGL((rom_kernel<T, 0>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);
   } else {
     if (v == 5) hipExtLaunchKernelGGL((rom_kernel<T, 5>), grid, block, (uint32_t)smem, s, ev0, ev1, 0, A);

@@ -119,7 +119,7 @@ hipError_t launch_sweep(const SweepArgs<T> &S, int batch, bool one, size_t smem,
   bool ok;
   if constexpr (sizeof(T) == 8) {   // the batched parts are FP32 only
     if (v & kRomNoPushRegs) ok = launch_sweep_v<T, kRomNoPushRegs>(S, grid, fe, smem, s, ev0, ev1);
-    else if (v & kRomWidePush) ok = launch_sweep_v<T, kRomWidePush>(S, grid, fe, smem, s, ev0, ev1);
+    else if (v & kRomWide) ok = launch_sweep_v<T, kRomWide>(S, grid, fe, smem, s, ev0, ev1);
     else ok = launch_sweep_v<T, 0>(S, grid, fe, smem, s, ev0, ev1);
   } else {
     if (v == 5) ok = launch_sweep_v<T, 5>(S, grid, fe, smem, s, ev0, ev1);
