@@ -373,25 +373,21 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
   }
   __syncthreads();
 
-  // ---- 6. velocity, convergence sums, next predictor; workgroup 0 stores the state
+  // ---- 6. velocity, convergence sums, next predictor (workgroup 0 stores the state after the
+  // push: stores and loads share one completion counter, so stores issued here would hold the
+  // push's first use of its preloaded row until they complete)
   double nrm[2] = {0.0, 0.0};
+  T qn = T(0), vn = T(0), an = T(0);
   if (tid < r) {
-    const T qn = q1s[tid], an = qdd1s[tid] + x_c;
-    const T vn = x_qd0 + A.half_dt * (x_qdd0 + an);
+    qn = q1s[tid];
+    an = qdd1s[tid] + x_c;
+    vn = x_qd0 + A.half_dt * (x_qdd0 + an);
     qps[tid] = newmark_pred<T>(qn, vn, an, A.dt, A.half_dt2);
     if (g == 0) {
       const double d = ((double)qn - (double)x_old_q) + (double)A.dt * ((double)vn - (double)x_old_v);
       nrm[0] = d * d;
       const double e = (double)qn + (double)A.dt * (double)vn;
       nrm[1] = e * e;
-      A.q[1 - s2][qo + tid] = qn;
-      A.qd[1 - s2][qo + tid] = vn;
-      A.qdd[1 - s2][qo + tid] = an;
-      A.qpred[qo + tid] = qps[tid];   // the next step's q(t_k) if this iterate is accepted
-      if (A.rec_q && A.rec_every > 0 && ((step + 1) % A.rec_every) == 0) {
-        const long long col = (step + 1) / A.rec_every;
-        if (col < A.rec_ncols) A.rec_q[((long long)b * A.rec_ncols + col) * r + tid] = qn;
-      }
     }
   }
   block_reduce<2>(nrm, red, nsum);   // also publishes qps to every thread
@@ -404,10 +400,12 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
     const int m = g * kRomThreads + tid;
     T acc0 = T(0), acc1 = T(0);
     if (PUSHREG && e == 0) {
+      // branch-free: every LDS read in range (index clamped), modes >= r add a zero product,
+      // so the reads go out together instead of one round trip per mode
 #pragma unroll
       for (int k = 0; k < kPushK; k += 2) {
-        if (k < r) acc0 += pv[k] * qps[k];
-        if (k + 1 < r) acc1 += pv[k + 1] * qps[k + 1];
+        acc0 += (k < r ? pv[k] : T(0)) * qps[min(k, r - 1)];
+        acc1 += (k + 1 < r ? pv[k + 1] : T(0)) * qps[min(k + 1, r - 1)];
       }
     }
     const Vec16<T> *row = reinterpret_cast<const Vec16<T> *>(ex.prow + (long long)min(m, n - 1) * ex.r4);
@@ -427,6 +425,17 @@ __device__ __forceinline__ void rom_body(const RomArgs<T> &A, int g, State state
     if (m < n) {
       const int c = m / ex.npl, nid = m - c * ex.npl;
       ex.role[role][(long long)b * ex.is + c * ex.cs + nid] = acc0 + acc1;
+    }
+  }
+
+  if (g == 0 && tid < r) {   // the state of this iterate
+    A.q[1 - s2][qo + tid] = qn;
+    A.qd[1 - s2][qo + tid] = vn;
+    A.qdd[1 - s2][qo + tid] = an;
+    A.qpred[qo + tid] = qps[tid];   // the next step's q(t_k) if this iterate is accepted
+    if (A.rec_q && A.rec_every > 0 && ((step + 1) % A.rec_every) == 0) {
+      const long long col = (step + 1) / A.rec_every;
+      if (col < A.rec_ncols) A.rec_q[((long long)b * A.rec_ncols + col) * r + tid] = qn;
     }
   }
 
