@@ -17,6 +17,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # the fused sweep kernel reads its by-value argument struct through more than
+         # InstCombine's default 300 users: above that the struct is copied into scratch
+         # (3.6 KB per lane) instead of being read from the argument segment
+         "-mllvm", "-instcombine-max-copied-from-constant-users=1000",
          "-Wno-unused-command-line-argument", "-I" + os.path.join(HERE, "..", "include")]
 
 

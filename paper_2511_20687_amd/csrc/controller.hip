@@ -938,8 +938,9 @@ void Ctx::fuse_layout(Subdomain &s) {
   const int nl = s.nzs - 1;
   s.fz_kc = std::max(1, std::min(fuse_kc, nl));
   s.fz_chunks = (nl + s.fz_kc - 1) / s.fz_kc;
-  // (the fused sweep keeps the plain interior layout); 8 waves per workgroup; <= max_nblocks
-  s.fz_nblocks = (fe_waves_in(s, s.fz_chunks, fe_interior_waves(s, false), kFusedBndChunks) + 7) / 8;
+  // (x-shared interior rows with one layer per thread, else the plain layout); 8 waves per
+  // workgroup; <= max_nblocks
+  s.fz_nblocks = (fe_waves_in(s, s.fz_chunks, fe_interior_waves(s, s.fz_kc == 1 && s.fe_xs), kFusedBndChunks) + 7) / 8;
 }
 
 std::string Ctx::fusion_unsupported() const {
@@ -995,7 +996,7 @@ static int32_t fused_sweep(Ctx &c, const Opts &o, hipEvent_t ev0, hipEvent_t ev1
       A.kc = d.fz_kc;
       A.n_chunks = d.fz_chunks;
       A.bnd_l = kFusedBndChunks;
-      A.xs = 0;
+      A.xs = d.fz_kc == 1 && d.fe_xs ? 1 : 0;   // the layout fuse_layout counted
       A.nblocks = d.fz_nblocks;
       A.part_stride = d.fz_nblocks;
       A.part_off = 0;

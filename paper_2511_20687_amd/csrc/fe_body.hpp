@@ -385,8 +385,8 @@ __device__ __forceinline__ void store_partials(const FeArgs<T> &A, int b, int bx
 
 // PACKB: boundary waves may hold several layer chunks (A.bnd_l > 1, fused
 // sweeps); otherwise every wave has one layer chunk and one wave-uniform layer.
-// XSOK: the x-shared interior layout (A.xs) is compiled in (not in the fused
-// sweep kernel, where its shuffles push the register budget into spills).
+// XSOK: the x-shared interior layout (A.xs) is compiled in (fused sweeps: with one layer
+// per thread only).
 // st (optional): flags, step and iteration of the status this step starts from, when the
 // caller holds them (folded decisions of fused sweeps); else read from A.status[b].
 template <typename T, int MODE, bool ONE, bool PACKB = false, bool XSOK = true>

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kRomThreads) sweep_kernel(SweepArgs<T> S) {
       ss = folded();
       st = &ss;
     }
-    fe_body<T, kModeStep, FE == 1, true, false>(S.fe[S.fe_idx[i]], x, st);
+    fe_body<T, kModeStep, FE == 1, true, FE == 1>(S.fe[S.fe_idx[i]], x, st);   // x-shared rows with one layer
   }
 }
 
