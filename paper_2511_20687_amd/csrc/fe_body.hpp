@@ -145,14 +145,16 @@ __device__ __forceinline__ void state_loads(const Roles<T> &R, const Strides &B,
 // One layer's 3x3 neighbourhood: interior columns through wave-uniform row bases,
 // boundary columns (clamped indices) through per-lane addresses.
 // XS: interior rows shared across lanes (load_layer_xshare).
-// xf (boundary, wave-uniform): the columns are on an x-face (load_layer_xface, FP32).
+// xf (boundary, wave-uniform): the columns are on an x-face (load_layer_xface, FP32), else on
+// a y-face (load_layer_yface, FP32).
 template <typename T, bool INTERIOR, bool XS = false>
 __device__ __forceinline__ void layer(T (&w)[9][3], const T *P, const Strides &B, long long cs, int L, int npl,
                                       int nxp, int ix, int iy, int nx, int ny, int nid0, bool xf = false) {
   if (INTERIOR && XS) load_layer_xshare<T>(w, P, B, L, (unsigned)(nid0 - nxp) * (unsigned)sizeof(T));
   else if (INTERIOR) load_layer_uniform<T>(w, P, B, L, (unsigned)(nid0 - nxp - 1) * (unsigned)sizeof(T));
-  else if (sizeof(T) == 4 && xf) {
-    if constexpr (sizeof(T) == 4) load_layer_xface(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
+  else if constexpr (sizeof(T) == 4) {
+    if (xf) load_layer_xface(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
+    else load_layer_yface(w, P, cs, L, npl, nxp, ix, iy, ny);
   } else load_layer<T, false>(w, P, cs, L, npl, nxp, ix, iy, nx, ny);
 }
 

@@ -119,6 +119,38 @@ __device__ __forceinline__ void load_layer_xface(float (&w)[9][3], const float *
   }
 }
 
+// load_layer of a boundary column on a y-face (iy = 0 or ny, 1 <= ix < nx; FP32): the
+// two distinct rows (the face row and the row next to it; the clamped third is a copy of the
+// face row), each component as one 8-byte load of x - 1, x and one 4-byte load of x + 1:
+// 12 load instructions per layer instead of 27, the same values.
+__device__ __forceinline__ void load_layer_yface(float (&w)[9][3], const float *P, long long cs, int L, int npl,
+                                                 int nxp, int ix, int iy, int ny) {
+  const int jin = iy == 0 ? 1 : ny - 1;   // the row next to the face
+  float f[3][3], g[3][3];                  // [x - 1, x, x + 1][c] of the face row and of row jin
+  const float *pf = P + (long long)L * npl + (ix - 1 + nxp * iy);
+  const float *pg = P + (long long)L * npl + (ix - 1 + nxp * jin);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const unsigned long long a = *reinterpret_cast<const osam_u64_a4 *>(pf + c * cs);
+    const unsigned long long b = *reinterpret_cast<const osam_u64_a4 *>(pg + c * cs);
+    f[0][c] = __builtin_bit_cast(float, (unsigned)a);
+    f[1][c] = __builtin_bit_cast(float, (unsigned)(a >> 32));
+    f[2][c] = pf[c * cs + 2];
+    g[0][c] = __builtin_bit_cast(float, (unsigned)b);
+    g[1][c] = __builtin_bit_cast(float, (unsigned)(b >> 32));
+    g[2][c] = pg[c * cs + 2];
+  }
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // rows dy = -1, 0, +1: on the low face -1 clamps to the face, on the high face +1 does
+      w[dx][c] = iy == 0 ? f[dx][c] : g[dx][c];
+      w[3 + dx][c] = f[dx][c];
+      w[6 + dx][c] = iy == 0 ? g[dx][c] : f[dx][c];
+    }
+}
+
 // Raw buffer access to one instance's [3][cs] field (gfx9-family resource,
 // word 3 = 0x00020000): the resource and the byte offset soff are wave-uniform,
 // only the per-lane byte offset voff lives in a vector register, so the
